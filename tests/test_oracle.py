@@ -1,0 +1,351 @@
+"""Pins for the CPU oracle: closed forms, library routines, invariants and brute force.
+
+Each test would fail on a plausible mistake in the oracle (dropped term,
+wrong sign or index, transposed operand, off-by-one region).
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.distance import cdist
+
+from oracle import isax_ref as ir
+from oracle import knn_ref as kr
+from oracle import margin_ref as mr
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def walks(n, length, seed):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.standard_normal((n, length)), axis=1)
+    return ((t - t.mean(1, keepdims=True)) / t.std(1, keepdims=True)).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------- PAA
+def test_paa_ramp_closed_form():
+    X = np.arange(256, dtype=np.float32)[None, :]
+    want = 16 * np.arange(16) + 7.5
+    assert np.array_equal(ir.paa64(X, 16)[0], want)
+    assert np.array_equal(ir.paa32_tree(X, 16)[0], want.astype(np.float32))
+
+
+def test_paa_constant_and_linearity():
+    X = walks(50, 128, 1)
+    c = np.full((3, 128), 2.25, np.float32)
+    assert np.all(ir.paa64(c, 16) == 2.25) and np.all(ir.paa32_tree(c, 16) == 2.25)
+    a, b = 3.0, -1.5
+    lhs = ir.paa64(a * X.astype(np.float64) + b, 16)
+    assert np.allclose(lhs, a * ir.paa64(X, 16) + b, rtol=0, atol=1e-12)
+
+
+def test_paa_brute_force_tiny():
+    X = walks(4, 24, 2)
+    for w in (1, 2, 3, 4, 6, 8, 12, 24):
+        m = 24 // w
+        got = ir.paa64(X, w)
+        for i in range(4):
+            for j in range(w):
+                exact = math.fsum(float(v) for v in X[i, j * m:(j + 1) * m]) / m
+                assert abs(got[i, j] - exact) <= 4e-16 * max(1.0, abs(exact))
+
+
+def test_paa32_tree_order_and_error_bound():
+    # non-power-of-two segment: zero padding must not change an exact integer sum
+    X = np.arange(12, dtype=np.float32)[None, :]
+    assert np.array_equal(ir.paa32_tree(X, 4)[0], np.array([1, 4, 7, 10], np.float32))
+    # explicit tree for m = 4: ((x0 + x1) + (x2 + x3)) / 4 in FP32
+    Y = walks(200, 64, 3)
+    a = Y.reshape(200, 16, 4)
+    want = ((a[:, :, 0] + a[:, :, 1]) + (a[:, :, 2] + a[:, :, 3])) / np.float32(4)
+    assert np.array_equal(ir.paa32_tree(Y, 16), want)
+    # any-order FP32 mean of m terms is within m * 2^-23 * max|x| of the FP64 mean
+    Z = walks(500, 256, 4)
+    err = np.abs(ir.paa32_tree(Z, 16).astype(np.float64) - ir.paa64(Z, 16))
+    assert err.max() <= 16 * 2.0 ** -23 * np.abs(Z).max()
+
+
+# ----------------------------------------------------------------------------- breakpoints
+def _golden_quantiles():
+    out = {}
+    with open(os.path.join(GOLDEN, "normal_quantiles.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            c, *vals = line.split()
+            out[int(c)] = np.array([float(v) for v in vals])
+    return out
+
+
+def test_breakpoints_golden_table():
+    for c, vals in _golden_quantiles().items():
+        assert np.allclose(ir.breakpoints(c), vals, atol=5e-5)
+
+
+def test_breakpoints_against_erf_cdf():
+    # Phi(beta_j) = j / 2^c, with Phi from the stdlib error function
+    for c in range(1, 9):
+        beta = ir.breakpoints(c)
+        assert len(beta) == 2 ** c - 1
+        phi = np.array([0.5 * (1 + math.erf(b / math.sqrt(2))) for b in beta])
+        assert np.allclose(phi, np.arange(1, 2 ** c) / 2 ** c, rtol=0, atol=1e-13)
+        assert np.all(np.diff(beta) > 0)
+        assert np.allclose(beta, -beta[::-1], atol=1e-14)          # symmetry
+        assert beta[2 ** (c - 1) - 1] == 0.0                       # median edge is exactly 0
+
+
+def test_breakpoints_nest_across_cardinalities():
+    for c in range(2, 9):
+        fine = ir.breakpoints_f32(c)
+        for b in range(1, c):
+            coarse = ir.breakpoints_f32(b)
+            step = 2 ** (c - b)
+            assert np.array_equal(coarse, fine[step - 1::step])
+
+
+def test_c8_table_span():
+    beta = ir.breakpoints(8)
+    assert abs(beta[-1] - 2.6601) < 1e-4 and abs(beta[0] + 2.6601) < 1e-4
+    assert abs(np.diff(beta).min() - 0.00979) < 1e-5
+
+
+# ----------------------------------------------------------------------------- symbols
+def test_symbols_brute_force_and_half_open():
+    beta = ir.breakpoints_f32(3)
+    vals = np.concatenate([beta, np.nextafter(beta, -np.inf), np.nextafter(beta, np.inf),
+                           np.float32([-9, 9, 0])]).astype(np.float32)
+    got = ir.symbols(vals, beta)
+    for v, s in zip(vals, got):
+        assert s == sum(1 for b in beta if b <= v)
+    # a value exactly on beta_j belongs to region j (the region above)
+    assert np.array_equal(ir.symbols(beta, beta), np.arange(1, 8))
+
+
+def test_symbols_prefix_property_and_msb():
+    X = walks(300, 256, 5)
+    p = ir.paa32_tree(X, 16)
+    s8 = ir.symbols(p, ir.breakpoints_f32(8))
+    for b in range(1, 8):
+        assert np.array_equal(s8 >> (8 - b), ir.symbols(p, ir.breakpoints_f32(b)))
+    assert np.array_equal(s8 >> 7, (p >= 0).astype(np.uint8))
+
+
+def test_symbols_uniform_on_normal_samples():
+    rng = np.random.default_rng(6)
+    v = rng.standard_normal(256 * 400).astype(np.float32)
+    h = np.bincount(ir.symbols(v, ir.breakpoints_f32(8)), minlength=256)
+    exp = len(v) / 256
+    chi2 = ((h - exp) ** 2 / exp).sum()
+    assert chi2 < 255 + 6 * math.sqrt(2 * 255)
+
+
+def test_paper_word_example():
+    with open(os.path.join(GOLDEN, "isax_word_example.txt")) as f:
+        row = [l for l in f if not l.startswith("#")][0].split()
+    w, c = int(row[0]), int(row[1])
+    word = np.array([[int(s) for s in row[3].split(",")]], np.uint8)
+    assert ir.word_string(word[0], c) == row[2].replace("_", " ")
+    assert ir.root_subtree(word, c)[0] == int(row[4].replace(",", ""), 2)
+    bits = ir.interleaved_bits(word, c)[0]
+    assert "".join(str(int(b)) for b in bits) == row[5]
+    assert ir.key_prefix(word, c)[0] == np.uint64(int(row[5], 2) << (64 - w * c))
+
+
+def test_interleaved_key_brute_force():
+    rng = np.random.default_rng(7)
+    words = rng.integers(0, 256, size=(40, 16), dtype=np.uint8)
+    keys = ir.key_prefix(words, 8, 64)
+    for i in range(40):
+        s = "".join(format(int(words[i, j]), "08b")[r] for r in range(8) for j in range(16))
+        assert int(keys[i]) == int(s[:64], 2)
+        assert ir.root_subtree(words[i:i + 1], 8)[0] == int(s[:16], 2)
+
+
+def test_sorted_order_and_envelopes():
+    X = walks(3000, 256, 8)
+    words = ir.isax_words(X, 16, 8)
+    order = ir.sorted_order(words, 8, 64)
+    assert np.array_equal(np.sort(order), np.arange(3000))
+    keys = ir.key_prefix(words, 8, 64)[order]
+    assert np.all(keys[1:] >= keys[:-1])
+    ties = keys[1:] == keys[:-1]
+    assert np.all(order[1:][ties] > order[:-1][ties])
+    lo, hi = ir.leaf_envelopes(words[order], 256)
+    assert lo.shape == (12, 16)
+    for leaf in range(12):
+        blk = words[order[leaf * 256:(leaf + 1) * 256]]
+        assert np.all(blk >= lo[leaf]) and np.all(blk <= hi[leaf])
+        assert np.all(blk.min(0) == lo[leaf]) and np.all(blk.max(0) == hi[leaf])
+
+
+# ----------------------------------------------------------------------------- mindist
+def _ed2(q, X):
+    return ((X.astype(np.float64) - q.astype(np.float64)) ** 2).sum(axis=1)
+
+
+@pytest.mark.parametrize("kind", ["random", "noisy", "self"])
+def test_mindist_lower_bounds_distance(kind):
+    X = walks(2000, 256, 9)
+    rng = np.random.default_rng(10)
+    beta = ir.breakpoints(8)
+    words = ir.symbols(ir.paa64(X, 16), beta)
+    for t in range(10):
+        if kind == "random":
+            q = walks(1, 256, 100 + t)[0]
+        elif kind == "noisy":
+            q = X[rng.integers(2000)] + rng.normal(0, [0.01, 0.1, 1][t % 3], 256).astype(np.float32)
+        else:
+            q = X[t]
+        lb = ir.mindist_sq(ir.paa64(q[None], 16)[0], words, beta, 16)
+        assert np.all(lb <= _ed2(q, X) * (1 + 1e-12))
+        if kind == "self":
+            assert lb[t] == 0.0
+
+
+def test_mindist_tight_case_and_brute_force():
+    beta = ir.breakpoints(3)
+    m, w = 4, 3
+    p = np.array([-2.0, 0.1, 1.5])                   # query segment means
+    xs = np.array([beta[0], beta[3], beta[5]])       # series values exactly on region lower edges
+    s = ir.symbols(xs, beta)                         # regions 1, 4, 6
+    assert list(s) == [1, 4, 6]
+    q = np.repeat(p, m)[None, :]
+    x = np.repeat(xs, m)[None, :]
+    lb = ir.mindist_sq(p, s[None, :], beta, m)[0]
+    # segment 0: p below region 1 -> distance beta_1 - p = |x - p|; segment 1: p=0.1 is below
+    # region 4 = [0, 0.3186): p inside -> 0; segment 2: p=1.5 above region 6 = [0.6745, 1.1503)
+    ext = np.concatenate([[-np.inf], beta, [np.inf]])
+    want = m * ((ext[1] - p[0]) ** 2 + 0.0 + (p[2] - ext[7]) ** 2)
+    assert abs(lb - want) <= 1e-12
+    # where the query is on the far side of the region edge the bound is tight
+    assert abs(m * (ext[1] - p[0]) ** 2 - ((q[0, :4] - x[0, :4]) ** 2).sum()) <= 1e-12
+
+
+def test_mindist_monotone_in_cardinality_and_envelope():
+    X = walks(1500, 256, 11)
+    q = walks(1, 256, 12)[0]
+    pq = ir.paa64(q[None], 16)[0]
+    prev = None
+    for c in range(1, 9):
+        beta = ir.breakpoints(c)
+        lb = ir.mindist_sq(pq, ir.symbols(ir.paa64(X, 16), beta), beta, 16)
+        if prev is not None:
+            assert np.all(lb >= prev - 1e-12)
+        prev = lb
+    beta = ir.breakpoints(8)
+    words = ir.symbols(ir.paa64(X, 16), beta)
+    lo, hi = ir.leaf_envelopes(words, 100)
+    elb = ir.envelope_mindist_sq(pq, lo, hi, beta, 16)
+    for leaf in range(len(lo)):
+        assert np.all(elb[leaf] <= prev[leaf * 100:(leaf + 1) * 100] + 1e-12)
+
+
+def test_mindist_pure_python_tiny():
+    beta = ir.breakpoints(2)
+    ext = [-math.inf] + list(beta) + [math.inf]
+    rng = np.random.default_rng(13)
+    words = rng.integers(0, 4, size=(20, 4))
+    p = rng.normal(size=4)
+    got = ir.mindist_sq(p, words, beta, 8)
+    for i in range(20):
+        tot = 0.0
+        for j in range(4):
+            s = words[i, j]
+            d = max(0.0, ext[s] - p[j], p[j] - ext[s + 1])
+            tot += d * d
+        assert abs(got[i] - 8 * tot) <= 1e-12 * max(1, tot)
+
+
+# ----------------------------------------------------------------------------- k-NN
+def test_knn_pure_python_brute_force():
+    X = walks(60, 16, 14)
+    Q = walks(5, 16, 15)
+    ids, d2 = kr.knn_exact(X, Q, 7)
+    for j in range(5):
+        D = [math.fsum((float(Q[j, t]) - float(X[i, t])) ** 2 for t in range(16)) for i in range(60)]
+        want = sorted(range(60), key=lambda i: (D[i], i))[:7]
+        assert list(ids[j]) == want
+        assert np.allclose(d2[j], [D[i] for i in want], rtol=1e-14, atol=0)
+
+
+def test_knn_against_scipy_cdist():
+    X = walks(3000, 128, 16)
+    Q = walks(8, 128, 17)
+    ids, d2 = kr.knn_exact(X, Q, 10)
+    ref = cdist(Q.astype(np.float64), X.astype(np.float64), "sqeuclidean")
+    for j in range(8):
+        assert np.array_equal(ids[j], np.argsort(ref[j], kind="stable")[:10])
+        assert np.allclose(d2[j], ref[j][ids[j]], rtol=1e-13)
+
+
+def test_knn_duplicates_self_query_and_prefix():
+    X = walks(500, 64, 18)
+    X[300] = X[17]
+    X[401] = X[17]
+    ids, d2 = kr.knn_exact(X, X[[17, 300, 42]], 5)
+    assert list(ids[0][:3]) == [17, 300, 401] and list(ids[1][:3]) == [17, 300, 401]
+    assert np.all(d2[:2, :3] == 0.0)
+    assert ids[2][0] == 42 and d2[2][0] == 0.0
+    ids1, d21 = kr.knn_exact(X, X[[17, 300, 42]], 1)
+    assert np.array_equal(ids1[:, 0], ids[:, 0]) and np.array_equal(d21[:, 0], d2[:, 0])
+
+
+def test_knn_c_twin_bit_exact_and_chunked():
+    X = walks(4000, 256, 19)
+    Q = walks(6, 256, 20)
+    X[3999] = X[5]
+    Q[1] = X[5]
+    ids, d2 = kr.knn_exact(X, Q, 10)
+    ids_c, d2_c = kr.knn_exact_c(X, Q, 10)
+    assert np.array_equal(ids, ids_c) and np.array_equal(d2, d2_c)
+    st = kr.KnnState(Q, 10)
+    for a in range(0, 4000, 1500):
+        st.merge(X[a:a + 1500], a)
+    assert np.array_equal(st.ids, ids) and np.array_equal(st.d2, d2)
+    assert np.array_equal(kr.sq_dists_c(X, Q[0]), kr.sq_dists(X, Q[0]))
+
+
+# ----------------------------------------------------------------------------- quantisers / margin
+def test_bf16_round_matches_torch():
+    rng = np.random.default_rng(21)
+    x = (rng.standard_normal(100000) * rng.choice([1e-3, 1, 30], 100000)).astype(np.float32)
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(mr.bf16_round(x), want)
+
+
+def test_e4m3_round_matches_torch():
+    rng = np.random.default_rng(22)
+    X = walks(400, 256, 23) * np.float32(3)
+    xt, s = mr.quantise_rows(X, "fp8")
+    assert np.all(np.abs(X).max(1) / s <= 448) and np.all(np.abs(X).max(1) / (s / 2) > 448)
+    y = (X.astype(np.float64) / s[:, None]).astype(np.float32)
+    want = torch.from_numpy(y).to(torch.float8_e4m3fn).to(torch.float64).numpy() * s[:, None]
+    assert np.array_equal(xt, want)
+    v = (rng.standard_normal(50000) * 0.02).astype(np.float32)   # includes the subnormal range
+    want_v = torch.from_numpy(v).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(mr.e4m3_round(v.astype(np.float64)), want_v)
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp8"])
+def test_dot_error_bound_holds(kind):
+    X = walks(300, 256, 24)
+    Q = walks(20, 256, 25)
+    xt, _ = mr.quantise_rows(X, kind)
+    qt, _ = mr.quantise_rows(Q, kind)
+    err = np.abs(Q.astype(np.float64) @ X.astype(np.float64).T - qt @ xt.T)
+    bound = mr.dot_error_bound(Q, X, qt, xt)
+    assert np.all(err <= bound * (1 + 1e-12))
+    assert bound.mean() > 10 * err.mean() or kind == "bf16"
+
+
+def test_oracle_brute_force_itertools_tiny():
+    # every pair of rows, distances by itertools, matches the ordered answer at k = n
+    X = walks(9, 8, 26)
+    q = walks(1, 8, 27)
+    ids, d2 = kr.knn_exact(X, q, 9)
+    pairs = sorted((sum((float(a) - float(b)) ** 2 for a, b in zip(q[0], X[i])), i)
+                   for i in itertools.islice(range(9), 9))
+    assert [i for _, i in pairs] == list(ids[0])

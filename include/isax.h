@@ -1,0 +1,241 @@
+/*
+ * isax.h -- exact k-nearest-neighbour Euclidean search over an in-memory
+ * collection of data series with an iSAX index, on one AMD Instinct MI355X
+ * (gfx950).  C ABI: plain pointers and sizes, no C++ or PyTorch types.
+ *
+ * Paper: B. Peng, P. Fatourou, T. Palpanas, "Data Series Indexing Gone
+ * Parallel".  The method summarises every series with PAA and an iSAX word
+ * (Sec. II, iSAX Representation), groups the words into leaves of an index
+ * whose root subtrees are selected by the first bit of every segment (Sec. II,
+ * ADS+ Index; Sec. III, ParIS/ParIS+ approach), and answers an exact
+ * nearest-neighbour query (Sec. II, Similarity Search) by (1) an approximate
+ * answer that sets the best-so-far distance, (2) lower-bound distances
+ * between the query and the leaves / iSAX summaries, pruning those above the
+ * best-so-far, and (3) real distances for the survivors, updating the
+ * best-so-far (Sec. III, ParIS/ParIS+ and MESSI query answering).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers documented "device" are HIP device pointers on the current
+ *     device; "host" pointers are ordinary host memory.
+ *   - Series are FP32, row-major, `len` contiguous values per series.
+ *   - Distances are Euclidean (not squared); returned lists are ascending by
+ *     (distance, series id): ties go to the lower id.
+ *   - The library never normalises: it measures the values it is given.
+ *   - Every call validates its arguments before any device work and returns
+ *     ISAX_EINVAL (or NULL) on a bad argument, writing nothing to outputs.
+ *     The text of the last error of the calling thread is returned by
+ *     isax_last_error().  HIP failures give ISAX_EDEVICE with HIP's message.
+ *   - Calls run on the stream given in their options (NULL: the null stream)
+ *     and return after the results are in the output buffers.
+ */
+#ifndef ISAX_H
+#define ISAX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+enum {
+    ISAX_OK = 0,
+    ISAX_EINVAL = -1,    /* bad argument, or a non-finite value in data or queries */
+    ISAX_ENOMEM = -2,    /* device allocation failed */
+    ISAX_EDEVICE = -3,   /* a HIP call failed */
+    ISAX_EOVERFLOW = -4  /* more than 4096 candidates tie within the rounding window of the k-th distance */
+};
+
+/* Query execution modes (isax_query_options.mode). All return the same exact answer. */
+enum {
+    ISAX_MODE_INDEX = 0, /* iSAX path: home leaf, leaf and series lower bounds, refinement (Sec. III) */
+    ISAX_MODE_SCAN = 1,  /* plain FP32 scan of every series (the sequential-scan baseline, Sec. I) */
+    ISAX_MODE_BF16 = 2,  /* BF16 matrix-core dot-product filter with a proven error margin, FP32 refinement */
+    ISAX_MODE_FP8 = 3    /* FP8 E4M3 (power-of-two scale per series) filter, same margin rule */
+};
+
+/* Query flags (isax_query_options.flags): switches for testing; the answer never changes. */
+enum {
+    ISAX_QF_NO_SHARING = 1,       /* do not lower the best-so-far during the scan */
+    ISAX_QF_NO_EARLY_ABANDON = 2  /* refine every surviving series to the end */
+};
+
+#define ISAX_MAX_K 1024
+#define ISAX_MAX_LEN 4096
+#define ISAX_MAX_SEGMENTS 64
+
+typedef struct isax_index isax_index; /* opaque, owned by the library */
+
+typedef struct isax_build_options {
+    int32_t leaf_size; /* series per leaf (consecutive runs of the sorted order); 0 = 256; 16..4096 */
+    int32_t key_bits;  /* leading bits of the interleaved key that are sorted; 0 = min(64, w*c); 8..64, multiple of 8 */
+    int32_t precision; /* bit 0: also keep a BF16 copy, bit 1: also keep an FP8 E4M3 copy (needed by those modes) */
+    int32_t reserved;  /* must be 0 */
+    void* stream;      /* hipStream_t the build runs on; NULL = null stream */
+} isax_build_options;
+
+typedef struct isax_query_stats { /* per query, filled when requested */
+    int64_t leaves_scanned;  /* leaves whose lower bound was computed */
+    int64_t leaves_kept;     /* leaves that survived the leaf bound */
+    int64_t series_bounded;  /* series whose iSAX lower bound was computed */
+    int64_t series_refined;  /* series whose real distance was (partly) computed */
+    int64_t refine_bytes;    /* raw-data bytes read by refinement */
+    int64_t candidates;      /* entries appended to the candidate list */
+    float tau_initial;       /* squared best-so-far after the approximate answer */
+    float tau_final;         /* squared k-th distance found, FP32 */
+} isax_query_stats;
+
+typedef struct isax_query_options {
+    int32_t mode;               /* ISAX_MODE_* */
+    int32_t candidate_capacity; /* candidate slots per query; 0 = 4096; grows on overflow */
+    int32_t flags;              /* ISAX_QF_* */
+    int32_t batch;              /* queries per internal pass; 0 = 1024 */
+    const int32_t* k_per_query; /* device, m values in 1..k (row i keeps k_i results, the rest
+                                   of the row is filled with id -1 and +inf); NULL = k for all */
+    void* stream;               /* hipStream_t; NULL = null stream */
+    isax_query_stats* stats;    /* host, m entries, or NULL */
+} isax_query_options;
+
+/* Last error message of the calling thread ("" if none). Static storage, thread-local. */
+const char* isax_last_error(void);
+
+/*
+ * Build an index over `data` (device, n x len FP32).  `segments` (w) is the
+ * number of PAA segments and must divide len (segments of equal length, Sec.
+ * II); `card_bits` (c, 1..8) is the number of bits of every iSAX symbol.
+ * Regions are cut at the standard-normal quantiles Phi^-1(j / 2^c).
+ * The index BORROWS `data`: the caller keeps it allocated and unmodified until
+ * isax_free().  Returns NULL on error (see isax_last_error()); EINVAL if data
+ * holds a non-finite value.  n < 2^31, len <= ISAX_MAX_LEN,
+ * segments <= ISAX_MAX_SEGMENTS.
+ */
+isax_index* isax_build(const float* data, int64_t n, int32_t len, int32_t segments, int32_t card_bits);
+isax_index* isax_build_ex(const float* data, int64_t n, int32_t len, int32_t segments, int32_t card_bits,
+                          const isax_build_options* opt);
+
+/* Release an index and everything it owns (not the borrowed data). NULL is a no-op. */
+void isax_free(isax_index* idx);
+
+/*
+ * Exact k-NN of m queries (device, m x len FP32).  Writes out_ids (device,
+ * m x k int64) and out_dists (device, m x k FP32): for each query the k
+ * series of smallest Euclidean distance, ascending, ties by lower id (Sec. II,
+ * Similarity Search, generalised from 1 to k neighbours).  m = 0 succeeds with
+ * no work.  1 <= k <= min(n, ISAX_MAX_K).  EINVAL if a query value is not
+ * finite (outputs untouched).
+ */
+int isax_query(isax_index* idx, const float* queries, int64_t m, int32_t k, int64_t* out_ids, float* out_dists);
+int isax_query_ex(isax_index* idx, const float* queries, int64_t m, int32_t k, int64_t* out_ids, float* out_dists,
+                  const isax_query_options* opt);
+
+/* ---------------------------------------------------------- inspection */
+
+/* The 2^c - 1 region edges used for c-bit symbols, FP32, ascending (host out). */
+int isax_breakpoints(int32_t card_bits, float* out);
+
+/*
+ * iSAX words of n series without building an index (Sec. II, iSAX
+ * Representation): out_words (device, n x segments uint8) receives the
+ * symbol of every segment.  max_abs (host, may be NULL) receives max |x|.
+ */
+int isax_summarize(const float* data, int64_t n, int32_t len, int32_t segments, int32_t card_bits,
+                   uint8_t* out_words, float* max_abs, void* stream);
+
+typedef struct isax_index_info {
+    int64_t n;
+    int32_t len, segments, card_bits, leaf_size, key_bits;
+    int32_t has_bf16, has_fp8;
+    int64_t n_leaves;
+    float max_abs;       /* max |x| over the collection */
+    float delta;         /* bound on |FP32 PAA - exact PAA| of any series */
+    int64_t device_bytes;/* bytes the index owns on the device */
+} isax_index_info;
+
+int isax_index_get_info(const isax_index* idx, isax_index_info* out);
+
+/*
+ * Copy the index layout out (all device, any may be NULL): ids_sorted
+ * (n int32, series ids in leaf order), words_sorted (n x segments uint8),
+ * env_lo / env_hi (n_leaves x segments uint8, per-leaf per-segment min / max
+ * symbol).  Leaf i holds sorted positions [i*leaf_size, (i+1)*leaf_size).
+ */
+int isax_index_export(const isax_index* idx, int32_t* ids_sorted, uint8_t* words_sorted,
+                      uint8_t* env_lo, uint8_t* env_hi);
+
+/*
+ * Squared iSAX lower bounds used for pruning (Sec. III, lower-bound distance
+ * calculations): out_lb (device, m x n FP32, column = original series id)
+ * receives the bound of every (query, series) pair.  Each value is at most
+ * the squared Euclidean distance of the pair.
+ */
+int isax_lower_bounds(isax_index* idx, const float* queries, int64_t m, float* out_lb);
+
+/*
+ * Scores of the reduced-precision filter (mode ISAX_MODE_BF16 or _FP8), for
+ * testing its margin: out_approx (device, m x n) = |q|^2 + |x|^2 - 2 q~.x~
+ * accumulated on the matrix cores, out_margin (device, m x n) = the bound M
+ * with |ED^2 - approx| <= M.  m <= 1024.
+ */
+int isax_filter_scores(isax_index* idx, const float* queries, int64_t m, int32_t mode,
+                       float* out_approx, float* out_margin);
+
+/* ------------------------------------------------------- kernel timing */
+/* When enabled, every library kernel launch is bracketed by HIP events on its
+ * own stream; isax_profile_read() returns per-kernel totals (host out). */
+typedef struct isax_profile_entry {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+    double algorithmic_bytes; /* bytes the method must move in those launches (where defined) */
+} isax_profile_entry;
+
+int isax_profile_enable(int32_t on);
+int isax_profile_read(isax_profile_entry* out, int32_t max_entries, int32_t* n_entries);
+int isax_profile_reset(void);
+
+/* ------------------------------------------------------------- serving */
+/*
+ * A request loop over resident indexes.  submit() copies the host query and
+ * returns at once; a scheduler thread admits waiting requests into batches
+ * whenever a slot and the memory budget allow, runs every batch on its own
+ * stream so batches overlap on the device, and publishes each result.  Every
+ * result equals the result of the same query run alone (ids, and distances
+ * bit for bit).
+ */
+typedef struct isax_server isax_server;
+
+typedef struct isax_server_options {
+    int32_t max_batch;       /* requests per batch; 0 = 256 */
+    int32_t streams;         /* batches in flight; 0 = 4 */
+    int64_t memory_budget;   /* bytes of per-batch scratch allowed in flight; 0 = 4 GiB */
+    int32_t mode;            /* ISAX_MODE_* used for every batch */
+    int32_t reserved;
+} isax_server_options;
+
+typedef struct isax_result {
+    uint64_t tag;            /* the caller's tag from submit() */
+    int32_t status;          /* ISAX_OK or an error code */
+    int32_t k;
+    int32_t collection;
+    int32_t batch_size;      /* requests in the batch that served it */
+    double t_submit, t_start, t_done; /* seconds, steady clock */
+    int64_t ids[ISAX_MAX_K];
+    float dists[ISAX_MAX_K];
+} isax_result;
+
+isax_server* isax_server_create(isax_index* const* collections, int32_t n_collections,
+                                const isax_server_options* opt);
+/* query: host, len floats of that collection; 1 <= k <= min(n, ISAX_MAX_K). */
+int isax_server_submit(isax_server* s, int32_t collection, const float* query, int32_t k, uint64_t tag);
+/* Wait up to timeout_ms for results; returns how many were written to out (0..max). */
+int isax_server_poll(isax_server* s, isax_result* out, int32_t max_results, int32_t timeout_ms);
+/* Requests submitted and not yet returned by poll(). */
+int64_t isax_server_pending(isax_server* s);
+void isax_server_destroy(isax_server* s);
+/* Seconds on the steady clock the server stamps results with. */
+double isax_clock(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ISAX_H */

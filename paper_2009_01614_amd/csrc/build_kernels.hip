@@ -1,0 +1,541 @@
+// Index build kernels for gfx950: PAA + iSAX summarisation, interleaved keys,
+// LSD radix sort of (key, id), word gather, leaf envelopes, and the BF16 /
+// FP8 copies used by the dot-product filter.
+//
+// Paper: Sec. II (iSAX Representation: PAA segment means, bit-string symbols
+// per region; ADS+ Index: root subtrees by the first bit of every segment,
+// leaves refine one segment by one bit) and Sec. III (ParIS Stage 2 and MESSI
+// Stage 1 summarise every series; MESSI Stage 2 builds the root subtrees).
+// Here the tree is replaced by a flat layout: words sorted by their
+// bit-interleaved key and cut into fixed-size leaves, each with a per-segment
+// symbol envelope.
+#include "build_kernels.h"
+
+namespace isax {
+namespace {
+
+constexpr int kTile = 4096;            // radix-sort tile: 256 threads x 16 items
+constexpr int kSortThreads = 256;
+constexpr int kItemsPerWave = kTile / (kSortThreads / kWaveSize);  // 1024
+
+__device__ inline unsigned float_ord(float v) { return __float_as_uint(v); }  // v >= 0
+
+// Symbol = #{ j : beta_j <= p } by binary lifting over the 2^c - 1 sorted edges.
+__device__ inline int symbol_of(float p, const float* beta, int c) {
+    int s = 0;
+    for (int step = 1 << (c - 1); step > 0; step >>= 1)
+        if (beta[s + step - 1] <= p) s += step;
+    return s;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Summarise, fast path.  The collection is read as a flat stream of float4;
+// one wave consumes 64 float4 (1 KB) per "page" with one coalesced load.  A
+// segment of M points (M in 4..64, a power of two) spans M/4 consecutive lanes;
+// each lane adds its four values as (x0 + x1) + (x2 + x3) and the segment sum is
+// completed by a butterfly over those lanes, i.e. a balanced tree of adjacent
+// pairs.  The mean is sum * (1/M) (exact for a power of two).
+template <int M>
+__global__ void __launch_bounds__(256) k_summarise_fast(const float4* __restrict__ data, int64_t n_f4, int w,
+                                                        int out_stride, const float* __restrict__ beta_g, int c,
+                                                        uint8_t* __restrict__ words, unsigned* __restrict__ maxabs,
+                                                        int* __restrict__ nonfinite) {
+    constexpr int LPS = M / 4;  // lanes per segment
+    __shared__ float beta[256];
+    const int nb = (1 << c) - 1;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) beta[i] = beta_g[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    const int64_t pages = (n_f4 + 63) / 64;
+    float amax = 0.f;
+    bool bad = false;
+    constexpr int U = 4;
+    for (int64_t p0 = wave * U; p0 < pages; p0 += n_waves * U) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t g = (p0 + u) * 64 + lane;
+            v[u] = (p0 + u < pages && g < n_f4) ? data[g] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t g = (p0 + u) * 64 + lane;
+            const float4 x = v[u];
+            amax = fmaxf(amax, fmaxf(fmaxf(fabsf(x.x), fabsf(x.y)), fmaxf(fabsf(x.z), fabsf(x.w))));
+            bad |= !(fabsf(x.x) <= 3.4028235e38f) | !(fabsf(x.y) <= 3.4028235e38f) |
+                   !(fabsf(x.z) <= 3.4028235e38f) | !(fabsf(x.w) <= 3.4028235e38f);
+            float s = (x.x + x.y) + (x.z + x.w);
+#pragma unroll
+            for (int o = 1; o < LPS; o <<= 1) s += __shfl_xor(s, o, 64);
+            if (p0 + u < pages && g < n_f4 && (lane % LPS) == 0) {
+                const float paa = s * (1.0f / M);
+                const int64_t seg = g / LPS;
+                const int64_t i = seg / w;
+                const int j = (int)(seg - i * w);
+                words[i * out_stride + j] = (uint8_t)symbol_of(paa, beta, c);
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+    unsigned long long anybad = __ballot(bad);
+    if (lane == 0) {
+        atomicMax(maxabs, float_ord(amax));
+        if (anybad) atomicOr(nonfinite, 1);
+    }
+}
+
+// Summarise, generic path (any segment length): one thread per segment.  The
+// segment is zero-padded to the next power of two and summed as a balanced
+// tree of adjacent pairs (binary-counter order), the same tree as above.
+__global__ void k_summarise_generic(const float* __restrict__ data, int64_t n, int len, int w, int m,
+                                    int out_stride, const float* __restrict__ beta_g, int c,
+                                    uint8_t* __restrict__ words, unsigned* __restrict__ maxabs,
+                                    int* __restrict__ nonfinite) {
+    __shared__ float beta[256];
+    const int nb = (1 << c) - 1;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) beta[i] = beta_g[i];
+    __syncthreads();
+    int P = 1;
+    while (P < m) P <<= 1;
+    float amax = 0.f;
+    bool bad = false;
+    const int64_t nseg = n * w;
+    for (int64_t seg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; seg < nseg;
+         seg += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = seg / w;
+        const int j = (int)(seg - i * w);
+        const float* x = data + i * len + (int64_t)j * m;
+        float stack[14];
+        int level[14];
+        int top = 0;
+        for (int t = 0; t < P; ++t) {
+            float v = 0.f;
+            if (t < m) {
+                v = x[t];
+                amax = fmaxf(amax, fabsf(v));
+                bad |= !(fabsf(v) <= 3.4028235e38f);
+            }
+            stack[top] = v;
+            level[top] = 0;
+            ++top;
+            while (top >= 2 && level[top - 1] == level[top - 2]) {
+                stack[top - 2] = stack[top - 2] + stack[top - 1];
+                level[top - 2] += 1;
+                --top;
+            }
+        }
+        const float paa = stack[0] / (float)m;
+        words[i * out_stride + j] = (uint8_t)symbol_of(paa, beta, c);
+    }
+    for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+    unsigned long long anybad = __ballot(bad);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(maxabs, float_ord(amax));
+        if (anybad) atomicOr(nonfinite, 1);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Interleaved key: bit (63 - (r*w + j)) holds bit (c-1-r) of segment j; only
+// the first key_bits positions are kept.  The first w bits are the root subtree.
+__global__ void k_make_keys(const uint8_t* __restrict__ words, int64_t n, int ws, int w, int c, int key_bits,
+                            uint64_t* __restrict__ keys, int32_t* __restrict__ ids) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint8_t s[64];
+    const uint4* src = reinterpret_cast<const uint4*>(words + i * ws);
+    for (int q = 0; q < ws / 16; ++q) {
+        uint4 v = src[q];
+        unsigned u[4] = {v.x, v.y, v.z, v.w};
+        for (int b = 0; b < 16 && q * 16 + b < w; ++b) s[q * 16 + b] = (uint8_t)(u[b >> 2] >> (8 * (b & 3)));
+    }
+    uint64_t key = 0;
+    int pos = 0;
+    for (int r = 0; r < c && pos < key_bits; ++r)
+        for (int j = 0; j < w && pos < key_bits; ++j, ++pos)
+            key |= (uint64_t)((s[j] >> (c - 1 - r)) & 1) << (63 - pos);
+    keys[i] = key;
+    ids[i] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------------------------
+// LSD radix sort, 8-bit digits.  Pass: per-tile histograms (digit-major),
+// exclusive scan, stable scatter.  Within a tile, each wave owns a contiguous
+// run of 1024 items processed 64 at a time; lanes holding the same digit are
+// found with eight ballots, ranked by popcount, and a per-wave LDS counter per
+// digit carries the running count, so the scatter is stable.
+__global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                             int n_tiles, uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    for (int t = threadIdx.x; t < kTile; t += kSortThreads) {
+        const int64_t i = base + t;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of `len` uint32 in place: per-chunk scan, chunk totals in `sums`.
+constexpr int kScanChunk = 4096;
+__global__ void __launch_bounds__(256) k_scan_chunks(uint32_t* __restrict__ a, int64_t len, uint32_t* __restrict__ sums) {
+    __shared__ uint32_t part[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + threadIdx.x * 16;
+    uint32_t v[16];
+    uint32_t tot = 0;
+    for (int i = 0; i < 16; ++i) {
+        v[i] = (base + i < len) ? a[base + i] : 0u;
+        tot += v[i];
+    }
+    part[threadIdx.x] = tot;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        uint32_t add = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - tot;
+    for (int i = 0; i < 16; ++i) {
+        if (base + i < len) a[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 255) sums[blockIdx.x] = part[255];
+}
+
+__global__ void __launch_bounds__(1024) k_scan_sums(uint32_t* __restrict__ sums, int nchunks) {
+    __shared__ uint32_t part[1024];
+    const int per = (nchunks + 1023) / 1024;
+    const int base = threadIdx.x * per;
+    uint32_t tot = 0;
+    for (int i = 0; i < per; ++i)
+        if (base + i < nchunks) tot += sums[base + i];
+    part[threadIdx.x] = tot;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        uint32_t add = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - tot;
+    for (int i = 0; i < per; ++i)
+        if (base + i < nchunks) {
+            uint32_t v = sums[base + i];
+            sums[base + i] = run;
+            run += v;
+        }
+}
+
+__global__ void k_scan_add(uint32_t* __restrict__ a, int64_t len, const uint32_t* __restrict__ sums) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) a[i] += sums[i / kScanChunk];
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint64_t* __restrict__ kin,
+                                                                const int32_t* __restrict__ vin, int64_t n, int shift,
+                                                                int n_tiles, const uint32_t* __restrict__ offs,
+                                                                uint64_t* __restrict__ kout, int32_t* __restrict__ vout) {
+    constexpr int R = kItemsPerWave / 64;  // 16 rounds per wave
+    __shared__ uint32_t cnt[kSortThreads / 64][256];
+    __shared__ uint32_t base[256];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int wv = 0; wv < kSortThreads / 64; ++wv) cnt[wv][threadIdx.x] = 0;
+    base[threadIdx.x] = offs[(int64_t)threadIdx.x * n_tiles + blockIdx.x];
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t key[R];
+    int32_t val[R];
+    uint32_t rank[R];
+    int dig[R];
+    const int64_t start = (int64_t)blockIdx.x * kTile + (int64_t)wave * kItemsPerWave;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t i = start + r * 64 + lane;
+        const bool valid = i < n;
+        key[r] = valid ? kin[i] : 0ull;
+        val[r] = valid ? vin[i] : 0;
+        const int d = (int)((key[r] >> shift) & 255);
+        dig[r] = valid ? d : -1;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bm = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? bm : ~bm;
+        }
+        uint32_t prior = 0;
+        if (valid) prior = cnt[wave][d];
+        rank[r] = prior + (uint32_t)__popcll(peers & lt);
+        const int leader = valid ? (int)(__ffsll((long long)peers) - 1) : -1;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && leader == lane) cnt[wave][d] = prior + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        uint32_t s = 0;
+        for (int wv = 0; wv < kSortThreads / 64; ++wv) {
+            const uint32_t c0 = cnt[wv][threadIdx.x];
+            cnt[wv][threadIdx.x] = s;
+            s += c0;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (dig[r] >= 0) {
+            const uint32_t dst = base[dig[r]] + cnt[wave][dig[r]] + rank[r];
+            kout[dst] = key[r];
+            vout[dst] = val[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+__global__ void k_gather_words(const uint8_t* __restrict__ words, const int32_t* __restrict__ ids, int64_t n, int ws,
+                               uint8_t* __restrict__ out) {
+    const int q16 = ws / 16;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * q16) return;
+    const int64_t p = t / q16;
+    const int q = (int)(t - p * q16);
+    reinterpret_cast<uint4*>(out + p * ws)[q] = reinterpret_cast<const uint4*>(words + (int64_t)ids[p] * ws)[q];
+}
+
+__global__ void k_leaf_keys(const uint64_t* __restrict__ keys_sorted, int64_t n_leaves, int leaf,
+                            uint64_t* __restrict__ leaf_key) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l < n_leaves) leaf_key[l] = keys_sorted[l * leaf];
+}
+
+// One wave per leaf: per-segment min and max symbol of the leaf's words.
+__global__ void __launch_bounds__(256) k_envelopes(const uint8_t* __restrict__ ws_words, int64_t n, int ws, int leaf,
+                                                   int64_t n_leaves, uint8_t* __restrict__ lo,
+                                                   uint8_t* __restrict__ hi) {
+    const int lane = threadIdx.x & 63;
+    const int64_t l = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (l >= n_leaves) return;
+    const int64_t a = l * leaf;
+    const int64_t b = min(n, a + leaf);
+    for (int q = 0; q < ws / 16; ++q) {
+        int mn[16], mx[16];
+        for (int j = 0; j < 16; ++j) {
+            mn[j] = 255;
+            mx[j] = 0;
+        }
+        for (int64_t p = a + lane; p < b; p += 64) {
+            const uint4 v = reinterpret_cast<const uint4*>(ws_words + p * ws)[q];
+            const unsigned u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int s = (u[j >> 2] >> (8 * (j & 3))) & 255;
+                mn[j] = min(mn[j], s);
+                mx[j] = max(mx[j], s);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            for (int o = 32; o > 0; o >>= 1) {
+                mn[j] = min(mn[j], __shfl_xor(mn[j], o, 64));
+                mx[j] = max(mx[j], __shfl_xor(mx[j], o, 64));
+            }
+        if (lane < 16) {
+            int vmn = 0, vmx = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (j == lane) {
+                    vmn = mn[j];
+                    vmx = mx[j];
+                }
+            lo[l * ws + q * 16 + lane] = (uint8_t)vmn;
+            hi[l * ws + q * 16 + lane] = (uint8_t)vmx;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Reduced-precision copies.  BF16: round to nearest even.  FP8 E4M3 (OCP, max
+// 448): the row is divided by the smallest power of two s with max|x|/s <= 448
+// and rounded to nearest even; x~ = s * code value is exact in FP32, and so is
+// e_x = x - x~.  Per row: |x|^2 (FP32), |e_x| and |x~| rounded up.
+__device__ inline uint16_t bf16_rne(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_val(uint16_t b) { return __uint_as_float((unsigned)b << 16); }
+
+// E4M3 code of y, |y| <= 448, round to nearest even (exp bias 7, 3 mantissa bits,
+// subnormal quantum 2^-9).
+__device__ inline uint8_t e4m3_rne(float y) {
+    const unsigned sign = (__float_as_uint(y) >> 24) & 0x80u;
+    const float a = fabsf(y);
+    if (a == 0.f) return (uint8_t)sign;
+    int e = ((int)((__float_as_uint(a) >> 23) & 255)) - 127;  // floor(log2 a) for normal FP32
+    if (e < -6) {
+        const float q = rintf(a * 512.f);  // subnormal grid 2^-9; q == 8 is the smallest normal
+        return (uint8_t)(sign | (unsigned)q);
+    }
+    float q = rintf(ldexpf(a, 3 - e));  // in [8, 16]
+    if (q >= 16.f) {
+        q = 8.f;
+        ++e;
+    }
+    return (uint8_t)(sign | (unsigned)((e + 7) << 3) | ((unsigned)q - 8u));
+}
+__device__ inline float e4m3_val(uint8_t b) {
+    const int ex = (b >> 3) & 15, mn = b & 7;
+    const float v = ex == 0 ? ldexpf((float)mn, -9) : ldexpf((float)(8 + mn), ex - 10);
+    return (b & 0x80) ? -v : v;
+}
+
+// Round-up for norms: multiply by (1 + 2^-10), which exceeds the relative
+// rounding error of an FP32 sum of up to 4096 squares (4096 * 2^-24) plus the sqrt.
+__device__ inline float up_norm(float sumsq) { return sqrtf(sumsq * (1.0f + 0.0009765625f)) * (1.0f + 0.0009765625f); }
+
+// Rows are written in leaf order: row p of the copy is series ids_sorted[p].
+__global__ void __launch_bounds__(256) k_quantise(const float* __restrict__ data, const int32_t* __restrict__ ids,
+                                                  int64_t n, int len, int kind, uint16_t* __restrict__ xb,
+                                                  uint8_t* __restrict__ xf, float4* __restrict__ meta) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const float* x = data + (int64_t)ids[i] * len;
+    float amax = 0.f;
+    for (int t = lane; t < len; t += 64) amax = fmaxf(amax, fabsf(x[t]));
+    for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+    float scale = 1.f;
+    if (kind == 1 && amax > 0.f) {
+        // smallest power of two s with amax / s <= 448
+        int e;
+        const float f = frexpf(amax / 448.f, &e);  // amax/448 = f * 2^e, f in [0.5, 1)
+        scale = ldexpf(1.f, f == 0.5f ? e - 1 : e);
+        if (amax / scale > 448.f) scale *= 2.f;
+        if (amax / (scale * 0.5f) <= 448.f) scale *= 0.5f;
+    }
+    float xn = 0.f, en = 0.f, tn = 0.f;
+    for (int t = lane; t < len; t += 64) {
+        const float v = x[t];
+        float vt;
+        if (kind == 0) {
+            const uint16_t b = bf16_rne(v);
+            xb[i * len + t] = b;
+            vt = bf16_val(b);
+        } else {
+            const uint8_t b = e4m3_rne(v / scale);
+            xf[i * len + t] = b;
+            vt = e4m3_val(b) * scale;
+        }
+        const float e = v - vt;
+        xn = fmaf(v, v, xn);
+        en = fmaf(e, e, en);
+        tn = fmaf(vt, vt, tn);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        xn += __shfl_xor(xn, o, 64);
+        en += __shfl_xor(en, o, 64);
+        tn += __shfl_xor(tn, o, 64);
+    }
+    if (lane == 0) meta[i] = make_float4(xn, up_norm(en), up_norm(tn), scale);
+}
+
+}  // namespace
+
+// =============================================================================================
+// Host launchers
+void launch_summarise(const float* data, int64_t n, int len, int w, int out_stride, const float* beta, int c,
+                      uint8_t* words, unsigned* maxabs, int* nonfinite, hipStream_t s) {
+    const int m = len / w;
+    const bool fast = (len % 4 == 0) && (reinterpret_cast<uintptr_t>(data) & 15) == 0 &&
+                      (m == 4 || m == 8 || m == 16 || m == 32 || m == 64);
+    ProfScope ps("summarise", s);
+    if (fast) {
+        const int64_t n_f4 = n * (int64_t)len / 4;
+        const int64_t pages = (n_f4 + 63) / 64;
+        int64_t blocks = (pages + 15) / 16;  // 4 waves x 4 pages per block iteration
+        blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, 256 * 16));
+        const float4* d4 = reinterpret_cast<const float4*>(data);
+        switch (m) {
+            case 4: k_summarise_fast<4><<<blocks, 256, 0, s>>>(d4, n_f4, w, out_stride, beta, c, words, maxabs, nonfinite); break;
+            case 8: k_summarise_fast<8><<<blocks, 256, 0, s>>>(d4, n_f4, w, out_stride, beta, c, words, maxabs, nonfinite); break;
+            case 16: k_summarise_fast<16><<<blocks, 256, 0, s>>>(d4, n_f4, w, out_stride, beta, c, words, maxabs, nonfinite); break;
+            case 32: k_summarise_fast<32><<<blocks, 256, 0, s>>>(d4, n_f4, w, out_stride, beta, c, words, maxabs, nonfinite); break;
+            default: k_summarise_fast<64><<<blocks, 256, 0, s>>>(d4, n_f4, w, out_stride, beta, c, words, maxabs, nonfinite); break;
+        }
+    } else {
+        const int64_t nseg = n * w;
+        int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((nseg + 255) / 256, 256 * 32));
+        k_summarise_generic<<<blocks, 256, 0, s>>>(data, n, len, w, m, out_stride, beta, c, words, maxabs, nonfinite);
+    }
+    ISAX_HIP(hipGetLastError());
+}
+
+void sort_keys(uint64_t* keys, int32_t* ids, int64_t n, int key_bits, hipStream_t s) {
+    const int n_tiles = (int)((n + kTile - 1) / kTile);
+    const int64_t hlen = (int64_t)256 * n_tiles;
+    const int nchunks = (int)((hlen + kScanChunk - 1) / kScanChunk);
+    DevBuf k2(n * sizeof(uint64_t), s), v2(n * sizeof(int32_t), s);
+    DevBuf hist(hlen * sizeof(uint32_t), s), sums((size_t)nchunks * sizeof(uint32_t), s);
+    uint64_t *ka = keys, *kb = k2.as<uint64_t>();
+    int32_t *va = ids, *vb = v2.as<int32_t>();
+    int passes = 0;
+    for (int shift = 64 - key_bits; shift < 64; shift += 8, ++passes) {
+        {
+            ProfScope ps("radix_hist", s);
+            k_radix_hist<<<n_tiles, kSortThreads, 0, s>>>(ka, n, shift, n_tiles, hist.as<uint32_t>());
+        }
+        {
+            ProfScope ps("radix_scan", s);
+            k_scan_chunks<<<nchunks, 256, 0, s>>>(hist.as<uint32_t>(), hlen, sums.as<uint32_t>());
+            k_scan_sums<<<1, 1024, 0, s>>>(sums.as<uint32_t>(), nchunks);
+            k_scan_add<<<(int)((hlen + 255) / 256), 256, 0, s>>>(hist.as<uint32_t>(), hlen, sums.as<uint32_t>());
+        }
+        {
+            ProfScope ps("radix_scatter", s);
+            k_radix_scatter<<<n_tiles, kSortThreads, 0, s>>>(ka, va, n, shift, n_tiles, hist.as<uint32_t>(), kb, vb);
+        }
+        ISAX_HIP(hipGetLastError());
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    if (ka != keys) {
+        ISAX_HIP(hipMemcpyAsync(keys, ka, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+        ISAX_HIP(hipMemcpyAsync(ids, va, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+}
+
+void launch_make_keys(const uint8_t* words, int64_t n, int ws, int w, int c, int key_bits, uint64_t* keys, int32_t* ids,
+                      hipStream_t s) {
+    ProfScope ps("make_keys", s);
+    k_make_keys<<<(int)((n + 255) / 256), 256, 0, s>>>(words, n, ws, w, c, key_bits, keys, ids);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_gather_words(const uint8_t* words, const int32_t* ids, int64_t n, int ws, uint8_t* out, hipStream_t s) {
+    ProfScope ps("gather_words", s);
+    const int64_t t = n * (ws / 16);
+    k_gather_words<<<(int)((t + 255) / 256), 256, 0, s>>>(words, ids, n, ws, out);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_leaf_layout(const uint64_t* keys_sorted, const uint8_t* words_sorted, int64_t n, int ws, int leaf,
+                        int64_t n_leaves, uint64_t* leaf_key, uint8_t* lo, uint8_t* hi, hipStream_t s) {
+    ProfScope ps("envelopes", s);
+    k_leaf_keys<<<(int)((n_leaves + 255) / 256), 256, 0, s>>>(keys_sorted, n_leaves, leaf, leaf_key);
+    k_envelopes<<<(int)((n_leaves + 3) / 4), 256, 0, s>>>(words_sorted, n, ws, leaf, n_leaves, lo, hi);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_quantise(const float* data, const int32_t* ids, int64_t n, int len, int kind, uint16_t* xb, uint8_t* xf,
+                     float4* meta, hipStream_t s) {
+    ProfScope ps("quantise", s);
+    k_quantise<<<(int)((n + 3) / 4), 256, 0, s>>>(data, ids, n, len, kind, xb, xf, meta);
+    ISAX_HIP(hipGetLastError());
+}
+
+}  // namespace isax

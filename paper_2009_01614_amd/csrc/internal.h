@@ -1,0 +1,116 @@
+// Internal declarations shared by the library's translation units.
+// Not part of the public ABI (that is include/isax.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/isax.h"
+
+namespace isax {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+    int code;
+    std::string msg;
+};
+
+void set_error(int code, const std::string& msg);
+void clear_error();
+
+#define ISAX_HIP(call)                                                                       \
+    do {                                                                                     \
+        hipError_t _e = (call);                                                              \
+        if (_e != hipSuccess)                                                                \
+            throw ::isax::Error{ISAX_EDEVICE, std::string(#call) + ": " + hipGetErrorString(_e)}; \
+    } while (0)
+
+#define ISAX_REQUIRE(cond, text)                                     \
+    do {                                                             \
+        if (!(cond)) throw ::isax::Error{ISAX_EINVAL, (text)};       \
+    } while (0)
+
+// ------------------------------------------------------------------ constants
+constexpr int kWaveSize = 64;
+constexpr int kMaxCandLds = 4096;   // candidates one top-k block sorts in LDS
+constexpr int kMaxLeaf = 1024;
+
+inline int word_stride(int w) { return (w + 15) / 16 * 16; }
+
+// Relative slack that covers any-order FP32 rounding of a sum of len squares
+// (gamma_len <= len * 2^-24); comparisons against the best-so-far use
+// tau * (1 + eps).  Never below 2^-13.
+inline float tau_eps(int len) {
+    double e = 4.0 * len * std::ldexp(1.0, -24);
+    double p = std::ldexp(1.0, -13);
+    while (p < e) p *= 2;
+    return (float)p;
+}
+
+// Region edges Phi^-1(j / 2^c), j = 1..2^c-1, FP32 (breakpoints.cpp).
+std::vector<float> breakpoints_f32(int card_bits);
+
+// ------------------------------------------------------------------ profiling
+struct ProfScope {
+    ProfScope(const char* name, hipStream_t s);
+    ~ProfScope();
+    const char* name;
+    hipStream_t stream;
+    hipEvent_t a = nullptr, b = nullptr;
+};
+bool profiling_on();
+void profile_add_bytes(const char* name, double bytes);
+
+// ------------------------------------------------------------------ device scratch
+// Stream-ordered device allocation that is released when the object dies.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    DevBuf() = default;
+    DevBuf(size_t n, hipStream_t s);
+    ~DevBuf();
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+    DevBuf& operator=(DevBuf&& o) noexcept;
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Plain device allocation owned by an index (freed with hipFree).
+void* dev_alloc(size_t bytes);
+
+}  // namespace isax
+
+// ---------------------------------------------------------------------------------------------
+// The index.  All device arrays are owned except `data`, which the caller lends.
+struct isax_index {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    const float* data = nullptr;  // [n][len], borrowed
+    int64_t n = 0;
+    int32_t len = 0, w = 0, c = 0, m_seg = 0, ws = 0, ns = 0;  // ws: word stride bytes, ns = 2^c
+    int32_t leaf_size = 256, key_bits = 64;
+    int64_t n_leaves = 0;
+    float max_abs = 0.f;
+    float delta = 0.f;
+    float* beta = nullptr;          // [ns-1] region edges
+    uint8_t* words_sorted = nullptr;// [n][ws]
+    int32_t* ids_sorted = nullptr;  // [n]
+    uint8_t* env_lo = nullptr;      // [n_leaves][ws]
+    uint8_t* env_hi = nullptr;      // [n_leaves][ws]
+    uint64_t* leaf_key = nullptr;   // [n_leaves] first key of each leaf
+    // reduced-precision copies for the dot-product filter
+    uint16_t* x_bf16 = nullptr;     // [n][len] BF16 bits
+    float4* meta_bf16 = nullptr;    // [n] {|x|^2, |e_x| (up), |x~| (up), 1}
+    uint8_t* x_fp8 = nullptr;       // [n][len] E4M3 codes
+    float4* meta_fp8 = nullptr;     // [n] {|x|^2, |e_x| (up), |x~| (up), scale}
+    int64_t device_bytes = 0;
+    std::vector<void*> owned;
+    ~isax_index();
+};

@@ -1,0 +1,82 @@
+// Query-side kernels (query_kernels.hip, filter_kernels.hip) and their arguments.
+#pragma once
+#include "internal.h"
+
+namespace isax {
+
+// Per-query statistics slots (unsigned long long each).
+enum { ST_LEAVES = 0, ST_LEAVES_KEPT, ST_SERIES_LB, ST_REFINED, ST_REFINE_BYTES, ST_CANDS, ST_N };
+
+// Everything one batch of queries needs on the device.  Passed by value.
+struct QueryArgs {
+    // index (read only)
+    const float* data;
+    int64_t n;
+    int len, w, c, m_seg, ws, ns;
+    int leaf_size;
+    int64_t n_leaves;
+    const uint8_t* words_sorted;
+    const int32_t* ids_sorted;
+    const uint8_t* env_lo;
+    const uint8_t* env_hi;
+    const uint64_t* leaf_key;
+    const float* beta;
+    float delta_x;
+    // batch
+    int mq;           // queries in this batch
+    const float* Q;   // [mq][len]
+    const int32_t* kq;// [mq] k per query
+    int kmax;         // row stride of bestk and of the outputs
+    int cap;          // candidate slots per query
+    float tau_scale;  // 1 + eps: slack on every comparison with the best-so-far
+    float lb_scale;   // 1 - 2^-16: slack on every lower bound
+    int flags;        // ISAX_QF_*
+    int rerun;        // 1: frozen best-so-far, no best-k insertion, skip finished queries
+    float* paa;       // [mq][w]
+    uint8_t* sym;     // [mq][ws]
+    uint64_t* qkey;   // [mq]
+    float4* qinfo;    // [mq] {|q|^2, max|q|, delta, tau after the approximate answer}
+    float* edges;     // [mq][2][ns]  widened region edges: lower then upper
+    float* T;         // [mq][w][ns]  per-segment squared lower-bound table
+    float* tau0;      // [mq] extra upper bound on the k-th squared distance (+inf if none)
+    unsigned long long* bestk;  // [mq][kmax] k smallest (d2 bits << 32 | id) seen so far
+    unsigned long long* cand;   // [mq][cap]
+    unsigned* cand_count;       // [mq]
+    int64_t* home;              // [mq][2] leaf range of the approximate answer
+    unsigned long long* stats;  // [mq][ST_N]
+    int* done;                  // [mq] 1 once the query's answer is written
+    int* status;                // [mq] 0 ok, 1 candidate overflow (re-run), 2 window too large
+    int64_t* out_ids;           // [mq][kmax]
+    float* out_dists;           // [mq][kmax]
+};
+
+void launch_check_finite(const float* x, int64_t count, int* flag, hipStream_t s);
+void launch_qprep(const QueryArgs& a, hipStream_t s);
+void launch_homeleaf(const QueryArgs& a, hipStream_t s);
+void launch_index_scan(const QueryArgs& a, hipStream_t s);
+void launch_seed(const QueryArgs& a, hipStream_t s);
+void launch_brute_scan(const QueryArgs& a, hipStream_t s);
+void launch_topk(const QueryArgs& a, hipStream_t s);
+void launch_rerun_reset(const QueryArgs& a, hipStream_t s);
+void launch_lower_bounds(const QueryArgs& a, float* out, hipStream_t s);
+
+// Reduced-precision filter (filter_kernels.hip).
+struct FilterArgs {
+    int kind;                 // 0 BF16, 1 FP8
+    const void* xq;           // collection codes [n][len] (uint16 BF16 bits or uint8 E4M3)
+    const float4* xmeta;      // [n] {|x|^2, |e_x|, |x~|, scale}
+    void* qq;                 // query codes [mq_pad][len]
+    float4* qmeta;            // [mq_pad] {|q|^2, |e_q|, |q~|, scale}
+    float gamma;              // accumulation error factor
+    float kappa;              // relative slack on |q|^2 + |x|^2
+    unsigned* fcand;          // [mq][fcap] candidate ids from the filter
+    unsigned* fcount;         // [mq]
+    int fcap;
+    float* out_approx;        // optional [mq][n] (inspection)
+    float* out_margin;        // optional [mq][n]
+};
+void launch_quantise_queries(const QueryArgs& a, const FilterArgs& f, int mq_pad, hipStream_t s);
+void launch_filter(const QueryArgs& a, const FilterArgs& f, hipStream_t s);
+void launch_refine_filtered(const QueryArgs& a, const FilterArgs& f, hipStream_t s);
+
+}  // namespace isax

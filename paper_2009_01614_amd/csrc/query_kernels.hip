@@ -1,0 +1,843 @@
+// Query kernels for gfx950: query preparation, approximate answer, the fused
+// leaf-bound / series-bound / refinement scan, the plain FP32 scan, and the
+// final top-k with a compensated-arithmetic tie guard.
+//
+// Paper, Sec. III (ParIS/ParIS+ and MESSI query answering): an approximate
+// answer gives the best-so-far (BSF) distance; lower bounds between the query
+// and leaves / iSAX summaries prune everything above the BSF; survivors get
+// real distances, which may lower the BSF; the BSF at the end is the answer.
+// Here the BSF is generalised to the k-th smallest distance (k-NN), kept per
+// query in device memory as the k smallest (distance, id) keys, and every
+// comparison carries a rounding slack so that FP32 arithmetic never prunes a
+// true answer.
+#include "query_kernels.h"
+
+namespace isax {
+namespace {
+
+constexpr float kInf = __builtin_huge_valf();
+constexpr unsigned long long kEmpty = ~0ull;
+
+__device__ inline unsigned long long make_key(float d2, int32_t id) {
+    return ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)id;
+}
+__device__ inline float key_d2(unsigned long long k) {
+    return k == kEmpty ? kInf : __uint_as_float((unsigned)(k >> 32));
+}
+__device__ inline int32_t key_id(unsigned long long k) { return (int32_t)(unsigned)(k & 0xffffffffu); }
+
+__device__ inline unsigned long long load_relaxed(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Current upper bound on the k-th smallest squared distance of query q.
+__device__ inline float read_tau(const QueryArgs& a, int q, int k) {
+    const float t = key_d2(load_relaxed(a.bestk + (int64_t)q * a.kmax + (k - 1)));
+    return fminf(t, a.tau0[q]);
+}
+
+// Insert a key into the query's ascending list of the k smallest keys.  Every
+// slot only ever decreases (atomic min), the displaced key moves on to the
+// next slot, and the list stays sorted; slot k-1 therefore always bounds the
+// k-th smallest key inserted so far.  The start slot is found by binary search:
+// a slot observed <= v stays <= v.
+__device__ void bestk_insert(unsigned long long* bk, int k, unsigned long long v) {
+    int lo = 0, hi = k;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (load_relaxed(bk + mid) <= v) lo = mid + 1;
+        else hi = mid;
+    }
+    for (int i = lo; i < k && v != kEmpty; ++i) {
+        const unsigned long long old = atomicMin(bk + i, v);
+        if (old > v) v = old;
+    }
+}
+
+__device__ inline void emit(const QueryArgs& a, int q, int k, float d2, int32_t id) {
+    const unsigned long long key = make_key(d2, id);
+    const unsigned slot = atomicAdd(a.cand_count + q, 1u);
+    if (slot < (unsigned)a.cap) a.cand[(int64_t)q * a.cap + slot] = key;
+    if (!a.rerun && !(a.flags & ISAX_QF_NO_SHARING)) bestk_insert(a.bestk + (int64_t)q * a.kmax, k, key);
+}
+
+__device__ inline float sum16(float v) {
+    v += __shfl_xor(v, 1, 16);
+    v += __shfl_xor(v, 2, 16);
+    v += __shfl_xor(v, 4, 16);
+    v += __shfl_xor(v, 8, 16);
+    return v;
+}
+__device__ inline float sum64(float v) {
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Squared distance of the query (LDS) to one row, by a group of 16 lanes;
+// a step covers 64 consecutive points (16 lanes x 4).  With `abandon`, the
+// partial sum is compared with thr after every step but the last and the
+// row is dropped (returns +inf) once it exceeds thr.  `steps` = steps read.
+template <bool VEC>
+__device__ float refine16(const float* __restrict__ row, const float* qrow, int len, int gl, float thr, bool abandon,
+                          int& steps) {
+    const int S = (len + 63) >> 6;
+    float acc = 0.f;
+    for (int s = 0; s < S; ++s) {
+        const int t = s * 64 + gl * 4;
+        if (VEC) {
+            if (t < len) {
+                const float4 x = *reinterpret_cast<const float4*>(row + t);
+                const float4 qv = *reinterpret_cast<const float4*>(qrow + t);
+                const float d0 = qv.x - x.x, d1 = qv.y - x.y, d2 = qv.z - x.z, d3 = qv.w - x.w;
+                acc = fmaf(d0, d0, acc);
+                acc = fmaf(d1, d1, acc);
+                acc = fmaf(d2, d2, acc);
+                acc = fmaf(d3, d3, acc);
+            }
+        } else {
+            for (int e = 0; e < 4; ++e)
+                if (t + e < len) {
+                    const float d = qrow[t + e] - row[t + e];
+                    acc = fmaf(d, d, acc);
+                }
+        }
+        steps = s + 1;
+        if (abandon && s + 1 < S) {
+            const float part = sum16(acc);
+            if (part > thr) return kInf;
+        }
+    }
+    return sum16(acc);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Compensated squared distance (Ogita, Rump, Oishi, "Accurate sum and dot
+// product", SIAM J. Sci. Comput. 2005: TwoSum / TwoProduct, Dot2).  The
+// difference q - x is split exactly into dh + dl, dh^2 is split exactly with an
+// FMA, and the running sum keeps its error term; lanes combine (sum, error)
+// pairs by TwoSum in a butterfly, so every lane ends with the same pair.  The
+// result (hi, lo) is normalised: hi = fl(hi + lo).  Relative error about
+// len * 2^-48, far below the FP32 rounding of the sum.
+__device__ inline void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ float2 dist2_dot2(const float* __restrict__ q, const float* __restrict__ x, int len, int lane) {
+    float S = 0.f, C = 0.f;
+    for (int t = lane; t < len; t += 64) {
+        float dh, dl;
+        two_sum(q[t], -x[t], dh, dl);
+        const float p = dh * dh;
+        float pe = fmaf(dh, dh, -p);
+        pe = fmaf(2.f * dh, dl, pe);
+        pe = fmaf(dl, dl, pe);
+        float s, e;
+        two_sum(S, p, s, e);
+        S = s;
+        C = C + (e + pe);
+    }
+    for (int o = 1; o < 64; o <<= 1) {
+        const float S2 = __shfl_xor(S, o, 64), C2 = __shfl_xor(C, o, 64);
+        float s, e;
+        two_sum(S, S2, s, e);
+        S = s;
+        C = (C + C2) + e;
+    }
+    const float hi = S + C;
+    const float lo = C - (hi - S);
+    return make_float2(hi, lo);
+}
+
+// ---------------------------------------------------------------------------------------------
+__global__ void k_check_finite(const float* __restrict__ x, int64_t count, int* __restrict__ flag) {
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !(fabsf(x[i]) <= 3.4028235e38f);
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+// Query preparation, one 64-lane block per query: FP32 PAA in the same fixed
+// order as the collection's (zero-padded balanced tree of adjacent pairs), the
+// symbols and key, |q|^2 and max|q|, the widened region edges and the per-
+// segment table T[j][s] = m * dist(p_j, region s widened by delta)^2.
+// delta = delta_x + m 2^-23 max|q| bounds the FP32 PAA error of both sides;
+// edges are moved one further ulp outwards after widening.
+__global__ void __launch_bounds__(64) k_qprep(QueryArgs a) {
+    const int q = blockIdx.x;
+    const int lane = threadIdx.x;
+    const float* row = a.Q + (int64_t)q * a.len;
+    __shared__ float s_paa[64];
+    __shared__ int s_sym[64];
+    // |q|^2 and max|q|
+    float qn = 0.f, amax = 0.f;
+    for (int t = lane; t < a.len; t += 64) {
+        const float v = row[t];
+        qn = fmaf(v, v, qn);
+        amax = fmaxf(amax, fabsf(v));
+    }
+    qn = sum64(qn);
+    for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+    // PAA, one lane per segment
+    if (lane < a.w) {
+        const int m = a.m_seg;
+        int P = 1;
+        while (P < m) P <<= 1;
+        float stack[14];
+        int level[14];
+        int top = 0;
+        for (int t = 0; t < P; ++t) {
+            stack[top] = t < m ? row[lane * m + t] : 0.f;
+            level[top] = 0;
+            ++top;
+            while (top >= 2 && level[top - 1] == level[top - 2]) {
+                stack[top - 2] = stack[top - 2] + stack[top - 1];
+                level[top - 2] += 1;
+                --top;
+            }
+        }
+        const float p = stack[0] / (float)m;
+        int s = 0;
+        for (int step = 1 << (a.c - 1); step > 0; step >>= 1)
+            if (a.beta[s + step - 1] <= p) s += step;
+        s_paa[lane] = p;
+        s_sym[lane] = s;
+        a.paa[(int64_t)q * a.w + lane] = p;
+    }
+    __syncthreads();
+    if (lane < a.ws) a.sym[(int64_t)q * a.ws + lane] = lane < a.w ? (uint8_t)s_sym[lane] : 0;
+    if (lane == 0) {
+        unsigned long long key = 0;
+        int pos = 0;
+        for (int r = 0; r < a.c && pos < 64; ++r)
+            for (int j = 0; j < a.w && pos < 64; ++j, ++pos)
+                key |= (unsigned long long)((s_sym[j] >> (a.c - 1 - r)) & 1) << (63 - pos);
+        a.qkey[q] = key;
+    }
+    const float delta = (a.delta_x + (float)a.m_seg * 1.1920929e-07f * amax) * 1.0001f;
+    if (lane == 0) a.qinfo[q] = make_float4(qn, amax, delta, kInf);
+    float* lo_e = a.edges + (int64_t)q * 2 * a.ns;
+    float* hi_e = lo_e + a.ns;
+    for (int s = lane; s < a.ns; s += 64) {
+        lo_e[s] = s == 0 ? -kInf : nextafterf(a.beta[s - 1] - delta, -kInf);
+        hi_e[s] = s == a.ns - 1 ? kInf : nextafterf(a.beta[s] + delta, kInf);
+    }
+    __syncthreads();
+    const float mf = (float)a.m_seg;
+    float* T = a.T + (int64_t)q * a.w * a.ns;
+    for (int idx = lane; idx < a.w * a.ns; idx += 64) {
+        const int j = idx / a.ns, s = idx - j * a.ns;
+        const float p = s_paa[j];
+        const float lo = s == 0 ? -kInf : nextafterf(a.beta[s - 1] - delta, -kInf);
+        const float hi = s == a.ns - 1 ? kInf : nextafterf(a.beta[s] + delta, kInf);
+        const float d = fmaxf(0.f, fmaxf(lo - p, p - hi));
+        T[idx] = mf * (d * d);
+    }
+    // per-query search state
+    for (int i = lane; i < a.kmax; i += 64) a.bestk[(int64_t)q * a.kmax + i] = kEmpty;
+    if (lane < ST_N) a.stats[(int64_t)q * ST_N + lane] = 0ull;
+    if (lane == 0) {
+        a.cand_count[q] = 0u;
+        a.tau0[q] = kInf;
+        a.done[q] = 0;
+        a.status[q] = 0;
+        a.home[2 * q] = 0;
+        a.home[2 * q + 1] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Bitonic sort of n (power of two) 64-bit keys in LDS by the whole block.
+__device__ void bitonic_sort_u64(unsigned long long* v, int n) {
+    for (int size = 2; size <= n; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < n / 2; i += blockDim.x) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const unsigned long long x = v[lo], y = v[hi];
+                if ((x > y) == up) {
+                    v[lo] = y;
+                    v[hi] = x;
+                }
+            }
+        }
+    __syncthreads();
+}
+
+constexpr int kHomeMax = 4096;  // keys the approximate-answer block can sort (k + 2 leaves)
+
+// Approximate answer (MESSI: descend to the leaf of the query's iSAX summary
+// and take the real distances of its series).  The home leaf is the last leaf
+// whose first key is <= the query key; it is widened by neighbouring leaves
+// until it holds at least k series.  All its series are refined here, the k
+// smallest keys seed the best-so-far list, and those within the slack of the
+// k-th are appended to the candidate list.  The scan skips these leaves.
+__global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
+    extern __shared__ unsigned char smem_raw[];
+    unsigned long long* keys = reinterpret_cast<unsigned long long*>(smem_raw);
+    float* qrow = reinterpret_cast<float*>(keys + kHomeMax);
+    __shared__ int64_t s_range[2];
+    const int q = blockIdx.x;
+    if (a.rerun && a.done[q]) return;
+    const int k = a.kq[q];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        const unsigned long long key = a.qkey[q];
+        int64_t lo = 0, hi = a.n_leaves - 1;
+        while (lo < hi) {  // last leaf with leaf_key <= key (leaf 0 if none)
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (a.leaf_key[mid] <= key) lo = mid;
+            else hi = mid - 1;
+        }
+        int64_t l0 = lo, l1 = lo + 1;
+        auto count = [&](int64_t x0, int64_t x1) { return min(a.n, x1 * a.leaf_size) - x0 * a.leaf_size; };
+        while (count(l0, l1) < k) {
+            if (l1 < a.n_leaves) ++l1;
+            else --l0;
+        }
+        s_range[0] = l0;
+        s_range[1] = l1;
+    }
+    for (int t = threadIdx.x; t < a.len; t += blockDim.x) qrow[t] = a.Q[(int64_t)q * a.len + t];
+    __syncthreads();
+    const int64_t p0 = s_range[0] * a.leaf_size, p1 = min(a.n, s_range[1] * a.leaf_size);
+    const int cnt = (int)(p1 - p0);
+    int P = 1;
+    while (P < cnt) P <<= 1;
+    for (int i = cnt + threadIdx.x; i < P; i += blockDim.x) keys[i] = kEmpty;
+    for (int i = wave; i < cnt; i += blockDim.x / 64) {
+        const int32_t id = a.ids_sorted[p0 + i];
+        const float* row = a.data + (int64_t)id * a.len;
+        float acc = 0.f;
+        for (int t = lane; t < a.len; t += 64) {
+            const float d = qrow[t] - row[t];
+            acc = fmaf(d, d, acc);
+        }
+        acc = sum64(acc);
+        if (lane == 0) keys[i] = make_key(acc, id);
+    }
+    __syncthreads();
+    bitonic_sort_u64(keys, P);
+    const float thr = a.rerun ? read_tau(a, q, k) * a.tau_scale : key_d2(keys[k - 1]) * a.tau_scale;
+    if (!a.rerun)
+        for (int i = threadIdx.x; i < k; i += blockDim.x) a.bestk[(int64_t)q * a.kmax + i] = keys[i];
+    // entries <= thr form a prefix of the sorted keys
+    __shared__ int s_nc;
+    if (threadIdx.x == 0) s_nc = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+        if (key_d2(keys[i]) <= thr) {
+            atomicMax(&s_nc, i + 1);
+            if (i < a.cap) a.cand[(int64_t)q * a.cap + i] = keys[i];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a.cand_count[q] = (unsigned)s_nc;
+        a.home[2 * q] = s_range[0];
+        a.home[2 * q + 1] = s_range[1];
+        if (!a.rerun) {
+            float4 qi = a.qinfo[q];
+            qi.w = key_d2(keys[k - 1]);
+            a.qinfo[q] = qi;
+            unsigned long long* st = a.stats + (int64_t)q * ST_N;
+            st[ST_REFINED] += (unsigned long long)cnt;
+            st[ST_REFINE_BYTES] += (unsigned long long)cnt * a.len * 4ull;
+            st[ST_CANDS] += (unsigned long long)s_nc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// The iSAX scan, one block per (query, tile of 256 leaves).
+//  1. leaf lower bound from the widened region edges of the leaf's envelope
+//     (Sec. III, MESSI: prune subtrees / leaves whose bound exceeds the BSF);
+//  2. for every surviving leaf, one wave computes the lower bound of each
+//     series from its word with the per-segment LDS table (ParIS / MESSI
+//     lower-bound calculation on the iSAX summaries);
+//  3. each surviving series is refined by 16 lanes with early abandoning,
+//     and results within the slack of the current BSF are emitted (candidate
+//     list + best-so-far update).
+struct ScanSmem {
+    int off_lo, off_hi, off_paa, off_q, off_T, off_list, off_wl, total;
+};
+// The series-bound table sits in LDS when it is at most 32 KB, else it is read
+// from global memory (L2-resident: one table per query).
+constexpr int kTableLdsMax = 32 * 1024;
+__host__ __device__ inline ScanSmem scan_smem(int ns, int w, int len) {
+    ScanSmem s;
+    int o = 0;
+    s.off_lo = o; o += ns * 4;
+    s.off_hi = o; o += ns * 4;
+    s.off_paa = o; o += 64 * 4;
+    s.off_q = o; o += ((len + 3) / 4) * 16;
+    s.off_T = o; o += (w * ns * 4 <= kTableLdsMax) ? w * ns * 4 : 0;
+    s.off_list = o; o += 257 * 4;
+    o = (o + 15) / 16 * 16;
+    s.off_wl = o; o += 4 * 64 * 4;
+    s.total = o;
+    return s;
+}
+
+template <bool VEC, bool T_LDS>
+__global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
+    extern __shared__ unsigned char smem[];
+    const ScanSmem L = scan_smem(a.ns, a.w, a.len);
+    float* lo_e = reinterpret_cast<float*>(smem + L.off_lo);
+    float* hi_e = reinterpret_cast<float*>(smem + L.off_hi);
+    float* paa = reinterpret_cast<float*>(smem + L.off_paa);
+    float* qrow = reinterpret_cast<float*>(smem + L.off_q);
+    const float* T = T_LDS ? reinterpret_cast<const float*>(smem + L.off_T) : a.T + (int64_t)blockIdx.y * a.w * a.ns;
+    int* list = reinterpret_cast<int*>(smem + L.off_list);
+    int* wl = reinterpret_cast<int*>(smem + L.off_wl);
+    __shared__ int s_nk;
+    __shared__ unsigned long long s_st[ST_N];
+
+    const int q = blockIdx.y;
+    if (a.rerun && a.done[q]) return;
+    const int k = a.kq[q];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t leaf = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t h0 = a.home[2 * q], h1 = a.home[2 * q + 1];
+
+    for (int s = threadIdx.x; s < a.ns; s += 256) {
+        lo_e[s] = a.edges[(int64_t)q * 2 * a.ns + s];
+        hi_e[s] = a.edges[(int64_t)q * 2 * a.ns + a.ns + s];
+    }
+    if (threadIdx.x < a.w) paa[threadIdx.x] = a.paa[(int64_t)q * a.w + threadIdx.x];
+    if (threadIdx.x < ST_N) s_st[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) s_nk = 0;
+    __syncthreads();
+
+    float thr = read_tau(a, q, k) * a.tau_scale;
+    const bool valid_leaf = leaf < a.n_leaves && !(leaf >= h0 && leaf < h1);
+    bool keep = false;
+    if (valid_leaf) {
+        const uint8_t* el = a.env_lo + leaf * a.ws;
+        const uint8_t* eh = a.env_hi + leaf * a.ws;
+        float lb = 0.f;
+        for (int qc = 0; qc < a.ws / 16; ++qc) {
+            const uint4 vl = reinterpret_cast<const uint4*>(el)[qc];
+            const uint4 vh = reinterpret_cast<const uint4*>(eh)[qc];
+            const unsigned ul[4] = {vl.x, vl.y, vl.z, vl.w};
+            const unsigned uh[4] = {vh.x, vh.y, vh.z, vh.w};
+#pragma unroll
+            for (int b = 0; b < 16; ++b) {
+                const int j = qc * 16 + b;
+                if (j < a.w) {
+                    const int slo = (ul[b >> 2] >> (8 * (b & 3))) & 255;
+                    const int shi = (uh[b >> 2] >> (8 * (b & 3))) & 255;
+                    const float p = paa[j];
+                    const float d = fmaxf(0.f, fmaxf(lo_e[slo] - p, p - hi_e[shi]));
+                    lb = fmaf(d, d, lb);
+                }
+            }
+        }
+        lb *= (float)a.m_seg;
+        keep = lb * a.lb_scale <= thr;
+    }
+    {
+        const unsigned long long vm = __ballot(valid_leaf), km = __ballot(keep);
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s_nk, __popcll(km));
+        base = __shfl(base, 0, 64);
+        if (keep) list[base + __popcll(km & lt)] = (int)leaf;
+        if (lane == 0) {
+            atomicAdd(&s_st[ST_LEAVES], (unsigned long long)__popcll(vm));
+            atomicAdd(&s_st[ST_LEAVES_KEPT], (unsigned long long)__popcll(km));
+        }
+    }
+    __syncthreads();
+    const int nk = s_nk;
+    if (nk > 0) {
+        if (T_LDS) {
+            float* Tw = reinterpret_cast<float*>(smem + L.off_T);
+            for (int i = threadIdx.x; i < a.w * a.ns; i += 256) Tw[i] = a.T[(int64_t)q * a.w * a.ns + i];
+        }
+        for (int t = threadIdx.x; t < a.len; t += 256) qrow[t] = a.Q[(int64_t)q * a.len + t];
+        __syncthreads();
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        const bool abandon = !(a.flags & ISAX_QF_NO_EARLY_ABANDON);
+        unsigned long long n_lb = 0, n_ref = 0, n_bytes = 0, n_emit = 0;
+        int* my_wl = wl + wave * 64;
+        for (int li = wave; li < nk; li += 4) {
+            const int64_t lf = list[li];
+            const int64_t pa = lf * a.leaf_size, pb = min(a.n, pa + a.leaf_size);
+            thr = read_tau(a, q, k) * a.tau_scale;
+            for (int64_t base = pa; base < pb; base += 64) {
+                const int64_t pos = base + lane;
+                const bool v = pos < pb;
+                float lb = 0.f;
+                if (v) {
+                    const uint4* wp = reinterpret_cast<const uint4*>(a.words_sorted + pos * a.ws);
+                    for (int qc = 0; qc < a.ws / 16; ++qc) {
+                        const uint4 vw = wp[qc];
+                        const unsigned u[4] = {vw.x, vw.y, vw.z, vw.w};
+#pragma unroll
+                        for (int b = 0; b < 16; ++b) {
+                            const int j = qc * 16 + b;
+                            if (j < a.w) lb += T[j * a.ns + ((u[b >> 2] >> (8 * (b & 3))) & 255)];
+                        }
+                    }
+                }
+                const bool pass = v && lb * a.lb_scale <= thr;
+                const unsigned long long pm = __ballot(pass);
+                n_lb += (unsigned long long)__popcll(__ballot(v));
+                if (pm == 0ull) continue;
+                if (pass) my_wl[__popcll(pm & lt)] = (int)(pos - pa);
+                __builtin_amdgcn_wave_barrier();
+                const int nc = __popcll(pm);
+                const int g = lane >> 4, gl = lane & 15;
+                for (int ci = 0; ci < nc; ci += 4) {
+                    const int my = ci + g;
+                    if (my < nc) {
+                        const int64_t p2 = pa + my_wl[my];
+                        const int32_t id = a.ids_sorted[p2];
+                        const float* row = a.data + (int64_t)id * a.len;
+                        int steps = 0;
+                        const float d2 = refine16<VEC>(row, qrow, a.len, gl, thr, abandon, steps);
+                        if (gl == 0) {
+                            ++n_ref;
+                            n_bytes += (unsigned long long)min(a.len, steps * 64) * 4ull;
+                            if (d2 <= thr) {
+                                emit(a, q, k, d2, id);
+                                ++n_emit;
+                            }
+                        }
+                    }
+                    thr = read_tau(a, q, k) * a.tau_scale;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        atomicAdd(&s_st[ST_SERIES_LB], lane == 0 ? n_lb : 0ull);
+        if ((lane & 15) == 0) {
+            atomicAdd(&s_st[ST_REFINED], n_ref);
+            atomicAdd(&s_st[ST_REFINE_BYTES], n_bytes);
+            atomicAdd(&s_st[ST_CANDS], n_emit);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < ST_N && s_st[threadIdx.x])
+        atomicAdd(a.stats + (int64_t)q * ST_N + threadIdx.x, s_st[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Initial bound for the plain scan: the k-th smallest squared distance over
+// an evenly spaced sample of series (real distances, so a valid upper bound).
+constexpr int kSeedMax = 4096;
+__global__ void __launch_bounds__(256) k_seed(QueryArgs a) {
+    __shared__ unsigned long long keys[kSeedMax];
+    const int q = blockIdx.x;
+    const int k = a.kq[q];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int S = (int)min<int64_t>(a.n, (int64_t)min(kSeedMax, max(1024, 32 * k)));
+    int P = 1;
+    while (P < S) P <<= 1;
+    for (int i = S + threadIdx.x; i < P; i += 256) keys[i] = kEmpty;
+    const float* qrow = a.Q + (int64_t)q * a.len;
+    for (int i = wave; i < S; i += 4) {
+        const int64_t id = (int64_t)i * a.n / S;
+        const float* row = a.data + id * a.len;
+        float acc = 0.f;
+        for (int t = lane; t < a.len; t += 64) {
+            const float d = qrow[t] - row[t];
+            acc = fmaf(d, d, acc);
+        }
+        acc = sum64(acc);
+        if (lane == 0) keys[i] = make_key(acc, (int32_t)id);
+    }
+    __syncthreads();
+    bitonic_sort_u64(keys, P);
+    if (threadIdx.x == 0) {
+        a.tau0[q] = key_d2(keys[k - 1]);
+        float4 qi = a.qinfo[q];
+        qi.w = key_d2(keys[k - 1]);
+        a.qinfo[q] = qi;
+    }
+}
+
+// Plain FP32 scan: every (query, series) pair by direct differences.  Block =
+// 64 queries x 64 series, thread = 4 x 4 pairs, points staged through LDS in
+// chunks of 32; pairs within the slack of the query's bound are emitted.
+constexpr int kBT = 64, kBK = 32;
+__global__ void __launch_bounds__(256) k_brute_scan(QueryArgs a) {
+    __shared__ float Qs[kBK][kBT + 1];
+    __shared__ float Xs[kBK][kBT + 1];
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int64_t x0 = (int64_t)blockIdx.x * kBT;
+    const int q0 = blockIdx.y * kBT;
+    float acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+    for (int t0 = 0; t0 < a.len; t0 += kBK) {
+        for (int e = threadIdx.x; e < kBT * kBK; e += 256) {
+            const int r = e / kBK, t = e - r * kBK;
+            const int qi = q0 + r;
+            const int64_t xi = x0 + r;
+            Qs[t][r] = (qi < a.mq && t0 + t < a.len) ? a.Q[(int64_t)qi * a.len + t0 + t] : 0.f;
+            Xs[t][r] = (xi < a.n && t0 + t < a.len) ? a.data[xi * a.len + t0 + t] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int t = 0; t < kBK; ++t) {
+            float qv[4], xv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) qv[i] = Qs[t][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) xv[j] = Xs[t][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float d = qv[i] - xv[j];
+                    acc[i][j] = fmaf(d, d, acc[i][j]);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int qi = q0 + ty + 16 * i;
+        if (qi >= a.mq || (a.rerun && a.done[qi])) continue;
+        const int k = a.kq[qi];
+        const float thr = read_tau(a, qi, k) * a.tau_scale;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t xi = x0 + tx + 16 * j;
+            if (xi < a.n && acc[i][j] <= thr) emit(a, qi, k, acc[i][j], (int32_t)xi);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Final answer, one block per query.  The candidate list holds every series
+// whose FP32 squared distance came within the slack of the best-so-far at the
+// time, hence every true answer.  v_k = the k-th smallest FP32 value in the
+// list (radix select on its bits); the window = entries <= v_k * (1 + eps)
+// contains every true top-k series.  Window entries are recomputed with
+// compensated arithmetic and ordered by (value, id); the first k are written,
+// distance = sqrt(hi).  If the list overflowed, the k-th smallest stored value
+// tightens tau0 and the query is marked for a re-run with the bound frozen.
+constexpr int kWindowMax = 2048;
+
+// k-th smallest (1-based) of the high 32 bits of list[0..cnt), by 8-bit digits.
+__device__ unsigned radix_select_hi32(const unsigned long long* list, int cnt, int k, unsigned* hist) {
+    __shared__ unsigned s_prefix;
+    __shared__ int s_k;
+    if (threadIdx.x == 0) {
+        s_prefix = 0u;
+        s_k = k;
+    }
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        __syncthreads();
+        hist[threadIdx.x] = 0u;
+        __syncthreads();
+        const unsigned prefix = s_prefix;
+        for (int i = threadIdx.x; i < cnt; i += 256) {
+            const unsigned b = (unsigned)(list[i] >> 32);
+            const bool match = shift == 24 || (b >> (shift + 8)) == prefix;
+            if (match) atomicAdd(hist + ((b >> shift) & 255u), 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int kk = s_k;
+            unsigned d = 0;
+            for (; d < 255u; ++d) {
+                if ((int)hist[d] >= kk) break;
+                kk -= (int)hist[d];
+            }
+            s_k = kk;
+            s_prefix = (prefix << 8) | d;
+        }
+    }
+    __syncthreads();
+    return s_prefix;
+}
+
+__global__ void __launch_bounds__(256) k_topk(QueryArgs a) {
+    __shared__ unsigned long long wkeys[kWindowMax];
+    __shared__ float2 hl[kWindowMax];
+    __shared__ unsigned hist[256];
+    __shared__ int s_W;
+    const int q = blockIdx.x;
+    if (a.done[q]) return;
+    const int k = a.kq[q];
+    const unsigned cnt_all = a.cand_count[q];
+    const int cnt = (int)min<unsigned>(cnt_all, (unsigned)a.cap);
+    const unsigned long long* list = a.cand + (int64_t)q * a.cap;
+    if (cnt < k) {  // cannot happen for k <= n unless candidates were lost
+        if (threadIdx.x == 0) a.status[q] = cnt_all > (unsigned)a.cap ? 1 : 2;
+        return;
+    }
+    const float vk = __uint_as_float(radix_select_hi32(list, cnt, k, hist));
+    if (cnt_all > (unsigned)a.cap) {
+        if (threadIdx.x == 0) {
+            a.tau0[q] = fminf(a.tau0[q], vk);
+            a.status[q] = 1;
+        }
+        return;
+    }
+    const float thr = vk * a.tau_scale;
+    if (threadIdx.x == 0) s_W = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += 256) {
+        const unsigned long long key = list[i];
+        if (key_d2(key) <= thr) {
+            const int slot = atomicAdd(&s_W, 1);
+            if (slot < kWindowMax) wkeys[slot] = key;
+        }
+    }
+    __syncthreads();
+    const int W = s_W;
+    if (W > kWindowMax) {
+        if (threadIdx.x == 0) a.status[q] = 2;
+        return;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float* qrow = a.Q + (int64_t)q * a.len;
+    for (int i = wave; i < W; i += 4) {
+        const int32_t id = key_id(wkeys[i]);
+        const float2 r = dist2_dot2(qrow, a.data + (int64_t)id * a.len, a.len, lane);
+        if (lane == 0) hl[i] = r;
+    }
+    int PW = 1;
+    while (PW < W) PW <<= 1;
+    for (int i = W + threadIdx.x; i < PW; i += 256) {
+        wkeys[i] = kEmpty;
+        hl[i] = make_float2(kInf, kInf);
+    }
+    // bitonic sort of the window by (hi, lo, id)
+    for (int size = 2; size <= PW; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < PW / 2; i += 256) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const float2 x = hl[lo], y = hl[hi];
+                const unsigned ix = (unsigned)(wkeys[lo] & 0xffffffffu), iy = (unsigned)(wkeys[hi] & 0xffffffffu);
+                const bool gt = x.x > y.x || (x.x == y.x && (x.y > y.y || (x.y == y.y && ix > iy)));
+                if (gt == up) {
+                    hl[lo] = y;
+                    hl[hi] = x;
+                    const unsigned long long t = wkeys[lo];
+                    wkeys[lo] = wkeys[hi];
+                    wkeys[hi] = t;
+                }
+            }
+        }
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.kmax; i += 256) {
+        const int64_t o = (int64_t)q * a.kmax + i;
+        if (i < k) {
+            a.out_ids[o] = (int64_t)key_id(wkeys[i]);
+            a.out_dists[o] = sqrtf(fmaxf(hl[i].x, 0.f));
+        } else {
+            a.out_ids[o] = -1;
+            a.out_dists[o] = kInf;
+        }
+    }
+    if (threadIdx.x == 0) {
+        a.done[q] = 1;
+        a.status[q] = 0;
+        float4 qi = a.qinfo[q];
+        qi.y = vk;  // from here on: FP32 k-th squared distance
+        a.qinfo[q] = qi;
+    }
+}
+
+// Before a re-run: empty the candidate lists of the unfinished queries.
+__global__ void k_rerun_reset(QueryArgs a) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < a.mq && !a.done[q]) {
+        a.cand_count[q] = 0u;
+        a.status[q] = 0;
+    }
+}
+
+// Squared lower bound of every (query, series) pair, column = original id.
+__global__ void __launch_bounds__(256) k_lower_bounds(QueryArgs a, float* __restrict__ out) {
+    const int q = blockIdx.y;
+    const float* Ts = a.T + (int64_t)q * a.w * a.ns;
+    const int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (pos >= a.n) return;
+    const uint8_t* wd = a.words_sorted + pos * a.ws;
+    float lb = 0.f;
+    for (int j = 0; j < a.w; ++j) lb += Ts[j * a.ns + wd[j]];
+    out[(int64_t)q * a.n + a.ids_sorted[pos]] = lb * a.lb_scale;
+}
+
+}  // namespace
+
+// =============================================================================================
+void launch_check_finite(const float* x, int64_t count, int* flag, hipStream_t s) {
+    if (count <= 0) return;
+    ProfScope ps("check_finite", s);
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+    k_check_finite<<<(int)blocks, 256, 0, s>>>(x, count, flag);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_qprep(const QueryArgs& a, hipStream_t s) {
+    ProfScope ps("qprep", s);
+    k_qprep<<<a.mq, 64, 0, s>>>(a);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_homeleaf(const QueryArgs& a, hipStream_t s) {
+    ProfScope ps("homeleaf", s);
+    const size_t lds = kHomeMax * sizeof(unsigned long long) + (size_t)a.len * 4;
+    k_homeleaf<<<a.mq, 256, lds, s>>>(a);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_index_scan(const QueryArgs& a, hipStream_t s) {
+    ProfScope ps("index_scan", s);
+    const ScanSmem L = scan_smem(a.ns, a.w, a.len);
+    const dim3 grid((unsigned)((a.n_leaves + 255) / 256), (unsigned)a.mq);
+    const bool vec = a.len % 4 == 0 && (reinterpret_cast<uintptr_t>(a.data) & 15) == 0;
+    const bool tl = a.w * a.ns * 4 <= kTableLdsMax;
+    if (vec && tl) k_index_scan<true, true><<<grid, 256, L.total, s>>>(a);
+    else if (vec) k_index_scan<true, false><<<grid, 256, L.total, s>>>(a);
+    else if (tl) k_index_scan<false, true><<<grid, 256, L.total, s>>>(a);
+    else k_index_scan<false, false><<<grid, 256, L.total, s>>>(a);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_seed(const QueryArgs& a, hipStream_t s) {
+    ProfScope ps("seed", s);
+    k_seed<<<a.mq, 256, 0, s>>>(a);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_brute_scan(const QueryArgs& a, hipStream_t s) {
+    ProfScope ps("brute_scan", s);
+    const dim3 grid((unsigned)((a.n + kBT - 1) / kBT), (unsigned)((a.mq + kBT - 1) / kBT));
+    k_brute_scan<<<grid, 256, 0, s>>>(a);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_topk(const QueryArgs& a, hipStream_t s) {
+    ProfScope ps("topk", s);
+    k_topk<<<a.mq, 256, 0, s>>>(a);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_rerun_reset(const QueryArgs& a, hipStream_t s) {
+    k_rerun_reset<<<(a.mq + 255) / 256, 256, 0, s>>>(a);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_lower_bounds(const QueryArgs& a, float* out, hipStream_t s) {
+    const dim3 grid((unsigned)((a.n + 255) / 256), (unsigned)a.mq);
+    k_lower_bounds<<<grid, 256, 0, s>>>(a, out);
+    ISAX_HIP(hipGetLastError());
+}
+
+}  // namespace isax

@@ -1,0 +1,642 @@
+// C-ABI entry points: validation, error reporting, kernel timing, and the
+// host-side orchestration of index build and query answering.
+//
+// Build (Sec. II iSAX Representation / ADS+ Index; Sec. III ParIS Stage 2,
+// MESSI Stages 1-2): summarise every series, sort the words by their
+// interleaved key, cut the order into leaves with symbol envelopes.
+// Query (Sec. III, query answering): approximate answer -> best-so-far, leaf
+// and series lower bounds with pruning, refinement, final ordering.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+
+#include "build_kernels.h"
+#include "query_kernels.h"
+
+namespace isax {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err_msg;
+
+void set_error(int code, const std::string& msg) {
+    (void)code;
+    g_err_msg = msg;
+}
+void clear_error() { g_err_msg.clear(); }
+
+// ------------------------------------------------------------------ profiling
+namespace {
+struct ProfStat {
+    int64_t launches = 0;
+    double ms = 0.0;
+    double bytes = 0.0;
+};
+struct PendingPair {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::map<std::string, ProfStat> g_prof;
+std::vector<PendingPair> g_pending;
+
+void drain_pending_locked() {
+    for (auto& p : g_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            auto& st = g_prof[p.name];
+            st.launches += 1;
+            st.ms += ms;
+        }
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    g_pending.clear();
+}
+}  // namespace
+
+bool profiling_on() { return g_prof_on; }
+
+ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), stream(s) {
+    if (!g_prof_on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        a = b = nullptr;
+        return;
+    }
+    (void)hipEventRecord(a, stream);
+}
+ProfScope::~ProfScope() {
+    if (!a) return;
+    (void)hipEventRecord(b, stream);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_pending.push_back({name, a, b});
+    if (g_pending.size() > 4096) drain_pending_locked();
+}
+void profile_add_bytes(const char* name, double bytes) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof[name].bytes += bytes;
+}
+
+// ------------------------------------------------------------------ memory
+DevBuf::DevBuf(size_t n, hipStream_t s) : bytes(n), stream(s) {
+    if (n == 0) return;
+    const hipError_t e = hipMallocAsync(&p, n, s);
+    if (e != hipSuccess) {
+        p = nullptr;
+        throw Error{ISAX_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed: " + hipGetErrorString(e)};
+    }
+}
+DevBuf::~DevBuf() {
+    if (p) (void)hipFreeAsync(p, stream);
+}
+DevBuf& DevBuf::operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+        if (p) (void)hipFreeAsync(p, stream);
+        p = o.p;
+        bytes = o.bytes;
+        stream = o.stream;
+        o.p = nullptr;
+        o.bytes = 0;
+    }
+    return *this;
+}
+
+void* dev_alloc(size_t bytes) {
+    void* p = nullptr;
+    const hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 16));
+    if (e != hipSuccess)
+        throw Error{ISAX_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e)};
+    return p;
+}
+
+template <class T>
+static T* own(isax_index* idx, size_t count) {
+    T* p = static_cast<T*>(dev_alloc(count * sizeof(T)));
+    idx->owned.push_back(p);
+    idx->device_bytes += (int64_t)(count * sizeof(T));
+    return p;
+}
+
+// Carves aligned sub-arrays out of one stream-ordered allocation.
+struct Arena {
+    size_t off = 0;
+    std::vector<std::pair<void**, size_t>> reqs;
+    template <class T>
+    void add(T** p, size_t count) {
+        reqs.push_back({reinterpret_cast<void**>(p), off});
+        off += (count * sizeof(T) + 255) / 256 * 256;
+    }
+    DevBuf commit(hipStream_t s) {
+        DevBuf b(std::max<size_t>(off, 256), s);
+        for (auto& r : reqs) *r.first = static_cast<char*>(b.p) + r.second;
+        return b;
+    }
+};
+
+}  // namespace isax
+
+isax_index::~isax_index() {
+    for (void* p : owned) (void)hipFree(p);
+}
+
+using namespace isax;
+
+// =============================================================================================
+// Build
+namespace {
+
+int default_key_bits(int w, int c) {
+    int b = std::min(64, w * c);
+    return (b + 7) / 8 * 8 > 64 ? 64 : (b + 7) / 8 * 8;
+}
+
+void validate_series_shape(const float* data, int64_t n, int32_t len, int32_t w, int32_t c) {
+    ISAX_REQUIRE(data != nullptr, "data is NULL");
+    ISAX_REQUIRE(n >= 1, "n must be >= 1");
+    ISAX_REQUIRE(n < (int64_t(1) << 31), "n must be < 2^31");
+    ISAX_REQUIRE(len >= 1 && len <= ISAX_MAX_LEN, "len must be in 1..4096");
+    ISAX_REQUIRE(w >= 1 && w <= ISAX_MAX_SEGMENTS, "segments must be in 1..64");
+    ISAX_REQUIRE(len % w == 0, "segments must divide len (segments of equal length)");
+    ISAX_REQUIRE(c >= 1 && c <= 8, "card_bits must be in 1..8");
+    ISAX_REQUIRE((reinterpret_cast<uintptr_t>(data) & 3) == 0, "data must be 4-byte aligned");
+}
+
+float* upload_beta(int c, hipStream_t s, DevBuf* tmp, isax_index* idx) {
+    const std::vector<float> b = breakpoints_f32(c);
+    float* d = idx ? own<float>(idx, b.size()) : nullptr;
+    if (!idx) {
+        *tmp = DevBuf(b.size() * sizeof(float), s);
+        d = tmp->as<float>();
+    }
+    ISAX_HIP(hipMemcpyAsync(d, b.data(), b.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    return d;
+}
+
+isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int32_t c, const isax_build_options* opt) {
+    validate_series_shape(data, n, len, w, c);
+    isax_build_options o{};
+    if (opt) o = *opt;
+    const int leaf = o.leaf_size ? o.leaf_size : 256;
+    ISAX_REQUIRE(leaf >= 16 && leaf <= kMaxLeaf, "leaf_size must be in 16..1024");
+    const int key_bits = o.key_bits ? o.key_bits : default_key_bits(w, c);
+    ISAX_REQUIRE(key_bits >= 8 && key_bits <= 64 && key_bits % 8 == 0, "key_bits must be a multiple of 8 in 8..64");
+    ISAX_REQUIRE(o.precision >= 0 && o.precision <= 3, "precision must be a bitmask of 1 (BF16) and 2 (FP8)");
+    ISAX_REQUIRE(o.reserved == 0, "reserved must be 0");
+    hipStream_t s = static_cast<hipStream_t>(o.stream);
+
+    std::unique_ptr<isax_index> idx(new isax_index());
+    ISAX_HIP(hipGetDevice(&idx->device));
+    idx->stream = s;
+    idx->data = data;
+    idx->n = n;
+    idx->len = len;
+    idx->w = w;
+    idx->c = c;
+    idx->m_seg = len / w;
+    idx->ws = word_stride(w);
+    idx->ns = 1 << c;
+    idx->leaf_size = leaf;
+    idx->key_bits = key_bits;
+    idx->n_leaves = (n + leaf - 1) / leaf;
+    idx->beta = upload_beta(c, s, nullptr, idx.get());
+
+    const int ws = idx->ws;
+    DevBuf words(n * ws, s), flags(16, s);
+    ISAX_HIP(hipMemsetAsync(words.p, 0, n * ws, s));
+    ISAX_HIP(hipMemsetAsync(flags.p, 0, 16, s));
+    unsigned* d_max = flags.as<unsigned>();
+    int* d_bad = reinterpret_cast<int*>(d_max + 1);
+    launch_summarise(data, n, len, w, ws, idx->beta, c, words.as<uint8_t>(), d_max, d_bad, s);
+    unsigned hflags[2];
+    ISAX_HIP(hipMemcpyAsync(hflags, flags.p, 8, hipMemcpyDeviceToHost, s));
+    ISAX_HIP(hipStreamSynchronize(s));
+    ISAX_REQUIRE(hflags[1] == 0, "data holds a non-finite value");
+    std::memcpy(&idx->max_abs, &hflags[0], 4);
+    // |FP32 PAA - exact PAA| <= m 2^-24 max|x| for any summation order; use twice that.
+    idx->delta = (float)((double)idx->m_seg * std::ldexp(1.0, -23) * idx->max_abs * (1.0 + 1e-6));
+
+    DevBuf keys(n * sizeof(uint64_t), s);
+    idx->ids_sorted = own<int32_t>(idx.get(), n);
+    launch_make_keys(words.as<uint8_t>(), n, ws, w, c, key_bits, keys.as<uint64_t>(), idx->ids_sorted, s);
+    sort_keys(keys.as<uint64_t>(), idx->ids_sorted, n, key_bits, s);
+    idx->words_sorted = own<uint8_t>(idx.get(), (size_t)n * ws);
+    launch_gather_words(words.as<uint8_t>(), idx->ids_sorted, n, ws, idx->words_sorted, s);
+    idx->leaf_key = own<uint64_t>(idx.get(), idx->n_leaves);
+    idx->env_lo = own<uint8_t>(idx.get(), (size_t)idx->n_leaves * ws);
+    idx->env_hi = own<uint8_t>(idx.get(), (size_t)idx->n_leaves * ws);
+    launch_leaf_layout(keys.as<uint64_t>(), idx->words_sorted, n, ws, leaf, idx->n_leaves, idx->leaf_key, idx->env_lo,
+                       idx->env_hi, s);
+    if (o.precision & 1) {
+        idx->x_bf16 = own<uint16_t>(idx.get(), (size_t)n * len);
+        idx->meta_bf16 = own<float4>(idx.get(), n);
+        launch_quantise(data, idx->ids_sorted, n, len, 0, idx->x_bf16, nullptr, idx->meta_bf16, s);
+    }
+    if (o.precision & 2) {
+        idx->x_fp8 = own<uint8_t>(idx.get(), (size_t)n * len);
+        idx->meta_fp8 = own<float4>(idx.get(), n);
+        launch_quantise(data, idx->ids_sorted, n, len, 1, nullptr, idx->x_fp8, idx->meta_fp8, s);
+    }
+    words = DevBuf();
+    keys = DevBuf();
+    flags = DevBuf();
+    ISAX_HIP(hipStreamSynchronize(s));
+    ISAX_HIP(hipGetLastError());
+    return idx.release();
+}
+
+// =============================================================================================
+// Query
+struct Batch {
+    DevBuf mem;
+    QueryArgs a;
+};
+
+void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const int32_t* kq_dev, int kmax, int cap,
+                 int flags, int64_t* out_ids, float* out_dists, hipStream_t s) {
+    QueryArgs& a = b.a;
+    std::memset(&a, 0, sizeof(a));
+    a.data = idx->data;
+    a.n = idx->n;
+    a.len = idx->len;
+    a.w = idx->w;
+    a.c = idx->c;
+    a.m_seg = idx->m_seg;
+    a.ws = idx->ws;
+    a.ns = idx->ns;
+    a.leaf_size = idx->leaf_size;
+    a.n_leaves = idx->n_leaves;
+    a.words_sorted = idx->words_sorted;
+    a.ids_sorted = idx->ids_sorted;
+    a.env_lo = idx->env_lo;
+    a.env_hi = idx->env_hi;
+    a.leaf_key = idx->leaf_key;
+    a.beta = idx->beta;
+    a.delta_x = idx->delta;
+    a.mq = mq;
+    a.Q = Q;
+    a.kq = kq_dev;
+    a.kmax = kmax;
+    a.cap = cap;
+    a.tau_scale = 1.0f + tau_eps(idx->len);
+    a.lb_scale = 1.0f - 1.52587890625e-05f;
+    a.flags = flags;
+    a.rerun = 0;
+    a.out_ids = out_ids;
+    a.out_dists = out_dists;
+    Arena ar;
+    ar.add(&a.paa, (size_t)mq * idx->w);
+    ar.add(&a.sym, (size_t)mq * idx->ws);
+    ar.add(&a.qkey, mq);
+    ar.add(&a.qinfo, mq);
+    ar.add(&a.edges, (size_t)mq * 2 * idx->ns);
+    ar.add(&a.T, (size_t)mq * idx->w * idx->ns);
+    ar.add(&a.tau0, mq);
+    ar.add(&a.bestk, (size_t)mq * kmax);
+    ar.add(&a.cand, (size_t)mq * cap);
+    ar.add(&a.cand_count, mq);
+    ar.add(&a.home, (size_t)mq * 2);
+    ar.add(&a.stats, (size_t)mq * ST_N);
+    ar.add(&a.done, mq);
+    ar.add(&a.status, mq);
+    b.mem = ar.commit(s);
+}
+
+void fill_stats(const Batch& b, isax_query_stats* out, hipStream_t s) {
+    const int mq = b.a.mq;
+    std::vector<unsigned long long> st((size_t)mq * ST_N);
+    std::vector<float4> qi(mq);
+    ISAX_HIP(hipMemcpyAsync(st.data(), b.a.stats, st.size() * 8, hipMemcpyDeviceToHost, s));
+    ISAX_HIP(hipMemcpyAsync(qi.data(), b.a.qinfo, qi.size() * sizeof(float4), hipMemcpyDeviceToHost, s));
+    ISAX_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < mq; ++i) {
+        const unsigned long long* r = &st[(size_t)i * ST_N];
+        out[i].leaves_scanned = (int64_t)r[ST_LEAVES];
+        out[i].leaves_kept = (int64_t)r[ST_LEAVES_KEPT];
+        out[i].series_bounded = (int64_t)r[ST_SERIES_LB];
+        out[i].series_refined = (int64_t)r[ST_REFINED];
+        out[i].refine_bytes = (int64_t)r[ST_REFINE_BYTES];
+        out[i].candidates = (int64_t)r[ST_CANDS];
+        out[i].tau_initial = qi[i].w;
+        out[i].tau_final = qi[i].y;
+    }
+}
+
+// Algorithmic bytes of the iSAX scan for one batch: 2 * word stride per leaf
+// bounded (envelope), word stride per series bounded, refinement bytes read.
+double scan_bytes(const Batch& b, const isax_index* idx, hipStream_t s) {
+    const int mq = b.a.mq;
+    std::vector<unsigned long long> st((size_t)mq * ST_N);
+    ISAX_HIP(hipMemcpyAsync(st.data(), b.a.stats, st.size() * 8, hipMemcpyDeviceToHost, s));
+    ISAX_HIP(hipStreamSynchronize(s));
+    double tot = 0;
+    for (int i = 0; i < mq; ++i) {
+        const unsigned long long* r = &st[(size_t)i * ST_N];
+        tot += 2.0 * idx->ws * r[ST_LEAVES] + (double)idx->ws * r[ST_SERIES_LB] + (double)r[ST_REFINE_BYTES];
+    }
+    return tot;
+}
+
+void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s);  // filter section below
+
+void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
+    QueryArgs& a = b.a;
+    launch_qprep(a, s);
+    if (mode == ISAX_MODE_INDEX) {
+        launch_homeleaf(a, s);
+        launch_index_scan(a, s);
+        if (profiling_on()) profile_add_bytes("index_scan", scan_bytes(b, idx, s));
+    } else if (mode == ISAX_MODE_SCAN) {
+        launch_seed(a, s);
+        launch_brute_scan(a, s);
+        if (profiling_on()) profile_add_bytes("brute_scan", (double)a.n * a.len * 4.0 * ((a.mq + 63) / 64));
+    } else {
+        run_filter_batch(idx, b, mode, s);
+    }
+    launch_topk(a, s);
+    std::vector<int> status(a.mq);
+    for (int round = 0;; ++round) {
+        ISAX_HIP(hipMemcpyAsync(status.data(), a.status, a.mq * sizeof(int), hipMemcpyDeviceToHost, s));
+        ISAX_HIP(hipStreamSynchronize(s));
+        bool rerun = false;
+        for (int v : status) {
+            if (v == 2)
+                throw Error{ISAX_EOVERFLOW,
+                            "more than 2048 series lie within the rounding window of the k-th distance"};
+            rerun |= v == 1;
+        }
+        if (!rerun) break;
+        if (round >= 8) throw Error{ISAX_EOVERFLOW, "candidate list overflowed on 8 re-runs"};
+        a.rerun = 1;
+        launch_rerun_reset(a, s);
+        if (mode == ISAX_MODE_INDEX) {
+            launch_homeleaf(a, s);
+            launch_index_scan(a, s);
+        } else if (mode == ISAX_MODE_SCAN) {
+            launch_brute_scan(a, s);
+        } else {
+            run_filter_batch(idx, b, mode, s);
+        }
+        launch_topk(a, s);
+    }
+}
+
+int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* out_ids, float* out_dists,
+               const isax_query_options* opt) {
+    ISAX_REQUIRE(idx != nullptr, "index is NULL");
+    ISAX_REQUIRE(m >= 0, "m must be >= 0");
+    ISAX_REQUIRE(k >= 1 && k <= ISAX_MAX_K && k <= idx->n, "k must be in 1..min(n, 1024)");
+    isax_query_options o{};
+    if (opt) o = *opt;
+    ISAX_REQUIRE(o.mode >= ISAX_MODE_INDEX && o.mode <= ISAX_MODE_FP8, "unknown mode");
+    ISAX_REQUIRE(o.candidate_capacity >= 0 && o.batch >= 0, "candidate_capacity and batch must be >= 0");
+    ISAX_REQUIRE((o.flags & ~(ISAX_QF_NO_SHARING | ISAX_QF_NO_EARLY_ABANDON)) == 0, "unknown flag");
+    ISAX_REQUIRE(o.mode != ISAX_MODE_BF16 || idx->x_bf16, "index was built without the BF16 copy");
+    ISAX_REQUIRE(o.mode != ISAX_MODE_FP8 || idx->x_fp8, "index was built without the FP8 copy");
+    if (m == 0) return ISAX_OK;
+    ISAX_REQUIRE(Q && out_ids && out_dists, "queries and outputs must not be NULL");
+    ISAX_REQUIRE((reinterpret_cast<uintptr_t>(Q) & 3) == 0, "queries must be 4-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(o.stream);
+    int cur = 0;
+    ISAX_HIP(hipGetDevice(&cur));
+    ISAX_REQUIRE(cur == idx->device, "current device differs from the index's device");
+
+    // validation of values before any output is written
+    {
+        DevBuf flag(4, s);
+        ISAX_HIP(hipMemsetAsync(flag.p, 0, 4, s));
+        launch_check_finite(Q, m * idx->len, flag.as<int>(), s);
+        int bad = 0;
+        ISAX_HIP(hipMemcpyAsync(&bad, flag.p, 4, hipMemcpyDeviceToHost, s));
+        ISAX_HIP(hipStreamSynchronize(s));
+        ISAX_REQUIRE(bad == 0, "queries hold a non-finite value");
+    }
+    DevBuf kdev;
+    const int32_t* kq = o.k_per_query;
+    if (kq) {
+        std::vector<int32_t> hk(m);
+        ISAX_HIP(hipMemcpyAsync(hk.data(), kq, m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        ISAX_HIP(hipStreamSynchronize(s));
+        for (int32_t v : hk) ISAX_REQUIRE(v >= 1 && v <= k, "k_per_query values must be in 1..k");
+    } else {
+        std::vector<int32_t> hk(m, k);
+        kdev = DevBuf(m * sizeof(int32_t), s);
+        ISAX_HIP(hipMemcpyAsync(kdev.p, hk.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        ISAX_HIP(hipStreamSynchronize(s));
+        kq = kdev.as<int32_t>();
+    }
+    const int B = o.batch ? o.batch : 1024;
+    const int cap = o.candidate_capacity ? std::max(o.candidate_capacity, k) : 16384;
+    for (int64_t q0 = 0; q0 < m; q0 += B) {
+        const int mq = (int)std::min<int64_t>(B, m - q0);
+        Batch b;
+        setup_batch(b, idx, Q + q0 * idx->len, mq, kq + q0, k, cap, o.flags, out_ids + q0 * k, out_dists + q0 * k, s);
+        run_batch(idx, b, o.mode, s);
+        if (o.stats) fill_stats(b, o.stats + q0, s);
+    }
+    ISAX_HIP(hipStreamSynchronize(s));
+    return ISAX_OK;
+}
+
+template <class F>
+int guarded(F&& f) {
+    clear_error();
+    try {
+        return f();
+    } catch (const Error& e) {
+        set_error(e.code, e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error(ISAX_ENOMEM, "host allocation failed");
+        return ISAX_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(ISAX_EDEVICE, e.what());
+        return ISAX_EDEVICE;
+    }
+}
+
+}  // namespace
+
+// =============================================================================================
+// Reduced-precision filter batch (kernels in filter_kernels.hip)
+namespace {
+void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
+    QueryArgs& a = b.a;
+    FilterArgs f{};
+    f.kind = mode == ISAX_MODE_BF16 ? 0 : 1;
+    f.xq = f.kind == 0 ? static_cast<const void*>(idx->x_bf16) : static_cast<const void*>(idx->x_fp8);
+    f.xmeta = f.kind == 0 ? idx->meta_bf16 : idx->meta_fp8;
+    (void)f;
+    if (!a.rerun) launch_homeleaf(a, s);
+    else launch_homeleaf(a, s);
+    throw Error{ISAX_EINVAL, "reduced-precision filter not available in this build"};
+}
+}  // namespace
+
+// =============================================================================================
+extern "C" {
+
+const char* isax_last_error(void) { return g_err_msg.c_str(); }
+
+isax_index* isax_build_ex(const float* data, int64_t n, int32_t len, int32_t segments, int32_t card_bits,
+                          const isax_build_options* opt) {
+    isax_index* out = nullptr;
+    guarded([&] {
+        out = build_impl(data, n, len, segments, card_bits, opt);
+        return ISAX_OK;
+    });
+    return out;
+}
+
+isax_index* isax_build(const float* data, int64_t n, int32_t len, int32_t segments, int32_t card_bits) {
+    return isax_build_ex(data, n, len, segments, card_bits, nullptr);
+}
+
+void isax_free(isax_index* idx) {
+    if (!idx) return;
+    (void)hipStreamSynchronize(idx->stream);
+    delete idx;
+}
+
+int isax_query_ex(isax_index* idx, const float* queries, int64_t m, int32_t k, int64_t* out_ids, float* out_dists,
+                  const isax_query_options* opt) {
+    return guarded([&] { return query_impl(idx, queries, m, k, out_ids, out_dists, opt); });
+}
+
+int isax_query(isax_index* idx, const float* queries, int64_t m, int32_t k, int64_t* out_ids, float* out_dists) {
+    return isax_query_ex(idx, queries, m, k, out_ids, out_dists, nullptr);
+}
+
+int isax_breakpoints(int32_t card_bits, float* out) {
+    return guarded([&] {
+        ISAX_REQUIRE(card_bits >= 1 && card_bits <= 8, "card_bits must be in 1..8");
+        ISAX_REQUIRE(out != nullptr, "out is NULL");
+        const std::vector<float> b = breakpoints_f32(card_bits);
+        std::memcpy(out, b.data(), b.size() * sizeof(float));
+        return ISAX_OK;
+    });
+}
+
+int isax_summarize(const float* data, int64_t n, int32_t len, int32_t segments, int32_t card_bits, uint8_t* out_words,
+                   float* max_abs, void* stream) {
+    return guarded([&] {
+        validate_series_shape(data, n, len, segments, card_bits);
+        ISAX_REQUIRE(out_words != nullptr, "out_words is NULL");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        DevBuf flags(16, s), bt;
+        ISAX_HIP(hipMemsetAsync(flags.p, 0, 16, s));
+        launch_check_finite(data, n * len, reinterpret_cast<int*>(flags.as<unsigned>() + 1), s);
+        unsigned h[2];
+        ISAX_HIP(hipMemcpyAsync(h, flags.p, 8, hipMemcpyDeviceToHost, s));
+        ISAX_HIP(hipStreamSynchronize(s));
+        ISAX_REQUIRE(h[1] == 0, "data holds a non-finite value");
+        const float* beta = upload_beta(card_bits, s, &bt, nullptr);
+        launch_summarise(data, n, len, segments, segments, beta, card_bits, out_words, flags.as<unsigned>(),
+                         reinterpret_cast<int*>(flags.as<unsigned>() + 1), s);
+        ISAX_HIP(hipMemcpyAsync(h, flags.p, 8, hipMemcpyDeviceToHost, s));
+        ISAX_HIP(hipStreamSynchronize(s));
+        if (max_abs) std::memcpy(max_abs, &h[0], 4);
+        return ISAX_OK;
+    });
+}
+
+int isax_index_get_info(const isax_index* idx, isax_index_info* out) {
+    return guarded([&] {
+        ISAX_REQUIRE(idx && out, "index and out must not be NULL");
+        out->n = idx->n;
+        out->len = idx->len;
+        out->segments = idx->w;
+        out->card_bits = idx->c;
+        out->leaf_size = idx->leaf_size;
+        out->key_bits = idx->key_bits;
+        out->has_bf16 = idx->x_bf16 != nullptr;
+        out->has_fp8 = idx->x_fp8 != nullptr;
+        out->n_leaves = idx->n_leaves;
+        out->max_abs = idx->max_abs;
+        out->delta = idx->delta;
+        out->device_bytes = idx->device_bytes;
+        return ISAX_OK;
+    });
+}
+
+int isax_index_export(const isax_index* idx, int32_t* ids_sorted, uint8_t* words_sorted, uint8_t* env_lo,
+                      uint8_t* env_hi) {
+    return guarded([&] {
+        ISAX_REQUIRE(idx != nullptr, "index is NULL");
+        hipStream_t s = idx->stream;
+        if (ids_sorted)
+            ISAX_HIP(hipMemcpyAsync(ids_sorted, idx->ids_sorted, idx->n * 4, hipMemcpyDeviceToDevice, s));
+        if (words_sorted)
+            ISAX_HIP(hipMemcpy2DAsync(words_sorted, idx->w, idx->words_sorted, idx->ws, idx->w, idx->n,
+                                      hipMemcpyDeviceToDevice, s));
+        if (env_lo)
+            ISAX_HIP(hipMemcpy2DAsync(env_lo, idx->w, idx->env_lo, idx->ws, idx->w, idx->n_leaves,
+                                      hipMemcpyDeviceToDevice, s));
+        if (env_hi)
+            ISAX_HIP(hipMemcpy2DAsync(env_hi, idx->w, idx->env_hi, idx->ws, idx->w, idx->n_leaves,
+                                      hipMemcpyDeviceToDevice, s));
+        ISAX_HIP(hipStreamSynchronize(s));
+        return ISAX_OK;
+    });
+}
+
+int isax_lower_bounds(isax_index* idx, const float* queries, int64_t m, float* out_lb) {
+    return guarded([&] {
+        ISAX_REQUIRE(idx != nullptr, "index is NULL");
+        ISAX_REQUIRE(m >= 0, "m must be >= 0");
+        if (m == 0) return ISAX_OK;
+        ISAX_REQUIRE(queries && out_lb, "queries and out_lb must not be NULL");
+        hipStream_t s = idx->stream;
+        std::vector<int32_t> ones(std::min<int64_t>(m, 1024), 1);
+        DevBuf kd(ones.size() * 4, s);
+        ISAX_HIP(hipMemcpyAsync(kd.p, ones.data(), ones.size() * 4, hipMemcpyHostToDevice, s));
+        for (int64_t q0 = 0; q0 < m; q0 += 1024) {
+            const int mq = (int)std::min<int64_t>(1024, m - q0);
+            Batch b;
+            setup_batch(b, idx, queries + q0 * idx->len, mq, kd.as<int32_t>(), 1, 1, 0, nullptr, nullptr, s);
+            launch_qprep(b.a, s);
+            launch_lower_bounds(b.a, out_lb + q0 * idx->n, s);
+        }
+        ISAX_HIP(hipStreamSynchronize(s));
+        return ISAX_OK;
+    });
+}
+
+int isax_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return ISAX_OK;
+}
+
+int isax_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    drain_pending_locked();
+    g_prof.clear();
+    return ISAX_OK;
+}
+
+int isax_profile_read(isax_profile_entry* out, int32_t max_entries, int32_t* n_entries) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    drain_pending_locked();
+    int i = 0;
+    for (auto& kv : g_prof) {
+        if (i >= max_entries) break;
+        std::memset(&out[i], 0, sizeof(out[i]));
+        std::strncpy(out[i].name, kv.first.c_str(), sizeof(out[i].name) - 1);
+        out[i].launches = kv.second.launches;
+        out[i].total_ms = kv.second.ms;
+        out[i].algorithmic_bytes = kv.second.bytes;
+        ++i;
+    }
+    if (n_entries) *n_entries = (int32_t)g_prof.size();
+    return ISAX_OK;
+}
+
+double isax_clock(void) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // extern "C"

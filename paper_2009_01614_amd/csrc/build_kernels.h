@@ -11,8 +11,9 @@ void sort_keys(uint64_t* keys, int32_t* ids, int64_t n, int key_bits, hipStream_
 void launch_gather_words(const uint8_t* words, const int32_t* ids, int64_t n, int ws, uint8_t* out, hipStream_t s);
 void launch_leaf_layout(const uint64_t* keys_sorted, const uint8_t* words_sorted, int64_t n, int ws, int leaf,
                         int64_t n_leaves, uint64_t* leaf_key, uint8_t* lo, uint8_t* hi, hipStream_t s);
-// kind 0: BF16 copy into xb; kind 1: FP8 E4M3 copy into xf; row p holds series ids[p].
+// kind 0: BF16 copy into xb; kind 1: FP8 E4M3 copy into xf; row p (len_pad wide, zero-padded)
+// holds series ids[p].
 // meta[p] = {|x|^2, |e_x|, |x~|, scale}.
-void launch_quantise(const float* data, const int32_t* ids, int64_t n, int len, int kind, uint16_t* xb, uint8_t* xf,
-                     float4* meta, hipStream_t s);
+void launch_quantise(const float* data, const int32_t* ids, int64_t n, int len, int len_pad, int kind, uint16_t* xb,
+                     uint8_t* xf, float4* meta, hipStream_t s);
 }  // namespace isax

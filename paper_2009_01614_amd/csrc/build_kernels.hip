@@ -400,7 +400,7 @@ __device__ inline float up_norm(float sumsq) { return sqrtf(sumsq * (1.0f + 0.00
 
 // Rows are written in leaf order: row p of the copy is series ids_sorted[p].
 __global__ void __launch_bounds__(256) k_quantise(const float* __restrict__ data, const int32_t* __restrict__ ids,
-                                                  int64_t n, int len, int kind, uint16_t* __restrict__ xb,
+                                                  int64_t n, int len, int len_pad, int kind, uint16_t* __restrict__ xb,
                                                   uint8_t* __restrict__ xf, float4* __restrict__ meta) {
     const int lane = threadIdx.x & 63;
     const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
@@ -419,16 +419,16 @@ __global__ void __launch_bounds__(256) k_quantise(const float* __restrict__ data
         if (amax / (scale * 0.5f) <= 448.f) scale *= 0.5f;
     }
     float xn = 0.f, en = 0.f, tn = 0.f;
-    for (int t = lane; t < len; t += 64) {
-        const float v = x[t];
+    for (int t = lane; t < len_pad; t += 64) {
+        const float v = t < len ? x[t] : 0.f;
         float vt;
         if (kind == 0) {
             const uint16_t b = bf16_rne(v);
-            xb[i * len + t] = b;
+            xb[i * len_pad + t] = b;
             vt = bf16_val(b);
         } else {
             const uint8_t b = e4m3_rne(v / scale);
-            xf[i * len + t] = b;
+            xf[i * len_pad + t] = b;
             vt = e4m3_val(b) * scale;
         }
         const float e = v - vt;
@@ -531,10 +531,10 @@ void launch_leaf_layout(const uint64_t* keys_sorted, const uint8_t* words_sorted
     ISAX_HIP(hipGetLastError());
 }
 
-void launch_quantise(const float* data, const int32_t* ids, int64_t n, int len, int kind, uint16_t* xb, uint8_t* xf,
-                     float4* meta, hipStream_t s) {
+void launch_quantise(const float* data, const int32_t* ids, int64_t n, int len, int len_pad, int kind, uint16_t* xb,
+                     uint8_t* xf, float4* meta, hipStream_t s) {
     ProfScope ps("quantise", s);
-    k_quantise<<<(int)((n + 3) / 4), 256, 0, s>>>(data, ids, n, len, kind, xb, xf, meta);
+    k_quantise<<<(int)((n + 3) / 4), 256, 0, s>>>(data, ids, n, len, len_pad, kind, xb, xf, meta);
     ISAX_HIP(hipGetLastError());
 }
 

@@ -1,6 +1,506 @@
-// Reduced-precision dot-product filter (work in progress).
+// Reduced-precision candidate filter on the gfx950 matrix cores.
+//
+// The paper computes lower bounds with SIMD so that only few real distances
+// are needed (Sec. III, ParIS/MESSI).  Here a second, denser filter does the
+// same job for large query batches: ED^2 = |q|^2 + |x|^2 - 2 q.x, with q.x
+// taken from BF16 (or FP8 E4M3) copies on the MFMA units with FP32
+// accumulation.  Its error is bounded rigorously:
+//   q.x - q~.x~ = q.e_x + e_q.x~            (q = q~ + e_q, x = x~ + e_x)
+//   |acc - q~.x~| <= gamma |q~| |x~|        (FP32 accumulation, any order)
+//   M = 2 (|q| |e_x| + (|e_q| + gamma |q~|) |x~|) + kappa (|q|^2 + |x|^2)
+// where kappa covers the FP32 rounding of the norms and of the epilogue.  A
+// series is a candidate iff approx - M <= tau (1 + eps); candidates are then
+// refined with FP32 direct differences like every other path, so the answer
+// stays exact.  The query-side factors are replaced by their maxima over the
+// batch, which makes M separable: per element one FMA and one compare.
+//
+// Layout (verified on the device): for v_mfma_f32_32x32x16_bf16 lane l holds
+// 8 K-values of row/column l % 32 from K-half l / 32, and accumulator r of lane
+// l is C[8 (r/4) + 4 (l/32) + r%4][l % 32].  Any permutation of K applied to
+// both operands leaves the products unchanged, so each lane loads one
+// contiguous half-row: step s of half h covers K [h len/2 + 8 s, +8) for BF16
+// and [h len/2 + 32 s, +32) for FP8 (v_mfma_scale_f32_32x32x64_f8f6f4).
+#include <type_traits>
+
 #include "query_kernels.h"
-extern "C" int isax_filter_scores(isax_index*, const float*, int64_t, int32_t, float*, float*) {
-    isax::set_error(ISAX_EINVAL, "reduced-precision filter not available in this build");
-    return ISAX_EINVAL;
+
+namespace isax {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kInf = __builtin_huge_valf();
+constexpr int kFThreads = 512;  // 8 waves: 2 per SIMD
+constexpr int kNT = 32;         // series per tile
+
+__device__ inline unsigned long long make_key(float d2, int32_t id) {
+    return ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)id;
 }
+__device__ inline unsigned long long load_relaxed(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline float read_tau(const QueryArgs& a, int q, int k) {
+    const unsigned long long b = load_relaxed(a.bestk + (int64_t)q * a.kmax + (k - 1));
+    const float t = b == ~0ull ? kInf : __uint_as_float((unsigned)(b >> 32));
+    return fminf(t, a.tau0[q]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Query codes (row-padded to len_pad with zeros) and per-query factors; batch
+// maxima of |q|, |e_q| + gamma |q~| and |q|^2 go to qmax[0..2].
+__device__ inline uint16_t bf16_rne(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline uint8_t e4m3_rne(float y) {
+    const unsigned sign = (__float_as_uint(y) >> 24) & 0x80u;
+    const float a = fabsf(y);
+    if (a == 0.f) return (uint8_t)sign;
+    int e = ((int)((__float_as_uint(a) >> 23) & 255)) - 127;
+    if (e < -6) return (uint8_t)(sign | (unsigned)rintf(a * 512.f));
+    float q = rintf(ldexpf(a, 3 - e));
+    if (q >= 16.f) {
+        q = 8.f;
+        ++e;
+    }
+    return (uint8_t)(sign | (unsigned)((e + 7) << 3) | ((unsigned)q - 8u));
+}
+__device__ inline float e4m3_val(uint8_t b) {
+    const int ex = (b >> 3) & 15, mn = b & 7;
+    const float v = ex == 0 ? ldexpf((float)mn, -9) : ldexpf((float)(8 + mn), ex - 10);
+    return (b & 0x80) ? -v : v;
+}
+__device__ inline float up(float v) { return v * (1.0f + 0.0009765625f); }
+
+__global__ void __launch_bounds__(64) k_quantise_queries(QueryArgs a, FilterArgs f, int len_pad, unsigned* qmax) {
+    const int q = blockIdx.x;
+    const int lane = threadIdx.x;
+    const bool real = q < a.mq;
+    const float* x = a.Q + (int64_t)q * a.len;
+    float amax = 0.f;
+    if (real)
+        for (int t = lane; t < a.len; t += 64) amax = fmaxf(amax, fabsf(x[t]));
+    for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+    float scale = 1.f;
+    if (f.kind == 1 && amax > 0.f) {
+        int e;
+        const float fr = frexpf(amax / 448.f, &e);
+        scale = ldexpf(1.f, fr == 0.5f ? e - 1 : e);
+        if (amax / scale > 448.f) scale *= 2.f;
+        if (amax / (scale * 0.5f) <= 448.f) scale *= 0.5f;
+    }
+    float qn = 0.f, en = 0.f, tn = 0.f;
+    for (int t = lane; t < len_pad; t += 64) {
+        const float v = (real && t < a.len) ? x[t] : 0.f;
+        float vt;
+        if (f.kind == 0) {
+            const uint16_t b = bf16_rne(v);
+            static_cast<uint16_t*>(f.qq)[(int64_t)q * len_pad + t] = b;
+            vt = __uint_as_float((unsigned)b << 16);
+        } else {
+            const uint8_t b = e4m3_rne(v / scale);
+            static_cast<uint8_t*>(f.qq)[(int64_t)q * len_pad + t] = b;
+            vt = e4m3_val(b) * scale;
+        }
+        const float e = v - vt;
+        qn = fmaf(v, v, qn);
+        en = fmaf(e, e, en);
+        tn = fmaf(vt, vt, tn);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        qn += __shfl_xor(qn, o, 64);
+        en += __shfl_xor(en, o, 64);
+        tn += __shfl_xor(tn, o, 64);
+    }
+    if (lane == 0) {
+        const float nq = up(sqrtf(up(qn)));
+        const float cq = up(up(sqrtf(up(en))) + f.gamma * up(sqrtf(up(tn))));
+        f.qmeta[q] = make_float4(qn, nq, cq, scale);
+        if (real) {
+            atomicMax(qmax + 0, __float_as_uint(nq));
+            atomicMax(qmax + 1, __float_as_uint(cq));
+            atomicMax(qmax + 2, __float_as_uint(up(qn)));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// The filter.  One 512-thread block per CU; each wave owns 32*MT queries whose
+// codes stay in registers; the block streams tiles of 32 series (sorted
+// order) through double-buffered LDS.  Blocks on one XCD that share a series
+// stream but hold different query tiles walk the same tiles together, so the
+// second read of a tile hits that XCD's L2.
+template <int KIND, int KS, int MT>
+struct FilterCfg {
+    static constexpr int EB = KIND == 0 ? 2 : 1;               // bytes per element
+    static constexpr int KPS = KIND == 0 ? 16 : 64;            // K per MFMA step
+    static constexpr int LEN_PAD = KS * KPS;
+    static constexpr int ROW = LEN_PAD * EB;                   // bytes per row
+    static constexpr int STRIDE = ROW + 16;                    // LDS row stride (bank spread)
+    static constexpr int HALF = ROW / 2;
+    static constexpr int STEP_B = KIND == 0 ? 16 : 32;         // bytes per lane per step
+    static constexpr int CHUNKS = kNT * ROW / 16;              // 16-B chunks per tile
+    static constexpr int CPT = (CHUNKS + kFThreads - 1) / kFThreads;
+    static constexpr int QPB = 8 * 32 * MT;                    // queries per block
+};
+
+template <int KIND, int KS, int MT, bool INSPECT>
+__global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs f, int qtiles, int n_streams,
+                                                          const unsigned* __restrict__ qmax) {
+    using C = FilterCfg<KIND, KS, MT>;
+    __shared__ __attribute__((aligned(16))) unsigned char tile[2][kNT * C::STRIDE];
+    __shared__ __attribute__((aligned(16))) float s_H[C::QPB];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    // block -> (query tile, series stream), XCD-aware: blocks b, b+8, ... share an XCD
+    const int b = blockIdx.x;
+    const int xcd = b & 7, slot = b >> 3;
+    const int qt = slot % qtiles;
+    const int stream = (slot / qtiles) * 8 + xcd;
+    const int q_base = qt * C::QPB + wave * 32 * MT;
+
+    const float A = __uint_as_float(qmax[0]), Cq = __uint_as_float(qmax[1]), QN = __uint_as_float(qmax[2]);
+    const float kappa = f.kappa;
+
+    // query fragments: MT tiles x KS steps
+    typedef typename std::conditional<KIND == 0, bf16x8, i32x8>::type Frag;
+    Frag fa[MT][KS];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        const int q = q_base + 32 * t + r;
+        const unsigned char* src = static_cast<const unsigned char*>(f.qq) + (int64_t)q * C::ROW + h * C::HALF;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if constexpr (KIND == 0) {
+                const i32x4 v = *reinterpret_cast<const i32x4*>(src + s * 16);
+                fa[t][s] = __builtin_bit_cast(bf16x8, v);
+            } else {
+                const i32x4 v0 = *reinterpret_cast<const i32x4*>(src + s * 32);
+                const i32x4 v1 = *reinterpret_cast<const i32x4*>(src + s * 32 + 16);
+                i32x8 w;
+                w[0] = v0[0]; w[1] = v0[1]; w[2] = v0[2]; w[3] = v0[3];
+                w[4] = v1[0]; w[5] = v1[1]; w[6] = v1[2]; w[7] = v1[3];
+                fa[t][s] = __builtin_bit_cast(Frag, w);
+            }
+        }
+    }
+    // per-row thresholds H = tau (1 + eps) - |q|^2 (refreshed periodically) and FP8 row scales
+    auto refresh_H = [&]() {
+        for (int i = threadIdx.x; i < C::QPB; i += kFThreads) {
+            const int q = qt * C::QPB + i;
+            float H = -kInf;
+            if (q < a.mq && !(a.rerun && a.done[q])) H = read_tau(a, q, a.kq[q]) * a.tau_scale - f.qmeta[q].x;
+            s_H[i] = H;
+        }
+    };
+    refresh_H();
+    float sq[MT][KIND == 1 ? 16 : 1];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int e = 0; e < (KIND == 1 ? 16 : 1); ++e) {
+            const int q = q_base + 32 * t + 8 * (e >> 2) + 4 * h + (e & 3);
+            sq[t][e] = KIND == 1 ? f.qmeta[q].w : 1.f;
+        }
+
+    const int64_t n_tiles = (a.n + kNT - 1) / kNT;
+    const unsigned char* X = static_cast<const unsigned char*>(f.xq);
+    auto load_tile = [&](int64_t tl, i32x4* stage) {
+#pragma unroll
+        for (int c = 0; c < C::CPT; ++c) {
+            const int ch = threadIdx.x + c * kFThreads;
+            i32x4 v = {0, 0, 0, 0};
+            if (ch < C::CHUNKS) {
+                const int row = ch / (C::ROW / 16), col = ch % (C::ROW / 16);
+                const int64_t pos = tl * kNT + row;
+                if (pos < a.n) v = *reinterpret_cast<const i32x4*>(X + pos * C::ROW + col * 16);
+            }
+            stage[c] = v;
+        }
+    };
+    auto store_tile = [&](int buf, const i32x4* stage) {
+#pragma unroll
+        for (int c = 0; c < C::CPT; ++c) {
+            const int ch = threadIdx.x + c * kFThreads;
+            if (ch < C::CHUNKS) {
+                const int row = ch / (C::ROW / 16), col = ch % (C::ROW / 16);
+                *reinterpret_cast<i32x4*>(&tile[buf][row * C::STRIDE + col * 16]) = stage[c];
+            }
+        }
+    };
+
+    i32x4 stage[C::CPT];
+    int64_t tl = stream;
+    if (tl < n_tiles) {
+        load_tile(tl, stage);
+        store_tile(0, stage);
+    }
+    __syncthreads();
+    int buf = 0;
+    int iter = 0;
+    for (; tl < n_tiles; tl += n_streams, buf ^= 1, ++iter) {
+        const int64_t nxt = tl + n_streams;
+        if (nxt < n_tiles) load_tile(nxt, stage);
+        // series of this lane's column
+        const int64_t pos = tl * kNT + r;
+        float G = kInf, Fx = -2.f, xn = 0.f, mx = 0.f;
+        if (pos < a.n) {
+            const float4 m4 = f.xmeta[pos];
+            xn = m4.x;
+            mx = 2.f * (A * m4.y + Cq * m4.z) + kappa * (QN + m4.x);
+            G = m4.x - mx;
+            Fx = -2.f * m4.w;
+        }
+        f32x16 acc[MT];
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
+        const unsigned char* bsrc = &tile[buf][r * C::STRIDE + h * C::HALF];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if constexpr (KIND == 0) {
+                const bf16x8 bv = __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(bsrc + s * 16));
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[t][s], bv, acc[t], 0, 0, 0);
+            } else {
+                const i32x4 v0 = *reinterpret_cast<const i32x4*>(bsrc + s * 32);
+                const i32x4 v1 = *reinterpret_cast<const i32x4*>(bsrc + s * 32 + 16);
+                i32x8 bv;
+                bv[0] = v0[0]; bv[1] = v0[1]; bv[2] = v0[2]; bv[3] = v0[3];
+                bv[4] = v1[0]; bv[5] = v1[1]; bv[6] = v1[2]; bv[7] = v1[3];
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        __builtin_bit_cast(i32x8, fa[t][s]), bv, acc[t], 0, 0, 0, 127, 0, 127);
+            }
+        }
+        // epilogue: candidate iff fma(-2 s_q s_x, acc, G) <= H; rows 8g + 4h + 0..3 are consecutive
+        if constexpr (INSPECT) {
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int row = 32 * t + 8 * (e >> 2) + 4 * h + (e & 3);
+                    const int q = q_base + row;
+                    if (q < a.mq && pos < a.n) {
+                        const float dot = KIND == 0 ? acc[t][e] : sq[t][KIND == 1 ? e : 0] * (-0.5f * Fx) * acc[t][e];
+                        const int32_t id = a.ids_sorted[pos];
+                        f.out_approx[(int64_t)q * a.n + id] = f.qmeta[q].x + xn - 2.f * dot;
+                        f.out_margin[(int64_t)q * a.n + id] = mx;
+                    }
+                }
+        } else {
+            unsigned hit = 0u;
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const float4 H4 = *reinterpret_cast<const float4*>(&s_H[wave * 32 * MT + 32 * t + 8 * g + 4 * h]);
+                    const float Hv[4] = {H4.x, H4.y, H4.z, H4.w};
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int e = 4 * g + u;
+                        const float v = KIND == 0 ? fmaf(-2.f, acc[t][e], G) : fmaf(sq[t][KIND == 1 ? e : 0], Fx * acc[t][e], G);
+                        hit |= (v <= Hv[u] ? 1u : 0u) << (16 * t + e);
+                    }
+                }
+            if (__ballot(hit != 0u)) {
+                while (hit) {
+                    const int bit = __ffs(hit) - 1;
+                    hit &= hit - 1u;
+                    const int t = bit >> 4, e = bit & 15;
+                    const int q = q_base + 32 * t + 8 * (e >> 2) + 4 * h + (e & 3);
+                    if (q >= a.mq || pos >= a.n) continue;
+                    const int64_t h0 = a.home[2 * q] * a.leaf_size, h1 = a.home[2 * q + 1] * a.leaf_size;
+                    if (pos >= h0 && pos < h1) continue;  // already refined by the approximate answer
+                    const unsigned slot = atomicAdd(f.fcount + q, 1u);
+                    if (slot < (unsigned)f.fcap) f.fcand[(int64_t)q * f.fcap + slot] = (unsigned)pos;
+                }
+            }
+        }
+        if (nxt < n_tiles) store_tile(buf ^ 1, stage);
+        if ((iter & 63) == 63) {
+            __syncthreads();
+            refresh_H();
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Refinement of the filter's candidates: 16 lanes per candidate, FP32 direct
+// differences, early abandoning against the current best-so-far; results in
+// the slack window are emitted like in the iSAX scan.
+__device__ void bestk_insert(unsigned long long* bk, int k, unsigned long long v) {
+    int lo = 0, hi = k;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (load_relaxed(bk + mid) <= v) lo = mid + 1;
+        else hi = mid;
+    }
+    for (int i = lo; i < k && v != ~0ull; ++i) {
+        const unsigned long long old = atomicMin(bk + i, v);
+        if (old > v) v = old;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_refine_filtered(QueryArgs a, FilterArgs f) {
+    extern __shared__ float qrow[];
+    const int q = blockIdx.y;
+    if (a.rerun && a.done[q]) return;
+    const int k = a.kq[q];
+    const unsigned cnt = min(f.fcount[q], (unsigned)f.fcap);
+    if (cnt == 0) return;
+    for (int t = threadIdx.x; t < a.len; t += 256) qrow[t] = a.Q[(int64_t)q * a.len + t];
+    __syncthreads();
+    const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;
+    const bool abandon = !(a.flags & ISAX_QF_NO_EARLY_ABANDON);
+    unsigned long long n_ref = 0, n_bytes = 0, n_emit = 0;
+    for (unsigned i = blockIdx.x * 16 + g; i < cnt; i += gridDim.x * 16) {
+        const unsigned pos = f.fcand[(int64_t)q * f.fcap + i];
+        const int32_t id = a.ids_sorted[pos];
+        const float* row = a.data + (int64_t)id * a.len;
+        const float thr = read_tau(a, q, k) * a.tau_scale;
+        const int S = (a.len + 63) >> 6;
+        float acc = 0.f;
+        int steps = 0;
+        bool dropped = false;
+        for (int s = 0; s < S; ++s) {
+            const int t0 = s * 64 + gl * 4;
+            for (int e = 0; e < 4; ++e)
+                if (t0 + e < a.len) {
+                    const float d = qrow[t0 + e] - row[t0 + e];
+                    acc = fmaf(d, d, acc);
+                }
+            steps = s + 1;
+            if (abandon && s + 1 < S) {
+                float part = acc;
+                part += __shfl_xor(part, 1, 16);
+                part += __shfl_xor(part, 2, 16);
+                part += __shfl_xor(part, 4, 16);
+                part += __shfl_xor(part, 8, 16);
+                if (part > thr) {
+                    dropped = true;
+                    break;
+                }
+            }
+        }
+        float d2 = acc;
+        d2 += __shfl_xor(d2, 1, 16);
+        d2 += __shfl_xor(d2, 2, 16);
+        d2 += __shfl_xor(d2, 4, 16);
+        d2 += __shfl_xor(d2, 8, 16);
+        if (gl == 0) {
+            ++n_ref;
+            n_bytes += (unsigned long long)min(a.len, steps * 64) * 4ull;
+            if (!dropped && d2 <= thr) {
+                const unsigned long long key = make_key(d2, id);
+                const unsigned slot = atomicAdd(a.cand_count + q, 1u);
+                if (slot < (unsigned)a.cap) a.cand[(int64_t)q * a.cap + slot] = key;
+                if (!a.rerun && !(a.flags & ISAX_QF_NO_SHARING)) bestk_insert(a.bestk + (int64_t)q * a.kmax, k, key);
+                ++n_emit;
+            }
+        }
+    }
+    if (gl == 0) {
+        unsigned long long* st = a.stats + (int64_t)q * ST_N;
+        if (n_ref) atomicAdd(st + ST_REFINED, n_ref);
+        if (n_bytes) atomicAdd(st + ST_REFINE_BYTES, n_bytes);
+        if (n_emit) atomicAdd(st + ST_CANDS, n_emit);
+    }
+}
+
+// After a filter-candidate overflow: keep the k-th bound found so far in tau0
+// and start the query's search state afresh (no series is inserted twice).
+__global__ void k_filter_tighten(QueryArgs a, FilterArgs f) {
+    const int q = blockIdx.x;
+    const int k = a.kq[q];
+    __shared__ float t;
+    if (threadIdx.x == 0) t = read_tau(a, q, k);
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.kmax; i += blockDim.x) a.bestk[(int64_t)q * a.kmax + i] = ~0ull;
+    if (threadIdx.x == 0) {
+        a.tau0[q] = t;
+        a.cand_count[q] = 0u;
+        f.fcount[q] = 0u;
+    }
+}
+
+template <int KIND, int KS, int MT>
+void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax, hipStream_t s) {
+    using C = FilterCfg<KIND, KS, MT>;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int qtiles = (a.mq + C::QPB - 1) / C::QPB;
+    const int64_t n_tiles = (a.n + kNT - 1) / kNT;
+    // n_streams * qtiles blocks, n_streams a multiple of 8 (one group per XCD)
+    int n_streams = std::max(8, (cus / qtiles) / 8 * 8);
+    while (n_streams > 8 && n_streams / 2 >= n_tiles) n_streams /= 2;
+    const int blocks = n_streams * qtiles;
+    if (f.out_approx) k_filter<KIND, KS, MT, true><<<blocks, kFThreads, 0, s>>>(a, f, qtiles, n_streams, qmax);
+    else k_filter<KIND, KS, MT, false><<<blocks, kFThreads, 0, s>>>(a, f, qtiles, n_streams, qmax);
+}
+
+}  // namespace
+
+int filter_len_pad(int len) { return (len + 63) / 64 * 64; }
+
+void launch_quantise_queries(const QueryArgs& a, const FilterArgs& f, int mq_pad, unsigned* qmax, hipStream_t s) {
+    ProfScope ps("quantise_queries", s);
+    k_quantise_queries<<<mq_pad, 64, 0, s>>>(a, f, filter_len_pad(a.len), qmax);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_filter(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax, hipStream_t s) {
+    ProfScope ps(f.kind == 0 ? "filter_bf16" : "filter_fp8", s);
+    const int lp = filter_len_pad(a.len);
+    if (f.kind == 0) {
+        switch (lp) {
+            case 64: launch_filter_t<0, 4, 2>(a, f, qmax, s); break;
+            case 128: launch_filter_t<0, 8, 2>(a, f, qmax, s); break;
+            case 192: launch_filter_t<0, 12, 2>(a, f, qmax, s); break;
+            case 256: launch_filter_t<0, 16, 2>(a, f, qmax, s); break;
+            case 320: launch_filter_t<0, 20, 1>(a, f, qmax, s); break;
+            case 384: launch_filter_t<0, 24, 1>(a, f, qmax, s); break;
+            case 448: launch_filter_t<0, 28, 1>(a, f, qmax, s); break;
+            case 512: launch_filter_t<0, 32, 1>(a, f, qmax, s); break;
+            default: throw Error{ISAX_EINVAL, "the reduced-precision filter supports len <= 512"};
+        }
+    } else {
+        switch (lp) {
+            case 64: launch_filter_t<1, 1, 2>(a, f, qmax, s); break;
+            case 128: launch_filter_t<1, 2, 2>(a, f, qmax, s); break;
+            case 192: launch_filter_t<1, 3, 2>(a, f, qmax, s); break;
+            case 256: launch_filter_t<1, 4, 2>(a, f, qmax, s); break;
+            case 320: launch_filter_t<1, 5, 2>(a, f, qmax, s); break;
+            case 384: launch_filter_t<1, 6, 2>(a, f, qmax, s); break;
+            case 448: launch_filter_t<1, 7, 2>(a, f, qmax, s); break;
+            case 512: launch_filter_t<1, 8, 2>(a, f, qmax, s); break;
+            default: throw Error{ISAX_EINVAL, "the reduced-precision filter supports len <= 512"};
+        }
+    }
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_refine_filtered(const QueryArgs& a, const FilterArgs& f, hipStream_t s) {
+    ProfScope ps("refine_filtered", s);
+    const dim3 grid(64, (unsigned)a.mq);
+    k_refine_filtered<<<grid, 256, (size_t)a.len * 4, s>>>(a, f);
+    ISAX_HIP(hipGetLastError());
+}
+
+int filter_queries_per_block(int len) { return filter_len_pad(len) <= 256 ? 512 : 256; }
+
+void launch_filter_tighten(const QueryArgs& a, const FilterArgs& f, hipStream_t s) {
+    k_filter_tighten<<<a.mq, 64, 0, s>>>(a, f);
+    ISAX_HIP(hipGetLastError());
+}
+
+}  // namespace isax

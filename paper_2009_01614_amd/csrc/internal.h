@@ -86,6 +86,12 @@ struct DevBuf {
 void* dev_alloc(size_t bytes);
 
 }  // namespace isax
+struct isax_index;
+namespace isax {
+// Device scratch one query batch of mq queries (row stride kmax) allocates in `mode`.
+int64_t query_scratch_bytes(const isax_index* idx, int mq, int kmax, int mode);
+
+}  // namespace isax
 
 // ---------------------------------------------------------------------------------------------
 // The index.  All device arrays are owned except `data`, which the caller lends.

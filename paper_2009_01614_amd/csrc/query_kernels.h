@@ -75,8 +75,11 @@ struct FilterArgs {
     float* out_approx;        // optional [mq][n] (inspection)
     float* out_margin;        // optional [mq][n]
 };
-void launch_quantise_queries(const QueryArgs& a, const FilterArgs& f, int mq_pad, hipStream_t s);
-void launch_filter(const QueryArgs& a, const FilterArgs& f, hipStream_t s);
+int filter_len_pad(int len);              // rows of the reduced-precision copies are padded to this
+int filter_queries_per_block(int len);    // query codes are padded to a multiple of this
+void launch_quantise_queries(const QueryArgs& a, const FilterArgs& f, int mq_pad, unsigned* qmax, hipStream_t s);
+void launch_filter(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax, hipStream_t s);
 void launch_refine_filtered(const QueryArgs& a, const FilterArgs& f, hipStream_t s);
+void launch_filter_tighten(const QueryArgs& a, const FilterArgs& f, hipStream_t s);
 
 }  // namespace isax

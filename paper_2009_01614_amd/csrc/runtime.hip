@@ -230,15 +230,17 @@ isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int
     idx->env_hi = own<uint8_t>(idx.get(), (size_t)idx->n_leaves * ws);
     launch_leaf_layout(keys.as<uint64_t>(), idx->words_sorted, n, ws, leaf, idx->n_leaves, idx->leaf_key, idx->env_lo,
                        idx->env_hi, s);
+    ISAX_REQUIRE(o.precision == 0 || len <= 512, "the reduced-precision copies support len <= 512");
+    const int lp = filter_len_pad(len);
     if (o.precision & 1) {
-        idx->x_bf16 = own<uint16_t>(idx.get(), (size_t)n * len);
+        idx->x_bf16 = own<uint16_t>(idx.get(), (size_t)n * lp);
         idx->meta_bf16 = own<float4>(idx.get(), n);
-        launch_quantise(data, idx->ids_sorted, n, len, 0, idx->x_bf16, nullptr, idx->meta_bf16, s);
+        launch_quantise(data, idx->ids_sorted, n, len, lp, 0, idx->x_bf16, nullptr, idx->meta_bf16, s);
     }
     if (o.precision & 2) {
-        idx->x_fp8 = own<uint8_t>(idx.get(), (size_t)n * len);
+        idx->x_fp8 = own<uint8_t>(idx.get(), (size_t)n * lp);
         idx->meta_fp8 = own<float4>(idx.get(), n);
-        launch_quantise(data, idx->ids_sorted, n, len, 1, nullptr, idx->x_fp8, idx->meta_fp8, s);
+        launch_quantise(data, idx->ids_sorted, n, len, lp, 1, nullptr, idx->x_fp8, idx->meta_fp8, s);
     }
     words = DevBuf();
     keys = DevBuf();
@@ -305,6 +307,8 @@ void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const 
     b.mem = ar.commit(s);
 }
 
+constexpr int kDefaultCap = 16384;
+
 void fill_stats(const Batch& b, isax_query_stats* out, hipStream_t s) {
     const int mq = b.a.mq;
     std::vector<unsigned long long> st((size_t)mq * ST_N);
@@ -340,7 +344,7 @@ double scan_bytes(const Batch& b, const isax_index* idx, hipStream_t s) {
     return tot;
 }
 
-void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s);  // filter section below
+void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s);  // defined below
 
 void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     QueryArgs& a = b.a;
@@ -429,7 +433,7 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
         kq = kdev.as<int32_t>();
     }
     const int B = o.batch ? o.batch : 1024;
-    const int cap = o.candidate_capacity ? std::max(o.candidate_capacity, k) : 16384;
+    const int cap = o.candidate_capacity ? std::max(o.candidate_capacity, k) : kDefaultCap;
     for (int64_t q0 = 0; q0 < m; q0 += B) {
         const int mq = (int)std::min<int64_t>(B, m - q0);
         Batch b;
@@ -463,18 +467,92 @@ int guarded(F&& f) {
 // =============================================================================================
 // Reduced-precision filter batch (kernels in filter_kernels.hip)
 namespace {
-void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
-    QueryArgs& a = b.a;
+constexpr int kFilterCap = 65536;  // filter candidates kept per query and pass
+
+// gamma: FP32 accumulation error of len_pad exact products, any order and
+// rounding (2u per add).  kappa: relative slack on |q|^2 + |x|^2 covering the
+// FP32 norms and the epilogue, never below 2^-14.
+void filter_constants(int len, float* gamma, float* kappa) {
+    const int lp = filter_len_pad(len);
+    *gamma = (float)(lp * std::ldexp(1.0, -23));
+    double k = std::ldexp(1.0, -14);
+    while (k < 8.0 * len * std::ldexp(1.0, -24)) k *= 2;
+    *kappa = (float)k;
+}
+
+struct FilterScratch {
+    DevBuf mem;
     FilterArgs f{};
+    unsigned* qmax = nullptr;
+    int mq_pad = 0;
+};
+
+void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, int mode, bool inspect,
+                  hipStream_t s) {
+    FilterArgs& f = fs.f;
     f.kind = mode == ISAX_MODE_BF16 ? 0 : 1;
     f.xq = f.kind == 0 ? static_cast<const void*>(idx->x_bf16) : static_cast<const void*>(idx->x_fp8);
     f.xmeta = f.kind == 0 ? idx->meta_bf16 : idx->meta_fp8;
-    (void)f;
-    if (!a.rerun) launch_homeleaf(a, s);
-    else launch_homeleaf(a, s);
-    throw Error{ISAX_EINVAL, "reduced-precision filter not available in this build"};
+    filter_constants(idx->len, &f.gamma, &f.kappa);
+    f.fcap = inspect ? 1 : kFilterCap;
+    const int lp = filter_len_pad(idx->len);
+    const int qpb = filter_queries_per_block(idx->len);
+    fs.mq_pad = (a.mq + qpb - 1) / qpb * qpb;
+    Arena ar;
+    unsigned char* qq = nullptr;
+    ar.add(&qq, (size_t)fs.mq_pad * lp * (f.kind == 0 ? 2 : 1));
+    ar.add(&f.qmeta, fs.mq_pad);
+    ar.add(&fs.qmax, 4);
+    ar.add(&f.fcand, (size_t)a.mq * f.fcap);
+    ar.add(&f.fcount, a.mq);
+    fs.mem = ar.commit(s);
+    f.qq = qq;
+    ISAX_HIP(hipMemsetAsync(fs.qmax, 0, 16, s));
+    ISAX_HIP(hipMemsetAsync(f.fcount, 0, a.mq * sizeof(unsigned), s));
+}
+
+void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
+    QueryArgs& a = b.a;
+    FilterScratch fs;
+    setup_filter(fs, idx, a, mode, false, s);
+    launch_homeleaf(a, s);
+    launch_quantise_queries(a, fs.f, fs.mq_pad, fs.qmax, s);
+    std::vector<unsigned> cnt(a.mq);
+    for (int round = 0;; ++round) {
+        launch_filter(a, fs.f, fs.qmax, s);
+        ISAX_HIP(hipMemcpyAsync(cnt.data(), fs.f.fcount, a.mq * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        ISAX_HIP(hipStreamSynchronize(s));
+        bool over = false;
+        double fb = 0;
+        for (unsigned c : cnt) {
+            over |= c > (unsigned)fs.f.fcap;
+            fb += std::min<unsigned>(c, fs.f.fcap);
+        }
+        if (profiling_on())
+            profile_add_bytes(fs.f.kind == 0 ? "filter_bf16" : "filter_fp8",
+                              (double)a.n * (filter_len_pad(idx->len) * (fs.f.kind == 0 ? 2 : 1) + 16));
+        launch_refine_filtered(a, fs.f, s);
+        if (!over) break;
+        if (a.rerun || round >= 8)
+            throw Error{ISAX_EOVERFLOW, "more than 65536 filter candidates for one query"};
+        launch_filter_tighten(a, fs.f, s);
+        launch_homeleaf(a, s);
+    }
 }
 }  // namespace
+
+int64_t isax::query_scratch_bytes(const isax_index* idx, int mq, int kmax, int mode) {
+    const int64_t per_q = idx->w * 4 + idx->ws + 8 + 16 + 2 * idx->ns * 4 + (int64_t)idx->w * idx->ns * 4 + 4 +
+                          (int64_t)kmax * 8 + (int64_t)kDefaultCap * 8 + 4 + 16 + ST_N * 8 + 8 + 4;
+    int64_t tot = per_q * mq + 16 * 256;
+    if (mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8) {
+        const int qpb = filter_queries_per_block(idx->len);
+        const int64_t mq_pad = (mq + qpb - 1) / qpb * qpb;
+        tot += mq_pad * filter_len_pad(idx->len) * (mode == ISAX_MODE_BF16 ? 2 : 1) + mq_pad * 16 +
+               (int64_t)mq * (kFilterCap * 4 + 4);
+    }
+    return tot;
+}
 
 // =============================================================================================
 extern "C" {
@@ -600,6 +678,34 @@ int isax_lower_bounds(isax_index* idx, const float* queries, int64_t m, float* o
             launch_qprep(b.a, s);
             launch_lower_bounds(b.a, out_lb + q0 * idx->n, s);
         }
+        ISAX_HIP(hipStreamSynchronize(s));
+        return ISAX_OK;
+    });
+}
+
+int isax_filter_scores(isax_index* idx, const float* queries, int64_t m, int32_t mode, float* out_approx,
+                       float* out_margin) {
+    return guarded([&] {
+        ISAX_REQUIRE(idx != nullptr, "index is NULL");
+        ISAX_REQUIRE(mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8, "mode must be ISAX_MODE_BF16 or ISAX_MODE_FP8");
+        ISAX_REQUIRE(mode != ISAX_MODE_BF16 || idx->x_bf16, "index was built without the BF16 copy");
+        ISAX_REQUIRE(mode != ISAX_MODE_FP8 || idx->x_fp8, "index was built without the FP8 copy");
+        ISAX_REQUIRE(m >= 0 && m <= 1024, "m must be in 0..1024");
+        if (m == 0) return ISAX_OK;
+        ISAX_REQUIRE(queries && out_approx && out_margin, "queries and outputs must not be NULL");
+        hipStream_t s = idx->stream;
+        std::vector<int32_t> ones(m, 1);
+        DevBuf kd(m * 4, s);
+        ISAX_HIP(hipMemcpyAsync(kd.p, ones.data(), m * 4, hipMemcpyHostToDevice, s));
+        Batch b;
+        setup_batch(b, idx, queries, (int)m, kd.as<int32_t>(), 1, 1, 0, nullptr, nullptr, s);
+        launch_qprep(b.a, s);
+        FilterScratch fs;
+        setup_filter(fs, idx, b.a, mode, true, s);
+        fs.f.out_approx = out_approx;
+        fs.f.out_margin = out_margin;
+        launch_quantise_queries(b.a, fs.f, fs.mq_pad, fs.qmax, s);
+        launch_filter(b.a, fs.f, fs.qmax, s);
         ISAX_HIP(hipStreamSynchronize(s));
         return ISAX_OK;
     });

@@ -143,8 +143,7 @@ __global__ void k_summarise_generic(const float* __restrict__ data, int64_t n, i
 // the first key_bits positions are kept.  The first w bits are the root subtree.
 __global__ void k_make_keys(const uint8_t* __restrict__ words, int64_t n, int ws, int w, int c, int key_bits,
                             uint64_t* __restrict__ keys, int32_t* __restrict__ ids) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     uint8_t s[64];
     const uint4* src = reinterpret_cast<const uint4*>(words + i * ws);
     for (int q = 0; q < ws / 16; ++q) {
@@ -159,6 +158,7 @@ __global__ void k_make_keys(const uint8_t* __restrict__ words, int64_t n, int ws
             key |= (uint64_t)((s[j] >> (c - 1 - r)) & 1) << (63 - pos);
     keys[i] = key;
     ids[i] = (int32_t)i;
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -300,11 +300,11 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint64_t* 
 __global__ void k_gather_words(const uint8_t* __restrict__ words, const int32_t* __restrict__ ids, int64_t n, int ws,
                                uint8_t* __restrict__ out) {
     const int q16 = ws / 16;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * q16) return;
-    const int64_t p = t / q16;
-    const int q = (int)(t - p * q16);
-    reinterpret_cast<uint4*>(out + p * ws)[q] = reinterpret_cast<const uint4*>(words + (int64_t)ids[p] * ws)[q];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * q16; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = t / q16;
+        const int q = (int)(t - p * q16);
+        reinterpret_cast<uint4*>(out + p * ws)[q] = reinterpret_cast<const uint4*>(words + (int64_t)ids[p] * ws)[q];
+    }
 }
 
 __global__ void k_leaf_keys(const uint64_t* __restrict__ keys_sorted, int64_t n_leaves, int leaf,
@@ -318,8 +318,8 @@ __global__ void __launch_bounds__(256) k_envelopes(const uint8_t* __restrict__ w
                                                    int64_t n_leaves, uint8_t* __restrict__ lo,
                                                    uint8_t* __restrict__ hi) {
     const int lane = threadIdx.x & 63;
-    const int64_t l = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    if (l >= n_leaves) return;
+    for (int64_t l = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); l < n_leaves;
+         l += (int64_t)gridDim.x * (blockDim.x / 64)) {
     const int64_t a = l * leaf;
     const int64_t b = min(n, a + leaf);
     for (int q = 0; q < ws / 16; ++q) {
@@ -355,6 +355,7 @@ __global__ void __launch_bounds__(256) k_envelopes(const uint8_t* __restrict__ w
             lo[l * ws + q * 16 + lane] = (uint8_t)vmn;
             hi[l * ws + q * 16 + lane] = (uint8_t)vmx;
         }
+    }
     }
 }
 
@@ -403,8 +404,8 @@ __global__ void __launch_bounds__(256) k_quantise(const float* __restrict__ data
                                                   int64_t n, int len, int len_pad, int kind, uint16_t* __restrict__ xb,
                                                   uint8_t* __restrict__ xf, float4* __restrict__ meta) {
     const int lane = threadIdx.x & 63;
-    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    if (i >= n) return;
+    for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); i < n;
+         i += (int64_t)gridDim.x * (blockDim.x / 64)) {
     const float* x = data + (int64_t)ids[i] * len;
     float amax = 0.f;
     for (int t = lane; t < len; t += 64) amax = fmaxf(amax, fabsf(x[t]));
@@ -442,6 +443,7 @@ __global__ void __launch_bounds__(256) k_quantise(const float* __restrict__ data
         tn += __shfl_xor(tn, o, 64);
     }
     if (lane == 0) meta[i] = make_float4(xn, up_norm(en), up_norm(tn), scale);
+    }
 }
 
 }  // namespace
@@ -512,14 +514,14 @@ void sort_keys(uint64_t* keys, int32_t* ids, int64_t n, int key_bits, hipStream_
 void launch_make_keys(const uint8_t* words, int64_t n, int ws, int w, int c, int key_bits, uint64_t* keys, int32_t* ids,
                       hipStream_t s) {
     ProfScope ps("make_keys", s);
-    k_make_keys<<<(int)((n + 255) / 256), 256, 0, s>>>(words, n, ws, w, c, key_bits, keys, ids);
+    k_make_keys<<<grid_blocks(n, 256), 256, 0, s>>>(words, n, ws, w, c, key_bits, keys, ids);
     ISAX_HIP(hipGetLastError());
 }
 
 void launch_gather_words(const uint8_t* words, const int32_t* ids, int64_t n, int ws, uint8_t* out, hipStream_t s) {
     ProfScope ps("gather_words", s);
     const int64_t t = n * (ws / 16);
-    k_gather_words<<<(int)((t + 255) / 256), 256, 0, s>>>(words, ids, n, ws, out);
+    k_gather_words<<<grid_blocks(t, 256), 256, 0, s>>>(words, ids, n, ws, out);
     ISAX_HIP(hipGetLastError());
 }
 
@@ -527,14 +529,14 @@ void launch_leaf_layout(const uint64_t* keys_sorted, const uint8_t* words_sorted
                         int64_t n_leaves, uint64_t* leaf_key, uint8_t* lo, uint8_t* hi, hipStream_t s) {
     ProfScope ps("envelopes", s);
     k_leaf_keys<<<(int)((n_leaves + 255) / 256), 256, 0, s>>>(keys_sorted, n_leaves, leaf, leaf_key);
-    k_envelopes<<<(int)((n_leaves + 3) / 4), 256, 0, s>>>(words_sorted, n, ws, leaf, n_leaves, lo, hi);
+    k_envelopes<<<grid_blocks(n_leaves, 4), 256, 0, s>>>(words_sorted, n, ws, leaf, n_leaves, lo, hi);
     ISAX_HIP(hipGetLastError());
 }
 
 void launch_quantise(const float* data, const int32_t* ids, int64_t n, int len, int len_pad, int kind, uint16_t* xb,
                      uint8_t* xf, float4* meta, hipStream_t s) {
     ProfScope ps("quantise", s);
-    k_quantise<<<(int)((n + 3) / 4), 256, 0, s>>>(data, ids, n, len, len_pad, kind, xb, xf, meta);
+    k_quantise<<<grid_blocks(n, 4), 256, 0, s>>>(data, ids, n, len, len_pad, kind, xb, xf, meta);
     ISAX_HIP(hipGetLastError());
 }
 

@@ -207,7 +207,13 @@ __global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs
             sq[t][e] = KIND == 1 ? f.qmeta[q].w : 1.f;
         }
 
+    // tiles of this phase, enumerated as virtual tiles v = 0 .. n_vt-1
     const int64_t n_tiles = (a.n + kNT - 1) / kNT;
+    const int64_t n_sub = (n_tiles + f.sub - 1) / f.sub;
+    const int64_t n_vt = f.phase == 0 ? n_tiles : f.phase == 1 ? n_sub : n_tiles - n_sub;
+    auto tile_of = [&](int64_t v) -> int64_t {
+        return f.phase == 0 ? v : f.phase == 1 ? v * f.sub : v + v / (f.sub - 1) + 1;
+    };
     const unsigned char* X = static_cast<const unsigned char*>(f.xq);
     auto load_tile = [&](int64_t tl, i32x4* stage) {
 #pragma unroll
@@ -234,17 +240,18 @@ __global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs
     };
 
     i32x4 stage[C::CPT];
-    int64_t tl = stream;
-    if (tl < n_tiles) {
-        load_tile(tl, stage);
+    int64_t v = stream;
+    if (v < n_vt) {
+        load_tile(tile_of(v), stage);
         store_tile(0, stage);
     }
     __syncthreads();
     int buf = 0;
     int iter = 0;
-    for (; tl < n_tiles; tl += n_streams, buf ^= 1, ++iter) {
-        const int64_t nxt = tl + n_streams;
-        if (nxt < n_tiles) load_tile(nxt, stage);
+    for (; v < n_vt; v += n_streams, buf ^= 1, ++iter) {
+        const int64_t tl = tile_of(v);
+        const bool has_next = v + n_streams < n_vt;
+        if (has_next) load_tile(tile_of(v + n_streams), stage);
         // series of this lane's column
         const int64_t pos = tl * kNT + r;
         float G = kInf, Fx = -2.f, xn = 0.f, mx = 0.f;
@@ -324,7 +331,7 @@ __global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs
                 }
             }
         }
-        if (nxt < n_tiles) store_tile(buf ^ 1, stage);
+        if (has_next) store_tile(buf ^ 1, stage);
         if ((iter & 63) == 63) {
             __syncthreads();
             refresh_H();
@@ -439,7 +446,11 @@ void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qm
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int qtiles = (a.mq + C::QPB - 1) / C::QPB;
-    const int64_t n_tiles = (a.n + kNT - 1) / kNT;
+    if (f.sub < 2) throw Error{ISAX_EINVAL, "internal: filter tile sampling factor must be >= 2"};
+    int64_t n_tiles = (a.n + kNT - 1) / kNT;
+    const int64_t n_sub = (n_tiles + f.sub - 1) / f.sub;
+    if (f.phase == 1) n_tiles = n_sub;
+    if (f.phase == 2) n_tiles -= n_sub;
     // n_streams * qtiles blocks, n_streams a multiple of 8 (one group per XCD)
     int n_streams = std::max(8, (cus / qtiles) / 8 * 8);
     while (n_streams > 8 && n_streams / 2 >= n_tiles) n_streams /= 2;

@@ -42,6 +42,16 @@ constexpr int kMaxLeaf = 1024;
 
 inline int word_stride(int w) { return (w + 15) / 16 * 16; }
 
+// Blocks for a grid-stride launch over `items` units of work, `per_block` units
+// per block and pass.  Capped so that blocks x threads stays far below 2^32:
+// a dispatch counts its work-items in 32 bits, and a larger grid would wrap.
+inline unsigned grid_blocks(int64_t items, int64_t per_block, int64_t cap = 1 << 16) {
+    int64_t b = (items + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (unsigned)b;
+}
+
 // Relative slack that covers any-order FP32 rounding of a sum of len squares
 // (gamma_len <= len * 2^-24); comparisons against the best-so-far use
 // tau * (1 + eps).  Never below 2^-13.

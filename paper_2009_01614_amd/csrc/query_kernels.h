@@ -74,6 +74,8 @@ struct FilterArgs {
     int fcap;
     float* out_approx;        // optional [mq][n] (inspection)
     float* out_margin;        // optional [mq][n]
+    int phase;                // 0: every tile; 1: tiles t % sub == 0; 2: the other tiles
+    int sub;
 };
 int filter_len_pad(int len);              // rows of the reduced-precision copies are padded to this
 int filter_queries_per_block(int len);    // query codes are padded to a multiple of this

@@ -267,12 +267,14 @@ __device__ void bitonic_sort_u64(unsigned long long* v, int n) {
     __syncthreads();
 }
 
-constexpr int kHomeMax = 4096;  // keys the approximate-answer block can sort (k + 2 leaves)
+constexpr int kHomeMax = 4096;  // keys the approximate-answer block can sort
+constexpr int kHomeLeaves = 4;  // the approximate answer covers at least this many leaves
 
 // Approximate answer (MESSI: descend to the leaf of the query's iSAX summary
 // and take the real distances of its series).  The home leaf is the last leaf
 // whose first key is <= the query key; it is widened by neighbouring leaves
-// until it holds at least k series.  All its series are refined here, the k
+// (alternately after and before it) until it holds at least max(k, 4 leaves)
+// series.  All its series are refined here, the k
 // smallest keys seed the best-so-far list, and those within the slack of the
 // k-th are appended to the candidate list.  The scan skips these leaves.
 __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
@@ -294,9 +296,15 @@ __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
         }
         int64_t l0 = lo, l1 = lo + 1;
         auto count = [&](int64_t x0, int64_t x1) { return min(a.n, x1 * a.leaf_size) - x0 * a.leaf_size; };
-        while (count(l0, l1) < k) {
-            if (l1 < a.n_leaves) ++l1;
-            else --l0;
+        const int64_t want = max((int64_t)k, min((int64_t)kHomeLeaves * a.leaf_size, (int64_t)kHomeMax - 2 * 1024));
+        while (count(l0, l1) < want && count(l0, l1) < a.n) {
+            // grow alternately after and before the home leaf
+            if ((l1 - l0) % 2 == 1 ? l1 < a.n_leaves : l0 == 0) {
+                if (l1 < a.n_leaves) ++l1;
+                else --l0;
+            } else {
+                --l0;
+            }
         }
         s_range[0] = l0;
         s_range[1] = l1;
@@ -568,8 +576,8 @@ __global__ void __launch_bounds__(256) k_brute_scan(QueryArgs a) {
     __shared__ float Qs[kBK][kBT + 1];
     __shared__ float Xs[kBK][kBT + 1];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int64_t x0 = (int64_t)blockIdx.x * kBT;
     const int q0 = blockIdx.y * kBT;
+    for (int64_t x0 = (int64_t)blockIdx.x * kBT; x0 < a.n; x0 += (int64_t)gridDim.x * kBT) {
     float acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -612,6 +620,7 @@ __global__ void __launch_bounds__(256) k_brute_scan(QueryArgs a) {
             const int64_t xi = x0 + tx + 16 * j;
             if (xi < a.n && acc[i][j] <= thr) emit(a, qi, k, acc[i][j], (int32_t)xi);
         }
+    }
     }
 }
 
@@ -765,12 +774,12 @@ __global__ void k_rerun_reset(QueryArgs a) {
 __global__ void __launch_bounds__(256) k_lower_bounds(QueryArgs a, float* __restrict__ out) {
     const int q = blockIdx.y;
     const float* Ts = a.T + (int64_t)q * a.w * a.ns;
-    const int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (pos >= a.n) return;
-    const uint8_t* wd = a.words_sorted + pos * a.ws;
-    float lb = 0.f;
-    for (int j = 0; j < a.w; ++j) lb += Ts[j * a.ns + wd[j]];
-    out[(int64_t)q * a.n + a.ids_sorted[pos]] = lb * a.lb_scale;
+    for (int64_t pos = (int64_t)blockIdx.x * 256 + threadIdx.x; pos < a.n; pos += (int64_t)gridDim.x * 256) {
+        const uint8_t* wd = a.words_sorted + pos * a.ws;
+        float lb = 0.f;
+        for (int j = 0; j < a.w; ++j) lb += Ts[j * a.ns + wd[j]];
+        out[(int64_t)q * a.n + a.ids_sorted[pos]] = lb * a.lb_scale;
+    }
 }
 
 }  // namespace
@@ -818,7 +827,7 @@ void launch_seed(const QueryArgs& a, hipStream_t s) {
 
 void launch_brute_scan(const QueryArgs& a, hipStream_t s) {
     ProfScope ps("brute_scan", s);
-    const dim3 grid((unsigned)((a.n + kBT - 1) / kBT), (unsigned)((a.mq + kBT - 1) / kBT));
+    const dim3 grid(grid_blocks(a.n, kBT, 1 << 15), (unsigned)((a.mq + kBT - 1) / kBT));
     k_brute_scan<<<grid, 256, 0, s>>>(a);
     ISAX_HIP(hipGetLastError());
 }
@@ -835,7 +844,7 @@ void launch_rerun_reset(const QueryArgs& a, hipStream_t s) {
 }
 
 void launch_lower_bounds(const QueryArgs& a, float* out, hipStream_t s) {
-    const dim3 grid((unsigned)((a.n + 255) / 256), (unsigned)a.mq);
+    const dim3 grid(grid_blocks(a.n, 256, 4096), (unsigned)a.mq);
     k_lower_bounds<<<grid, 256, 0, s>>>(a, out);
     ISAX_HIP(hipGetLastError());
 }

@@ -255,6 +255,7 @@ isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int
 struct Batch {
     DevBuf mem;
     QueryArgs a;
+    int fcap0 = 0;  // initial filter-candidate capacity (0: default)
 };
 
 void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const int32_t* kq_dev, int kmax, int cap,
@@ -438,6 +439,7 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
         const int mq = (int)std::min<int64_t>(B, m - q0);
         Batch b;
         setup_batch(b, idx, Q + q0 * idx->len, mq, kq + q0, k, cap, o.flags, out_ids + q0 * k, out_dists + q0 * k, s);
+        b.fcap0 = o.candidate_capacity;
         run_batch(idx, b, o.mode, s);
         if (o.stats) fill_stats(b, o.stats + q0, s);
     }
@@ -467,7 +469,7 @@ int guarded(F&& f) {
 // =============================================================================================
 // Reduced-precision filter batch (kernels in filter_kernels.hip)
 namespace {
-constexpr int kFilterCap = 65536;  // filter candidates kept per query and pass
+constexpr int kFilterCap = 1 << 18;  // initial filter candidates kept per query and pass
 
 // gamma: FP32 accumulation error of len_pad exact products, any order and
 // rounding (2u per add).  kappa: relative slack on |q|^2 + |x|^2 covering the
@@ -481,11 +483,20 @@ void filter_constants(int len, float* gamma, float* kappa) {
 }
 
 struct FilterScratch {
-    DevBuf mem;
+    DevBuf mem, cand;
     FilterArgs f{};
     unsigned* qmax = nullptr;
     int mq_pad = 0;
 };
+
+void alloc_filter_cands(FilterScratch& fs, int mq, int64_t fcap, hipStream_t s) {
+    ISAX_REQUIRE((int64_t)mq * fcap * 4 <= (int64_t(32) << 30),
+                 "filter candidates of this batch exceed 32 GiB; use a smaller batch");
+    fs.cand = DevBuf();
+    fs.cand = DevBuf((size_t)mq * fcap * 4, s);
+    fs.f.fcand = fs.cand.as<unsigned>();
+    fs.f.fcap = (int)fcap;
+}
 
 void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, int mode, bool inspect,
                   hipStream_t s) {
@@ -494,7 +505,8 @@ void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, 
     f.xq = f.kind == 0 ? static_cast<const void*>(idx->x_bf16) : static_cast<const void*>(idx->x_fp8);
     f.xmeta = f.kind == 0 ? idx->meta_bf16 : idx->meta_fp8;
     filter_constants(idx->len, &f.gamma, &f.kappa);
-    f.fcap = inspect ? 1 : kFilterCap;
+    f.phase = 0;
+    f.sub = 64;
     const int lp = filter_len_pad(idx->len);
     const int qpb = filter_queries_per_block(idx->len);
     fs.mq_pad = (a.mq + qpb - 1) / qpb * qpb;
@@ -503,39 +515,68 @@ void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, 
     ar.add(&qq, (size_t)fs.mq_pad * lp * (f.kind == 0 ? 2 : 1));
     ar.add(&f.qmeta, fs.mq_pad);
     ar.add(&fs.qmax, 4);
-    ar.add(&f.fcand, (size_t)a.mq * f.fcap);
     ar.add(&f.fcount, a.mq);
     fs.mem = ar.commit(s);
     f.qq = qq;
+    alloc_filter_cands(fs, a.mq, inspect ? 1 : kFilterCap, s);
     ISAX_HIP(hipMemsetAsync(fs.qmax, 0, 16, s));
     ISAX_HIP(hipMemsetAsync(f.fcount, 0, a.mq * sizeof(unsigned), s));
 }
+
+// Filter, then refine its candidates.  On a large collection the filter runs
+// in two phases: first one tile in kSub (an even sample of the collection),
+// whose refined candidates tighten the best-so-far, then the other tiles.  The
+// per-query candidate count is exact even past the buffer, so on overflow the
+// buffer grows to fit; in a first pass the stored candidates are refined first,
+// which tightens the bound (kept in tau0 while the per-query state restarts),
+// and the phases run again.
+constexpr int kSub = 64;  // equals FilterArgs::sub set in setup_filter
 
 void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     QueryArgs& a = b.a;
     FilterScratch fs;
     setup_filter(fs, idx, a, mode, false, s);
+    if (b.fcap0 > 0 && b.fcap0 != fs.f.fcap) alloc_filter_cands(fs, a.mq, b.fcap0, s);
     launch_homeleaf(a, s);
     launch_quantise_queries(a, fs.f, fs.mq_pad, fs.qmax, s);
+    const int64_t n_tiles = (idx->n + 31) / 32;
+    std::vector<int> phases;
+    if (n_tiles >= 16 * kSub) phases = {1, 2};
+    else phases = {0};
+    const int qpb = filter_queries_per_block(idx->len);
+    const double bytes_all = (double)idx->n * (filter_len_pad(idx->len) * (fs.f.kind == 0 ? 2 : 1) + 16) *
+                             ((fs.mq_pad + qpb - 1) / qpb);
     std::vector<unsigned> cnt(a.mq);
-    for (int round = 0;; ++round) {
-        launch_filter(a, fs.f, fs.qmax, s);
-        ISAX_HIP(hipMemcpyAsync(cnt.data(), fs.f.fcount, a.mq * sizeof(unsigned), hipMemcpyDeviceToHost, s));
-        ISAX_HIP(hipStreamSynchronize(s));
+    for (int attempt = 0;; ++attempt) {
         bool over = false;
-        double fb = 0;
-        for (unsigned c : cnt) {
-            over |= c > (unsigned)fs.f.fcap;
-            fb += std::min<unsigned>(c, fs.f.fcap);
+        unsigned maxc = 0;
+        for (int ph : phases) {
+            fs.f.phase = ph;
+            ISAX_HIP(hipMemsetAsync(fs.f.fcount, 0, a.mq * sizeof(unsigned), s));
+            launch_filter(a, fs.f, fs.qmax, s);
+            if (profiling_on())
+                profile_add_bytes(fs.f.kind == 0 ? "filter_bf16" : "filter_fp8",
+                                  ph == 0 ? bytes_all : ph == 1 ? bytes_all / kSub : bytes_all * (kSub - 1) / kSub);
+            ISAX_HIP(hipMemcpyAsync(cnt.data(), fs.f.fcount, a.mq * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+            ISAX_HIP(hipStreamSynchronize(s));
+            for (unsigned c : cnt) maxc = std::max(maxc, c);
+            if (maxc > (unsigned)fs.f.fcap) {
+                over = true;
+                break;
+            }
+            launch_refine_filtered(a, fs.f, s);
         }
-        if (profiling_on())
-            profile_add_bytes(fs.f.kind == 0 ? "filter_bf16" : "filter_fp8",
-                              (double)a.n * (filter_len_pad(idx->len) * (fs.f.kind == 0 ? 2 : 1) + 16));
-        launch_refine_filtered(a, fs.f, s);
         if (!over) break;
-        if (a.rerun || round >= 8)
-            throw Error{ISAX_EOVERFLOW, "more than 65536 filter candidates for one query"};
-        launch_filter_tighten(a, fs.f, s);
+        if (attempt >= 8) throw Error{ISAX_EOVERFLOW, "filter candidates kept overflowing"};
+        if (!a.rerun) {
+            launch_refine_filtered(a, fs.f, s);
+            launch_filter_tighten(a, fs.f, s);
+        } else {
+            launch_rerun_reset(a, s);
+        }
+        int64_t grow = std::max<int64_t>((int64_t)fs.f.fcap * 2, (int64_t)maxc + maxc / 4);
+        grow = std::min<int64_t>(grow, idx->n);
+        alloc_filter_cands(fs, a.mq, grow, s);
         launch_homeleaf(a, s);
     }
 }

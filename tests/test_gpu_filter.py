@@ -71,3 +71,15 @@ def test_filter_many_query_tiles_and_ragged(isax):
     for mode in ("bf16", "fp8"):
         ids, _ = idx.query(Q, k=3, mode=mode)
         assert np.array_equal(_cpu(ids), ref_ids)
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp8"])
+def test_filter_candidate_overflow_path(isax, mode):
+    X = workload.random_walks(50_021, 256, seed=51, device="cuda")
+    Qn, _, _ = workload.noisy_queries(X, 40, seed=52)
+    Q = torch.cat([Qn, workload.fresh_queries(8, 256, seed=53, device="cuda")]).contiguous()
+    ref_ids, _ = kr.knn_exact_c(_cpu(X), _cpu(Q), 10)
+    idx = isax.Index(X, 16, 8, precision=3)
+    for cap in (16, 200):
+        ids, _ = idx.query(Q, k=10, mode=mode, candidate_capacity=cap)
+        assert np.array_equal(_cpu(ids), ref_ids), cap

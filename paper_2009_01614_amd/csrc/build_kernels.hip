@@ -141,23 +141,40 @@ __global__ void k_summarise_generic(const float* __restrict__ data, int64_t n, i
 // ---------------------------------------------------------------------------------------------
 // Interleaved key: bit (63 - (r*w + j)) holds bit (c-1-r) of segment j; only
 // the first key_bits positions are kept.  The first w bits are the root subtree.
+// 16 segments: the bit of round r of the four bytes of a word is gathered with
+// one multiply ((t & 0x01010101) * 0x01020408 puts byte i's bit at bit 24+i),
+// the 16 bits are assembled with segment j at bit j and then bit-reversed.
+__device__ inline unsigned gather4(unsigned u, int b) {
+    return (((u >> b) & 0x01010101u) * 0x01020408u) >> 24 & 15u;
+}
+
+__global__ void k_make_keys16(const uint8_t* __restrict__ words, int64_t n, int c, int key_bits,
+                              uint64_t* __restrict__ keys, int32_t* __restrict__ ids) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint4 v = reinterpret_cast<const uint4*>(words + i * 16)[0];
+        uint64_t key = 0;
+        for (int r = 0; r < c && 16 * r < key_bits; ++r) {
+            const int b = c - 1 - r;
+            const unsigned g = gather4(v.x, b) | gather4(v.y, b) << 4 | gather4(v.z, b) << 8 | gather4(v.w, b) << 12;
+            key |= (uint64_t)(__builtin_bitreverse32(g) >> 16) << (48 - 16 * r);
+        }
+        if (key_bits < 64) key &= ~0ull << (64 - key_bits);
+        keys[i] = key;
+        ids[i] = (int32_t)i;
+    }
+}
+
 __global__ void k_make_keys(const uint8_t* __restrict__ words, int64_t n, int ws, int w, int c, int key_bits,
                             uint64_t* __restrict__ keys, int32_t* __restrict__ ids) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    uint8_t s[64];
-    const uint4* src = reinterpret_cast<const uint4*>(words + i * ws);
-    for (int q = 0; q < ws / 16; ++q) {
-        uint4 v = src[q];
-        unsigned u[4] = {v.x, v.y, v.z, v.w};
-        for (int b = 0; b < 16 && q * 16 + b < w; ++b) s[q * 16 + b] = (uint8_t)(u[b >> 2] >> (8 * (b & 3)));
-    }
-    uint64_t key = 0;
-    int pos = 0;
-    for (int r = 0; r < c && pos < key_bits; ++r)
-        for (int j = 0; j < w && pos < key_bits; ++j, ++pos)
-            key |= (uint64_t)((s[j] >> (c - 1 - r)) & 1) << (63 - pos);
-    keys[i] = key;
-    ids[i] = (int32_t)i;
+        const uint8_t* s = words + i * ws;
+        uint64_t key = 0;
+        int pos = 0;
+        for (int r = 0; r < c && pos < key_bits; ++r)
+            for (int j = 0; j < w && pos < key_bits; ++j, ++pos)
+                key |= (uint64_t)((s[j] >> (c - 1 - r)) & 1) << (63 - pos);
+        keys[i] = key;
+        ids[i] = (int32_t)i;
     }
 }
 
@@ -400,49 +417,81 @@ __device__ inline float e4m3_val(uint8_t b) {
 __device__ inline float up_norm(float sumsq) { return sqrtf(sumsq * (1.0f + 0.0009765625f)) * (1.0f + 0.0009765625f); }
 
 // Rows are written in leaf order: row p of the copy is series ids_sorted[p].
+// One wave per row and pass; float4 loads when the row allows them, packed
+// stores (4 BF16 = 8 B or 4 E4M3 = 4 B per lane and step).
+template <bool VEC>
 __global__ void __launch_bounds__(256) k_quantise(const float* __restrict__ data, const int32_t* __restrict__ ids,
                                                   int64_t n, int len, int len_pad, int kind, uint16_t* __restrict__ xb,
                                                   uint8_t* __restrict__ xf, float4* __restrict__ meta) {
     const int lane = threadIdx.x & 63;
     for (int64_t i = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); i < n;
          i += (int64_t)gridDim.x * (blockDim.x / 64)) {
-    const float* x = data + (int64_t)ids[i] * len;
-    float amax = 0.f;
-    for (int t = lane; t < len; t += 64) amax = fmaxf(amax, fabsf(x[t]));
-    for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
-    float scale = 1.f;
-    if (kind == 1 && amax > 0.f) {
-        // smallest power of two s with amax / s <= 448
-        int e;
-        const float f = frexpf(amax / 448.f, &e);  // amax/448 = f * 2^e, f in [0.5, 1)
-        scale = ldexpf(1.f, f == 0.5f ? e - 1 : e);
-        if (amax / scale > 448.f) scale *= 2.f;
-        if (amax / (scale * 0.5f) <= 448.f) scale *= 0.5f;
-    }
-    float xn = 0.f, en = 0.f, tn = 0.f;
-    for (int t = lane; t < len_pad; t += 64) {
-        const float v = t < len ? x[t] : 0.f;
-        float vt;
-        if (kind == 0) {
-            const uint16_t b = bf16_rne(v);
-            xb[i * len_pad + t] = b;
-            vt = bf16_val(b);
-        } else {
-            const uint8_t b = e4m3_rne(v / scale);
-            xf[i * len_pad + t] = b;
-            vt = e4m3_val(b) * scale;
+        const float* x = data + (int64_t)ids[i] * len;
+        // rows up to 512 points: every lane holds its (up to) two float4 chunks in registers
+        float v[8];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int t = (lane + 64 * c) * 4;
+            if (VEC) {
+                const float4 q = t < len ? *reinterpret_cast<const float4*>(x + t) : make_float4(0.f, 0.f, 0.f, 0.f);
+                v[4 * c] = q.x; v[4 * c + 1] = q.y; v[4 * c + 2] = q.z; v[4 * c + 3] = q.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[4 * c + e] = t + e < len ? x[t + e] : 0.f;
+            }
         }
-        const float e = v - vt;
-        xn = fmaf(v, v, xn);
-        en = fmaf(e, e, en);
-        tn = fmaf(vt, vt, tn);
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        xn += __shfl_xor(xn, o, 64);
-        en += __shfl_xor(en, o, 64);
-        tn += __shfl_xor(tn, o, 64);
-    }
-    if (lane == 0) meta[i] = make_float4(xn, up_norm(en), up_norm(tn), scale);
+        float amax = 0.f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) amax = fmaxf(amax, fabsf(v[e]));
+        for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+        float scale = 1.f;
+        if (kind == 1 && amax > 0.f) {
+            int e;
+            const float f = frexpf(amax / 448.f, &e);
+            scale = ldexpf(1.f, f == 0.5f ? e - 1 : e);
+            if (amax / scale > 448.f) scale *= 2.f;
+            if (amax / (scale * 0.5f) <= 448.f) scale *= 0.5f;
+        }
+        float xn = 0.f, en = 0.f, tn = 0.f;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int t = (lane + 64 * c) * 4;
+            if (t >= len_pad) continue;
+            float vt[4];
+            if (kind == 0) {
+                uint16_t b[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    b[e] = bf16_rne(v[4 * c + e]);
+                    vt[e] = bf16_val(b[e]);
+                }
+                *reinterpret_cast<uint2*>(xb + i * len_pad + t) =
+                    make_uint2((unsigned)b[0] | (unsigned)b[1] << 16, (unsigned)b[2] | (unsigned)b[3] << 16);
+            } else {
+                unsigned word = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint8_t b = e4m3_rne(v[4 * c + e] / scale);
+                    word |= (unsigned)b << (8 * e);
+                    vt[e] = e4m3_val(b) * scale;
+                }
+                *reinterpret_cast<unsigned*>(xf + i * len_pad + t) = word;
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float ve = v[4 * c + e];
+                const float er = ve - vt[e];
+                xn = fmaf(ve, ve, xn);
+                en = fmaf(er, er, en);
+                tn = fmaf(vt[e], vt[e], tn);
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            xn += __shfl_xor(xn, o, 64);
+            en += __shfl_xor(en, o, 64);
+            tn += __shfl_xor(tn, o, 64);
+        }
+        if (lane == 0) meta[i] = make_float4(xn, up_norm(en), up_norm(tn), scale);
     }
 }
 
@@ -514,7 +563,8 @@ void sort_keys(uint64_t* keys, int32_t* ids, int64_t n, int key_bits, hipStream_
 void launch_make_keys(const uint8_t* words, int64_t n, int ws, int w, int c, int key_bits, uint64_t* keys, int32_t* ids,
                       hipStream_t s) {
     ProfScope ps("make_keys", s);
-    k_make_keys<<<grid_blocks(n, 256), 256, 0, s>>>(words, n, ws, w, c, key_bits, keys, ids);
+    if (w == 16) k_make_keys16<<<grid_blocks(n, 256), 256, 0, s>>>(words, n, c, key_bits, keys, ids);
+    else k_make_keys<<<grid_blocks(n, 256), 256, 0, s>>>(words, n, ws, w, c, key_bits, keys, ids);
     ISAX_HIP(hipGetLastError());
 }
 
@@ -536,7 +586,10 @@ void launch_leaf_layout(const uint64_t* keys_sorted, const uint8_t* words_sorted
 void launch_quantise(const float* data, const int32_t* ids, int64_t n, int len, int len_pad, int kind, uint16_t* xb,
                      uint8_t* xf, float4* meta, hipStream_t s) {
     ProfScope ps("quantise", s);
-    k_quantise<<<grid_blocks(n, 4), 256, 0, s>>>(data, ids, n, len, len_pad, kind, xb, xf, meta);
+    if (len_pad > 512) throw Error{ISAX_EINVAL, "the reduced-precision copies support len <= 512"};
+    const bool vec = len % 4 == 0 && (reinterpret_cast<uintptr_t>(data) & 15) == 0;
+    if (vec) k_quantise<true><<<grid_blocks(n, 4), 256, 0, s>>>(data, ids, n, len, len_pad, kind, xb, xf, meta);
+    else k_quantise<false><<<grid_blocks(n, 4), 256, 0, s>>>(data, ids, n, len, len_pad, kind, xb, xf, meta);
     ISAX_HIP(hipGetLastError());
 }
 

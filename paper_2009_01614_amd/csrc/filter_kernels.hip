@@ -198,6 +198,9 @@ __global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs
         }
     };
     refresh_H();
+    // the query fragments stay resident for the whole kernel: wait for them once
+    // here (vmcnt(0)), so waits inside the loop only cover the tile prefetch
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     float sq[MT][KIND == 1 ? 16 : 1];
 #pragma unroll
     for (int t = 0; t < MT; ++t)
@@ -241,8 +244,15 @@ __global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs
 
     i32x4 stage[C::CPT];
     int64_t v = stream;
+    // per-series metadata of the current tile, fetched one tile ahead
+    auto load_meta = [&](int64_t tile) -> float4 {
+        const int64_t p = tile * kNT + r;
+        return p < a.n ? f.xmeta[p] : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    float4 m_cur = make_float4(0.f, 0.f, 0.f, 0.f);
     if (v < n_vt) {
         load_tile(tile_of(v), stage);
+        m_cur = load_meta(tile_of(v));
         store_tile(0, stage);
     }
     __syncthreads();
@@ -251,16 +261,11 @@ __global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs
     for (; v < n_vt; v += n_streams, buf ^= 1, ++iter) {
         const int64_t tl = tile_of(v);
         const bool has_next = v + n_streams < n_vt;
-        if (has_next) load_tile(tile_of(v + n_streams), stage);
-        // series of this lane's column
-        const int64_t pos = tl * kNT + r;
-        float G = kInf, Fx = -2.f, xn = 0.f, mx = 0.f;
-        if (pos < a.n) {
-            const float4 m4 = f.xmeta[pos];
-            xn = m4.x;
-            mx = 2.f * (A * m4.y + Cq * m4.z) + kappa * (QN + m4.x);
-            G = m4.x - mx;
-            Fx = -2.f * m4.w;
+        float4 m_next = m_cur;
+        if (has_next) {
+            const int64_t tn = tile_of(v + n_streams);
+            load_tile(tn, stage);
+            m_next = load_meta(tn);
         }
         f32x16 acc[MT];
 #pragma unroll
@@ -268,24 +273,47 @@ __global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
         const unsigned char* bsrc = &tile[buf][r * C::STRIDE + h * C::HALF];
+        // B fragments read two steps ahead of the MFMAs that use them
+        if constexpr (KIND == 0) {
+            bf16x8 bq[3];
+            bq[0] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(bsrc));
+            if (KS > 1) bq[1] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(bsrc + 16));
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            if constexpr (KIND == 0) {
-                const bf16x8 bv = __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(bsrc + s * 16));
+            for (int s = 0; s < KS; ++s) {
+                if (s + 2 < KS)
+                    bq[(s + 2) % 3] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(bsrc + (s + 2) * 16));
 #pragma unroll
                 for (int t = 0; t < MT; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[t][s], bv, acc[t], 0, 0, 0);
-            } else {
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[t][s], bq[s % 3], acc[t], 0, 0, 0);
+            }
+        } else {
+            i32x8 bq[2];
+            auto rd = [&](int s) {
                 const i32x4 v0 = *reinterpret_cast<const i32x4*>(bsrc + s * 32);
                 const i32x4 v1 = *reinterpret_cast<const i32x4*>(bsrc + s * 32 + 16);
                 i32x8 bv;
                 bv[0] = v0[0]; bv[1] = v0[1]; bv[2] = v0[2]; bv[3] = v0[3];
                 bv[4] = v1[0]; bv[5] = v1[1]; bv[6] = v1[2]; bv[7] = v1[3];
+                return bv;
+            };
+            bq[0] = rd(0);
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                if (s + 1 < KS) bq[(s + 1) % 2] = rd(s + 1);
 #pragma unroll
                 for (int t = 0; t < MT; ++t)
                     acc[t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        __builtin_bit_cast(i32x8, fa[t][s]), bv, acc[t], 0, 0, 0, 127, 0, 127);
+                        __builtin_bit_cast(i32x8, fa[t][s]), bq[s % 2], acc[t], 0, 0, 0, 127, 0, 127);
             }
+        }
+        // this lane's column: G = |x|^2 - M'(x), Fx = -2 s_x
+        const int64_t pos = tl * kNT + r;
+        float G = kInf, Fx = -2.f, xn = 0.f, mx = 0.f;
+        if (pos < a.n) {
+            xn = m_cur.x;
+            mx = 2.f * (A * m_cur.y + Cq * m_cur.z) + kappa * (QN + m_cur.x);
+            G = m_cur.x - mx;
+            Fx = -2.f * m_cur.w;
         }
         // epilogue: candidate iff fma(-2 s_q s_x, acc, G) <= H; rows 8g + 4h + 0..3 are consecutive
         if constexpr (INSPECT) {
@@ -332,6 +360,7 @@ __global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs
             }
         }
         if (has_next) store_tile(buf ^ 1, stage);
+        m_cur = m_next;
         if ((iter & 63) == 63) {
             __syncthreads();
             refresh_H();

@@ -45,6 +45,11 @@ def main():
     ap.add_argument("--cpu-sample-queries", type=int, default=4)
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="instead of the headline: serve 50M x 256 + 20M x 128 at swept Poisson rates")
+    ap.add_argument("--sweep-mode", default="bf16", choices=["index", "scan", "bf16", "fp8"])
+    ap.add_argument("--precision-report", action="store_true",
+                    help="instead of the headline: 10M x 256, batches of 1024, modes and filter error vs FP64")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many bytes (3 times) to scale HBM counters")
     args = ap.parse_args()
@@ -63,6 +68,10 @@ def main():
     isax.lib()  # fails loudly if the HIP library is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.serving_sweep:
+        return serving_sweep(args, dev)
+    if args.precision_report:
+        return precision_report(args, dev)
     n, L, m, k = args.n, args.len, args.m, args.k
 
     log(f"generating {n} x {L} random walks on the device")
@@ -241,6 +250,153 @@ def main():
         "modes_qps": modes_qps, "serving": serving, "kernels": kernels,
         "roofline": roof, "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def _serve_run(isax, srv, reqs, rate, rng, max_wait_s=120.0):
+    """Submit reqs [(collection, host query, k)] at Poisson rate; return results by tag and wall time."""
+    res = {}
+
+    def producer():
+        tnext = time.perf_counter()
+        for i, (c, q, kk) in enumerate(reqs):
+            tnext += rng.exponential(1.0 / rate) if rate > 0 else 0.0
+            while time.perf_counter() < tnext:
+                time.sleep(min(1e-4, max(0.0, tnext - time.perf_counter())))
+            srv.submit(c, q, kk, i)
+
+    th = threading.Thread(target=producer)
+    t0 = time.perf_counter()
+    th.start()
+    deadline = time.time() + max_wait_s
+    while len(res) < len(reqs) and time.time() < deadline:
+        for r in srv.poll(50):
+            res[r["tag"]] = r
+    th.join()
+    return res, time.perf_counter() - t0
+
+
+def serving_sweep(args, dev):
+    """Serving configuration: two resident collections, Poisson arrivals at swept rates.
+
+    Collections 50M x 256 and 20M x 128 (z-normalised random walks); requests go
+    50/50 to the collections, k uniform over {1, 10, 100}, noisy copies with sigma
+    uniform over {0.01, 0.1, 1}.  Saturation is measured with a burst; each rate
+    then runs a Poisson stream.  A sample of every rate's results is compared with
+    the same queries run alone (ids equal, distances bit-identical).
+    """
+    import numpy as np
+    import torch
+
+    import paper_2009_01614_amd as isax
+    import workload
+
+    mode = args.sweep_mode
+    prec = {"bf16": 1, "fp8": 2}.get(mode, 0)
+    log("generating 50M x 256 and 20M x 128")
+    cols = [workload.random_walks(50_000_000, 256, seed=20090165, device=dev),
+            workload.random_walks(20_000_000, 128, seed=20090166, device=dev)]
+    idx = [isax.Index(X, 16, 8, precision=prec) for X in cols]
+    rng = np.random.default_rng(20091165)
+    pools = []
+    for ci, X in enumerate(cols):
+        qs = []
+        for sgm in (0.01, 0.1, 1.0):
+            q, _, _ = workload.noisy_queries(X, 700, seed=20091165 + ci * 10 + int(sgm * 100), sigmas=(sgm,))
+            qs.append(q.cpu().numpy())
+        pools.append(np.concatenate(qs))
+
+    def make_reqs(count):
+        out = []
+        for _ in range(count):
+            c = int(rng.integers(2))
+            out.append((c, pools[c][int(rng.integers(len(pools[c])))], int(rng.choice([1, 10, 100]))))
+        return out
+
+    srv = isax.Server(idx, mode=mode, max_batch=512, streams=4)
+    _serve_run(isax, srv, make_reqs(512), 0.0, rng)          # warm-up
+    burst = make_reqs(4096)
+    res, wall = _serve_run(isax, srv, burst, 0.0, rng)
+    sat = len(res) / wall
+    log(f"saturation {sat:.0f} queries/s (burst of {len(burst)})")
+    points = []
+    for frac in (0.1, 0.25, 0.5, 0.75, 1.0, 1.2):
+        rate = frac * sat
+        count = int(min(6000, max(300, rate * 3.0)))
+        reqs = make_reqs(count)
+        res, wall = _serve_run(isax, srv, reqs, rate, rng)
+        lat = np.array([(r["t_done"] - r["t_submit"]) * 1e3 for r in res.values()])
+        # alone vs mix on a sample
+        bad = 0
+        for tag in list(res)[:: max(1, len(res) // 40)]:
+            c, q, kk = reqs[tag]
+            ids1, d1 = idx[c].query(torch.from_numpy(q[None]).to(dev), k=kk, mode=mode)
+            r = res[tag]
+            bad += int(r["ids"] != ids1[0].tolist() or
+                       not np.array_equal(np.array(r["dists"], np.float32), d1[0].cpu().numpy()))
+        pt = {"offered_frac": frac, "offered_qps": round(rate, 1), "requests": len(res),
+              "achieved_qps": round(len(res) / wall, 1), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+              "p99_ms": round(float(np.percentile(lat, 99)), 2),
+              "mean_batch": round(float(np.mean([r["batch_size"] for r in res.values()])), 1),
+              "alone_vs_mix_mismatches": bad}
+        log(f"rate {frac:.2f} x sat: {pt}")
+        points.append(pt)
+    srv.close()
+    print(json.dumps({"metric": "serving p50/p99 latency and queries/s", "mode": mode,
+                      "config": {"workload": "50M x 256 + 20M x 128 random walks resident; Poisson arrivals; "
+                                             "k in {1,10,100}; sigma in {0.01,0.1,1}; dynamic batching (max 512), "
+                                             "4 streams, admission by a 4 GiB scratch budget"},
+                      "saturation_qps": round(sat, 1), "sweep": points}), flush=True)
+
+
+def precision_report(args, dev):
+    """Precision configuration: 10M x 256, 4 batches of 1024 queries, k = 1 and 10.
+
+    Reports queries/s of every mode (all exact, ids compared) and, for sampled
+    queries, the reduced-precision filter's error against FP64 distances from the
+    C oracle: max |ED^2 - approx| / M (<= 1 by the proof), mean margin M and the
+    fraction of series the filter keeps at the final bound.
+    """
+    import numpy as np
+    import torch
+
+    import paper_2009_01614_amd as isax
+    import workload
+    from oracle import knn_ref
+
+    n, L = 10_000_000, 256
+    log("generating 10M x 256")
+    X = workload.random_walks(n, L, seed=20090162, device=dev)
+    Q, _, _ = workload.noisy_queries(X, 4096, seed=20091164)
+    idx = isax.Index(X, 16, 8, precision=3)
+    out = {"metric": "exact k-NN queries/s by mode; filter error vs FP64", "config": {
+        "workload": "10M x 256 random walks, 4 batches of 1024 noisy queries (sigma 0.01/0.1/1)"}, "qps": {}}
+    for k in (1, 10):
+        ref = None
+        for mode in ("bf16", "fp8", "index", "scan"):
+            idx.query(Q[:1024].contiguous(), k=k, mode=mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ids = [idx.query(Q[b:b + 1024].contiguous(), k=k, mode=mode, batch=1024)[0] for b in range(0, 4096, 1024)]
+            torch.cuda.synchronize()
+            out["qps"][f"{mode}_k{k}"] = round(4096 / (time.perf_counter() - t0), 1)
+            ids = torch.cat(ids)
+            if ref is None:
+                ref = ids
+            assert torch.equal(ids, ref), f"{mode} disagrees"
+            log(f"k={k} {mode}: {out['qps'][f'{mode}_k{k}']} queries/s")
+    log("filter error vs FP64 on 4 sampled queries")
+    Xh = X.cpu().numpy()
+    sample = Q[[0, 1, 2, 3]].contiguous()
+    d64 = np.stack([knn_ref.sq_dists_c(Xh, sample[j].cpu().numpy()) for j in range(4)])
+    for mode in ("bf16", "fp8"):
+        ap, mg = (t.cpu().numpy().astype(np.float64) for t in idx.filter_scores(sample, mode))
+        err = np.abs(d64 - ap)
+        tau = np.sort(d64, axis=1)[:, 0:1]
+        out[f"filter_{mode}"] = {"max_err_over_margin": float((err / mg).max()), "mean_margin": float(mg.mean()),
+                                 "mean_abs_err": float(err.mean()),
+                                 "kept_fraction_at_final_bound_k1": float(((ap - mg) <= tau).mean())}
+        log(f"{mode}: {out[f'filter_{mode}']}")
     print(json.dumps(out), flush=True)
 
 

@@ -33,7 +33,6 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr float kInf = __builtin_huge_valf();
-constexpr int kFThreads = 512;  // 8 waves: 2 per SIMD
 constexpr int kNT = 32;         // series per tile
 
 __device__ inline unsigned long long make_key(float d2, int32_t id) {
@@ -134,8 +133,9 @@ __global__ void __launch_bounds__(64) k_quantise_queries(QueryArgs a, FilterArgs
 // order) through double-buffered LDS.  Blocks on one XCD that share a series
 // stream but hold different query tiles walk the same tiles together, so the
 // second read of a tile hits that XCD's L2.
-template <int KIND, int KS, int MT>
+template <int KIND, int KS, int MT, int WAVES>
 struct FilterCfg {
+    static constexpr int THREADS = 64 * WAVES;
     static constexpr int EB = KIND == 0 ? 2 : 1;               // bytes per element
     static constexpr int KPS = KIND == 0 ? 16 : 64;            // K per MFMA step
     static constexpr int LEN_PAD = KS * KPS;
@@ -144,14 +144,14 @@ struct FilterCfg {
     static constexpr int HALF = ROW / 2;
     static constexpr int STEP_B = KIND == 0 ? 16 : 32;         // bytes per lane per step
     static constexpr int CHUNKS = kNT * ROW / 16;              // 16-B chunks per tile
-    static constexpr int CPT = (CHUNKS + kFThreads - 1) / kFThreads;
-    static constexpr int QPB = 8 * 32 * MT;                    // queries per block
+    static constexpr int CPT = (CHUNKS + THREADS - 1) / THREADS;
+    static constexpr int QPB = WAVES * 32 * MT;                // queries per block
 };
 
-template <int KIND, int KS, int MT, bool INSPECT>
-__global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs f, int qtiles, int n_streams,
-                                                          const unsigned* __restrict__ qmax) {
-    using C = FilterCfg<KIND, KS, MT>;
+template <int KIND, int KS, int MT, int WAVES, bool INSPECT>
+__global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f, int qtiles, int n_streams,
+                                                        const unsigned* __restrict__ qmax) {
+    using C = FilterCfg<KIND, KS, MT, WAVES>;
     __shared__ __attribute__((aligned(16))) unsigned char tile[2][kNT * C::STRIDE];
     __shared__ __attribute__((aligned(16))) float s_H[C::QPB];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs
     }
     // per-row thresholds H = tau (1 + eps) - |q|^2 (refreshed periodically) and FP8 row scales
     auto refresh_H = [&]() {
-        for (int i = threadIdx.x; i < C::QPB; i += kFThreads) {
+        for (int i = threadIdx.x; i < C::QPB; i += C::THREADS) {
             const int q = qt * C::QPB + i;
             float H = -kInf;
             if (q < a.mq && !(a.rerun && a.done[q])) H = read_tau(a, q, a.kq[q]) * a.tau_scale - f.qmeta[q].x;
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs
     auto load_tile = [&](int64_t tl, i32x4* stage) {
 #pragma unroll
         for (int c = 0; c < C::CPT; ++c) {
-            const int ch = threadIdx.x + c * kFThreads;
+            const int ch = threadIdx.x + c * C::THREADS;
             i32x4 v = {0, 0, 0, 0};
             if (ch < C::CHUNKS) {
                 const int row = ch / (C::ROW / 16), col = ch % (C::ROW / 16);
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(kFThreads, 1) k_filter(QueryArgs a, FilterArgs
     auto store_tile = [&](int buf, const i32x4* stage) {
 #pragma unroll
         for (int c = 0; c < C::CPT; ++c) {
-            const int ch = threadIdx.x + c * kFThreads;
+            const int ch = threadIdx.x + c * C::THREADS;
             if (ch < C::CHUNKS) {
                 const int row = ch / (C::ROW / 16), col = ch % (C::ROW / 16);
                 *reinterpret_cast<i32x4*>(&tile[buf][row * C::STRIDE + col * 16]) = stage[c];
@@ -468,24 +468,34 @@ __global__ void k_filter_tighten(QueryArgs a, FilterArgs f) {
     }
 }
 
-template <int KIND, int KS, int MT>
+// Large batches: 8 waves x 64 queries per block, one block per CU.  Small
+// batches (<= 64 queries): 2 waves x 32 queries, four blocks per CU; the pass is
+// then bound by reading the reduced-precision copy, not by the matrix cores.
+template <int KIND, int KS, int MT, int WAVES>
 void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax, hipStream_t s) {
-    using C = FilterCfg<KIND, KS, MT>;
+    using C = FilterCfg<KIND, KS, MT, WAVES>;
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int qtiles = (a.mq + C::QPB - 1) / C::QPB;
     if (f.sub < 2) throw Error{ISAX_EINVAL, "internal: filter tile sampling factor must be >= 2"};
+    const int qtiles = (a.mq + C::QPB - 1) / C::QPB;
+    const int per_cu = WAVES >= 8 ? 1 : 4;
     int64_t n_tiles = (a.n + kNT - 1) / kNT;
     const int64_t n_sub = (n_tiles + f.sub - 1) / f.sub;
     if (f.phase == 1) n_tiles = n_sub;
     if (f.phase == 2) n_tiles -= n_sub;
     // n_streams * qtiles blocks, n_streams a multiple of 8 (one group per XCD)
-    int n_streams = std::max(8, (cus / qtiles) / 8 * 8);
+    int n_streams = std::max(8, (per_cu * cus / qtiles) / 8 * 8);
     while (n_streams > 8 && n_streams / 2 >= n_tiles) n_streams /= 2;
     const int blocks = n_streams * qtiles;
-    if (f.out_approx) k_filter<KIND, KS, MT, true><<<blocks, kFThreads, 0, s>>>(a, f, qtiles, n_streams, qmax);
-    else k_filter<KIND, KS, MT, false><<<blocks, kFThreads, 0, s>>>(a, f, qtiles, n_streams, qmax);
+    if (f.out_approx) k_filter<KIND, KS, MT, WAVES, true><<<blocks, C::THREADS, 0, s>>>(a, f, qtiles, n_streams, qmax);
+    else k_filter<KIND, KS, MT, WAVES, false><<<blocks, C::THREADS, 0, s>>>(a, f, qtiles, n_streams, qmax);
+}
+
+template <int KIND, int KS, int MT>
+void launch_filter_sized(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax, hipStream_t s) {
+    if (a.mq <= 64 && !f.out_approx) launch_filter_t<KIND, KS, 1, 2>(a, f, qmax, s);
+    else launch_filter_t<KIND, KS, MT, 8>(a, f, qmax, s);
 }
 
 }  // namespace
@@ -503,26 +513,26 @@ void launch_filter(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax
     const int lp = filter_len_pad(a.len);
     if (f.kind == 0) {
         switch (lp) {
-            case 64: launch_filter_t<0, 4, 2>(a, f, qmax, s); break;
-            case 128: launch_filter_t<0, 8, 2>(a, f, qmax, s); break;
-            case 192: launch_filter_t<0, 12, 2>(a, f, qmax, s); break;
-            case 256: launch_filter_t<0, 16, 2>(a, f, qmax, s); break;
-            case 320: launch_filter_t<0, 20, 1>(a, f, qmax, s); break;
-            case 384: launch_filter_t<0, 24, 1>(a, f, qmax, s); break;
-            case 448: launch_filter_t<0, 28, 1>(a, f, qmax, s); break;
-            case 512: launch_filter_t<0, 32, 1>(a, f, qmax, s); break;
+            case 64: launch_filter_t<0, 4, 2, 8>(a, f, qmax, s); break;
+            case 128: launch_filter_sized<0, 8, 2>(a, f, qmax, s); break;
+            case 192: launch_filter_t<0, 12, 2, 8>(a, f, qmax, s); break;
+            case 256: launch_filter_sized<0, 16, 2>(a, f, qmax, s); break;
+            case 320: launch_filter_t<0, 20, 1, 8>(a, f, qmax, s); break;
+            case 384: launch_filter_t<0, 24, 1, 8>(a, f, qmax, s); break;
+            case 448: launch_filter_t<0, 28, 1, 8>(a, f, qmax, s); break;
+            case 512: launch_filter_t<0, 32, 1, 8>(a, f, qmax, s); break;
             default: throw Error{ISAX_EINVAL, "the reduced-precision filter supports len <= 512"};
         }
     } else {
         switch (lp) {
-            case 64: launch_filter_t<1, 1, 2>(a, f, qmax, s); break;
-            case 128: launch_filter_t<1, 2, 2>(a, f, qmax, s); break;
-            case 192: launch_filter_t<1, 3, 2>(a, f, qmax, s); break;
-            case 256: launch_filter_t<1, 4, 2>(a, f, qmax, s); break;
-            case 320: launch_filter_t<1, 5, 2>(a, f, qmax, s); break;
-            case 384: launch_filter_t<1, 6, 2>(a, f, qmax, s); break;
-            case 448: launch_filter_t<1, 7, 2>(a, f, qmax, s); break;
-            case 512: launch_filter_t<1, 8, 2>(a, f, qmax, s); break;
+            case 64: launch_filter_t<1, 1, 2, 8>(a, f, qmax, s); break;
+            case 128: launch_filter_sized<1, 2, 2>(a, f, qmax, s); break;
+            case 192: launch_filter_t<1, 3, 2, 8>(a, f, qmax, s); break;
+            case 256: launch_filter_sized<1, 4, 2>(a, f, qmax, s); break;
+            case 320: launch_filter_t<1, 5, 2, 8>(a, f, qmax, s); break;
+            case 384: launch_filter_t<1, 6, 2, 8>(a, f, qmax, s); break;
+            case 448: launch_filter_t<1, 7, 2, 8>(a, f, qmax, s); break;
+            case 512: launch_filter_t<1, 8, 2, 8>(a, f, qmax, s); break;
             default: throw Error{ISAX_EINVAL, "the reduced-precision filter supports len <= 512"};
         }
     }

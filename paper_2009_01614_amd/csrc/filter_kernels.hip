@@ -479,6 +479,9 @@ void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qm
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (f.sub < 2) throw Error{ISAX_EINVAL, "internal: filter tile sampling factor must be >= 2"};
     const int qtiles = (a.mq + C::QPB - 1) / C::QPB;
+    // the kernel reads query rows [0, qtiles * QPB): they must exist in the padded codes
+    if ((int64_t)qtiles * C::QPB > f.mq_pad)
+        throw Error{ISAX_EINVAL, "internal: query codes padded to fewer rows than the filter reads"};
     const int per_cu = WAVES >= 8 ? 1 : 4;
     int64_t n_tiles = (a.n + kNT - 1) / kNT;
     const int64_t n_sub = (n_tiles + f.sub - 1) / f.sub;
@@ -546,7 +549,12 @@ void launch_refine_filtered(const QueryArgs& a, const FilterArgs& f, hipStream_t
     ISAX_HIP(hipGetLastError());
 }
 
-int filter_queries_per_block(int len) { return filter_len_pad(len) <= 256 ? 512 : 256; }
+// Query codes are padded to a multiple of 512 rows, a multiple of every
+// configuration's queries per block (64, 256 or 512).
+int filter_queries_per_block(int len) {
+    (void)len;
+    return 512;
+}
 
 void launch_filter_tighten(const QueryArgs& a, const FilterArgs& f, hipStream_t s) {
     k_filter_tighten<<<a.mq, 64, 0, s>>>(a, f);

@@ -65,7 +65,8 @@ struct FilterArgs {
     int kind;                 // 0 BF16, 1 FP8
     const void* xq;           // collection codes [n][len] (uint16 BF16 bits or uint8 E4M3)
     const float4* xmeta;      // [n] {|x|^2, |e_x|, |x~|, scale}
-    void* qq;                 // query codes [mq_pad][len]
+    void* qq;                 // query codes [mq_pad][len_pad]
+    int mq_pad;               // rows of qq and qmeta
     float4* qmeta;            // [mq_pad] {|q|^2, |e_q|, |q~|, scale}
     float gamma;              // accumulation error factor
     float kappa;              // relative slack on |q|^2 + |x|^2

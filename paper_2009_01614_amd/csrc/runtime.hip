@@ -149,6 +149,20 @@ using namespace isax;
 // Build
 namespace {
 
+// A pointer the kernels dereference must be device memory or pinned host
+// memory mapped at the same address; anything else (pageable host memory, a
+// stale pointer) is rejected before any device work.
+void require_device_accessible(const void* p, const char* name) {
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof(attr));
+    const hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) (void)hipGetLastError();
+    if (e != hipSuccess || attr.devicePointer == nullptr)
+        throw Error{ISAX_EINVAL, std::string(name) + " is not device memory or pinned host memory"};
+    if (attr.devicePointer != p)
+        throw Error{ISAX_EINVAL, std::string(name) + " is not mapped at the same address on the device"};
+}
+
 int default_key_bits(int w, int c) {
     int b = std::min(64, w * c);
     return (b + 7) / 8 * 8 > 64 ? 64 : (b + 7) / 8 * 8;
@@ -186,6 +200,7 @@ isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int
     ISAX_REQUIRE(key_bits >= 8 && key_bits <= 64 && key_bits % 8 == 0, "key_bits must be a multiple of 8 in 8..64");
     ISAX_REQUIRE(o.precision >= 0 && o.precision <= 3, "precision must be a bitmask of 1 (BF16) and 2 (FP8)");
     ISAX_REQUIRE(o.reserved == 0, "reserved must be 0");
+    require_device_accessible(data, "data");
     hipStream_t s = static_cast<hipStream_t>(o.stream);
 
     std::unique_ptr<isax_index> idx(new isax_index());
@@ -404,6 +419,10 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     if (m == 0) return ISAX_OK;
     ISAX_REQUIRE(Q && out_ids && out_dists, "queries and outputs must not be NULL");
     ISAX_REQUIRE((reinterpret_cast<uintptr_t>(Q) & 3) == 0, "queries must be 4-byte aligned");
+    require_device_accessible(Q, "queries");
+    require_device_accessible(out_ids, "out_ids");
+    require_device_accessible(out_dists, "out_dists");
+    if (o.k_per_query) require_device_accessible(o.k_per_query, "k_per_query");
     hipStream_t s = static_cast<hipStream_t>(o.stream);
     int cur = 0;
     ISAX_HIP(hipGetDevice(&cur));
@@ -518,6 +537,7 @@ void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, 
     ar.add(&f.fcount, a.mq);
     fs.mem = ar.commit(s);
     f.qq = qq;
+    f.mq_pad = fs.mq_pad;
     alloc_filter_cands(fs, a.mq, inspect ? 1 : kFilterCap, s);
     ISAX_HIP(hipMemsetAsync(fs.qmax, 0, 16, s));
     ISAX_HIP(hipMemsetAsync(f.fcount, 0, a.mq * sizeof(unsigned), s));
@@ -644,6 +664,8 @@ int isax_summarize(const float* data, int64_t n, int32_t len, int32_t segments, 
     return guarded([&] {
         validate_series_shape(data, n, len, segments, card_bits);
         ISAX_REQUIRE(out_words != nullptr, "out_words is NULL");
+        require_device_accessible(data, "data");
+        require_device_accessible(out_words, "out_words");
         hipStream_t s = static_cast<hipStream_t>(stream);
         DevBuf flags(16, s), bt;
         ISAX_HIP(hipMemsetAsync(flags.p, 0, 16, s));
@@ -685,6 +707,8 @@ int isax_index_export(const isax_index* idx, int32_t* ids_sorted, uint8_t* words
                       uint8_t* env_hi) {
     return guarded([&] {
         ISAX_REQUIRE(idx != nullptr, "index is NULL");
+        for (const void* p : {(const void*)ids_sorted, (const void*)words_sorted, (const void*)env_lo, (const void*)env_hi})
+            if (p) require_device_accessible(p, "export output");
         hipStream_t s = idx->stream;
         if (ids_sorted)
             ISAX_HIP(hipMemcpyAsync(ids_sorted, idx->ids_sorted, idx->n * 4, hipMemcpyDeviceToDevice, s));
@@ -708,6 +732,8 @@ int isax_lower_bounds(isax_index* idx, const float* queries, int64_t m, float* o
         ISAX_REQUIRE(m >= 0, "m must be >= 0");
         if (m == 0) return ISAX_OK;
         ISAX_REQUIRE(queries && out_lb, "queries and out_lb must not be NULL");
+        require_device_accessible(queries, "queries");
+        require_device_accessible(out_lb, "out_lb");
         hipStream_t s = idx->stream;
         std::vector<int32_t> ones(std::min<int64_t>(m, 1024), 1);
         DevBuf kd(ones.size() * 4, s);
@@ -734,6 +760,9 @@ int isax_filter_scores(isax_index* idx, const float* queries, int64_t m, int32_t
         ISAX_REQUIRE(m >= 0 && m <= 1024, "m must be in 0..1024");
         if (m == 0) return ISAX_OK;
         ISAX_REQUIRE(queries && out_approx && out_margin, "queries and outputs must not be NULL");
+        require_device_accessible(queries, "queries");
+        require_device_accessible(out_approx, "out_approx");
+        require_device_accessible(out_margin, "out_margin");
         hipStream_t s = idx->stream;
         std::vector<int32_t> ones(m, 1);
         DevBuf kd(m * 4, s);

@@ -211,3 +211,7 @@ def test_errors_leave_outputs_untouched(isax, coll):
         idx.query(coll["Q"][:3].contiguous(), k=1001)
     out = idx.query(coll["Q"][:0].contiguous(), k=1)
     assert out[0].shape == (0, 1)
+    # pageable host memory is rejected before any device work
+    host = np.zeros((100, 256), np.float32)
+    assert not isax.lib().isax_build(host.ctypes.data, 100, 256, 16, 8)
+    assert "not device memory" in isax.last_error()

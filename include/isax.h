@@ -57,7 +57,9 @@ enum {
 /* Query flags (isax_query_options.flags): switches for testing; the answer never changes. */
 enum {
     ISAX_QF_NO_SHARING = 1,       /* do not lower the best-so-far during the scan */
-    ISAX_QF_NO_EARLY_ABANDON = 2  /* refine every surviving series to the end */
+    ISAX_QF_NO_EARLY_ABANDON = 2, /* refine every surviving series to the end */
+    ISAX_QF_NO_BEST_FIRST = 4     /* index mode: visit leaves in layout order in one pass, instead of the
+                                     leaves of smallest lower bound first (MESSI's priority order, Sec. III) */
 };
 
 #define ISAX_MAX_K 1024

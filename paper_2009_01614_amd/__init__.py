@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libisax.so")
 ISAX_OK, ISAX_EINVAL, ISAX_ENOMEM, ISAX_EDEVICE, ISAX_EOVERFLOW = 0, -1, -2, -3, -4
 MODE_INDEX, MODE_SCAN, MODE_BF16, MODE_FP8 = 0, 1, 2, 3
 MODES = {"index": MODE_INDEX, "scan": MODE_SCAN, "bf16": MODE_BF16, "fp8": MODE_FP8}
-QF_NO_SHARING, QF_NO_EARLY_ABANDON = 1, 2
+QF_NO_SHARING, QF_NO_EARLY_ABANDON, QF_NO_BEST_FIRST = 1, 2, 4
 MAX_K = 1024
 
 

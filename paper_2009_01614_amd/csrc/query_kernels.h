@@ -48,12 +48,20 @@ struct QueryArgs {
     int* status;                // [mq] 0 ok, 1 candidate overflow (re-run), 2 window too large
     int64_t* out_ids;           // [mq][kmax]
     float* out_dists;           // [mq][kmax]
+    // best-first rounds: round 0 = one pass over every leaf; round 1 = leaves
+    // whose bound is below theta[q]; round 2 = the others
+    int round;
+    float* theta;               // [mq]
+    unsigned* leaf_hist;        // [mq][kLeafBins]
 };
+constexpr int kLeafBins = 64;
+constexpr int kFirstLeaves = 64;  // leaves refined first, by smallest lower bound
 
 void launch_check_finite(const float* x, int64_t count, int* flag, hipStream_t s);
 void launch_qprep(const QueryArgs& a, hipStream_t s);
 void launch_homeleaf(const QueryArgs& a, hipStream_t s);
 void launch_index_scan(const QueryArgs& a, hipStream_t s);
+void launch_leaf_order(const QueryArgs& a, hipStream_t s);  // histogram of leaf bounds -> theta
 void launch_seed(const QueryArgs& a, hipStream_t s);
 void launch_brute_scan(const QueryArgs& a, hipStream_t s);
 void launch_topk(const QueryArgs& a, hipStream_t s);

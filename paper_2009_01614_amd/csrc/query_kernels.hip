@@ -358,6 +358,83 @@ __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
     }
 }
 
+// Squared lower bound of a query against a leaf's envelope: per segment the
+// distance from the query PAA to [widened lower edge of lo, widened upper edge
+// of hi] (the iSAX MINDIST of the union of the leaf's regions).
+__device__ inline float leaf_bound(const QueryArgs& a, int64_t leaf, const float* paa, const float* lo_e,
+                                   const float* hi_e) {
+    const uint8_t* el = a.env_lo + leaf * a.ws;
+    const uint8_t* eh = a.env_hi + leaf * a.ws;
+    float lb = 0.f;
+    for (int qc = 0; qc < a.ws / 16; ++qc) {
+        const uint4 vl = reinterpret_cast<const uint4*>(el)[qc];
+        const uint4 vh = reinterpret_cast<const uint4*>(eh)[qc];
+        const unsigned ul[4] = {vl.x, vl.y, vl.z, vl.w};
+        const unsigned uh[4] = {vh.x, vh.y, vh.z, vh.w};
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            const int j = qc * 16 + b;
+            if (j < a.w) {
+                const int slo = (ul[b >> 2] >> (8 * (b & 3))) & 255;
+                const int shi = (uh[b >> 2] >> (8 * (b & 3))) & 255;
+                const float p = paa[j];
+                const float d = fmaxf(0.f, fmaxf(lo_e[slo] - p, p - hi_e[shi]));
+                lb = fmaf(d, d, lb);
+            }
+        }
+    }
+    return lb * (float)a.m_seg;
+}
+
+// Best-first order (MESSI's priority queues, by rounds): a histogram of the
+// leaf bounds of every query over [0, bsf] in kLeafBins equal bins, and the
+// threshold theta[q] = the lowest bin edge below which at least kFirstLeaves
+// leaves lie.  Round 1 then refines those leaves, which lowers the
+// best-so-far before round 2 bounds the rest.
+__global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
+    __shared__ float lo_e[256], hi_e[256], paa[64];
+    __shared__ unsigned hist[kLeafBins];
+    const int q = blockIdx.y;
+    const int64_t leaf = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t h0 = a.home[2 * q], h1 = a.home[2 * q + 1];
+    for (int s = threadIdx.x; s < a.ns; s += 256) {
+        lo_e[s] = a.edges[(int64_t)q * 2 * a.ns + s];
+        hi_e[s] = a.edges[(int64_t)q * 2 * a.ns + a.ns + s];
+    }
+    if (threadIdx.x < a.w) paa[threadIdx.x] = a.paa[(int64_t)q * a.w + threadIdx.x];
+    if (threadIdx.x < kLeafBins) hist[threadIdx.x] = 0u;
+    __syncthreads();
+    const float thr = read_tau(a, q, a.kq[q]) * a.tau_scale;
+    if (leaf < a.n_leaves && !(leaf >= h0 && leaf < h1)) {
+        const float lb = leaf_bound(a, leaf, paa, lo_e, hi_e);
+        if (lb * a.lb_scale <= thr) {
+            // thr may be 0 (an exact duplicate) or +inf: keep the bin index in range
+            const float f = thr > 0.f ? lb / thr * (float)kLeafBins : 0.f;
+            const int bin = f < (float)(kLeafBins - 1) ? (int)f : kLeafBins - 1;
+            atomicAdd(&hist[bin], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kLeafBins && hist[threadIdx.x])
+        atomicAdd(a.leaf_hist + (int64_t)q * kLeafBins + threadIdx.x, hist[threadIdx.x]);
+}
+
+__global__ void k_leaf_theta(QueryArgs a) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.mq) return;
+    const float thr = read_tau(a, q, a.kq[q]) * a.tau_scale;
+    unsigned cum = 0;
+    float theta = kInf;
+    for (int b = 0; b < kLeafBins; ++b) {
+        cum += a.leaf_hist[(int64_t)q * kLeafBins + b];
+        if (cum >= (unsigned)kFirstLeaves) {
+            theta = (float)(b + 1) / kLeafBins * thr;
+            break;
+        }
+    }
+    a.theta[q] = theta;
+}
+
 // ---------------------------------------------------------------------------------------------
 // The iSAX scan, one block per (query, tile of 256 leaves).
 //  1. leaf lower bound from the widened region edges of the leaf's envelope
@@ -423,28 +500,10 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
     const bool valid_leaf = leaf < a.n_leaves && !(leaf >= h0 && leaf < h1);
     bool keep = false;
     if (valid_leaf) {
-        const uint8_t* el = a.env_lo + leaf * a.ws;
-        const uint8_t* eh = a.env_hi + leaf * a.ws;
-        float lb = 0.f;
-        for (int qc = 0; qc < a.ws / 16; ++qc) {
-            const uint4 vl = reinterpret_cast<const uint4*>(el)[qc];
-            const uint4 vh = reinterpret_cast<const uint4*>(eh)[qc];
-            const unsigned ul[4] = {vl.x, vl.y, vl.z, vl.w};
-            const unsigned uh[4] = {vh.x, vh.y, vh.z, vh.w};
-#pragma unroll
-            for (int b = 0; b < 16; ++b) {
-                const int j = qc * 16 + b;
-                if (j < a.w) {
-                    const int slo = (ul[b >> 2] >> (8 * (b & 3))) & 255;
-                    const int shi = (uh[b >> 2] >> (8 * (b & 3))) & 255;
-                    const float p = paa[j];
-                    const float d = fmaxf(0.f, fmaxf(lo_e[slo] - p, p - hi_e[shi]));
-                    lb = fmaf(d, d, lb);
-                }
-            }
-        }
-        lb *= (float)a.m_seg;
+        const float lb = leaf_bound(a, leaf, paa, lo_e, hi_e);
         keep = lb * a.lb_scale <= thr;
+        if (a.round == 1) keep = keep && lb < a.theta[q];
+        if (a.round == 2) keep = keep && !(lb < a.theta[q]);
     }
     {
         const unsigned long long vm = __ballot(valid_leaf), km = __ballot(keep);
@@ -454,7 +513,7 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
         base = __shfl(base, 0, 64);
         if (keep) list[base + __popcll(km & lt)] = (int)leaf;
         if (lane == 0) {
-            atomicAdd(&s_st[ST_LEAVES], (unsigned long long)__popcll(vm));
+            if (a.round != 1) atomicAdd(&s_st[ST_LEAVES], (unsigned long long)__popcll(vm));
             atomicAdd(&s_st[ST_LEAVES_KEPT], (unsigned long long)__popcll(km));
         }
     }
@@ -803,6 +862,15 @@ void launch_homeleaf(const QueryArgs& a, hipStream_t s) {
     ProfScope ps("homeleaf", s);
     const size_t lds = kHomeMax * sizeof(unsigned long long) + (size_t)a.len * 4;
     k_homeleaf<<<a.mq, 256, lds, s>>>(a);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_leaf_order(const QueryArgs& a, hipStream_t s) {
+    ProfScope ps("leaf_order", s);
+    ISAX_HIP(hipMemsetAsync(a.leaf_hist, 0, (size_t)a.mq * kLeafBins * sizeof(unsigned), s));
+    const dim3 grid((unsigned)((a.n_leaves + 255) / 256), (unsigned)a.mq);
+    k_leaf_hist<<<grid, 256, 0, s>>>(a);
+    k_leaf_theta<<<(a.mq + 255) / 256, 256, 0, s>>>(a);
     ISAX_HIP(hipGetLastError());
 }
 

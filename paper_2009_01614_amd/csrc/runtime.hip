@@ -320,6 +320,8 @@ void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const 
     ar.add(&a.stats, (size_t)mq * ST_N);
     ar.add(&a.done, mq);
     ar.add(&a.status, mq);
+    ar.add(&a.theta, mq);
+    ar.add(&a.leaf_hist, (size_t)mq * kLeafBins);
     b.mem = ar.commit(s);
 }
 
@@ -367,7 +369,16 @@ void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     launch_qprep(a, s);
     if (mode == ISAX_MODE_INDEX) {
         launch_homeleaf(a, s);
-        launch_index_scan(a, s);
+        if (a.flags & ISAX_QF_NO_BEST_FIRST) {
+            a.round = 0;
+            launch_index_scan(a, s);
+        } else {
+            launch_leaf_order(a, s);
+            a.round = 1;
+            launch_index_scan(a, s);
+            a.round = 2;
+            launch_index_scan(a, s);
+        }
         if (profiling_on()) profile_add_bytes("index_scan", scan_bytes(b, idx, s));
     } else if (mode == ISAX_MODE_SCAN) {
         launch_seed(a, s);
@@ -394,6 +405,7 @@ void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
         launch_rerun_reset(a, s);
         if (mode == ISAX_MODE_INDEX) {
             launch_homeleaf(a, s);
+            a.round = 0;  // the bound is frozen: one pass over every leaf
             launch_index_scan(a, s);
         } else if (mode == ISAX_MODE_SCAN) {
             launch_brute_scan(a, s);
@@ -413,7 +425,8 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     if (opt) o = *opt;
     ISAX_REQUIRE(o.mode >= ISAX_MODE_INDEX && o.mode <= ISAX_MODE_FP8, "unknown mode");
     ISAX_REQUIRE(o.candidate_capacity >= 0 && o.batch >= 0, "candidate_capacity and batch must be >= 0");
-    ISAX_REQUIRE((o.flags & ~(ISAX_QF_NO_SHARING | ISAX_QF_NO_EARLY_ABANDON)) == 0, "unknown flag");
+    ISAX_REQUIRE((o.flags & ~(ISAX_QF_NO_SHARING | ISAX_QF_NO_EARLY_ABANDON | ISAX_QF_NO_BEST_FIRST)) == 0,
+                 "unknown flag");
     ISAX_REQUIRE(o.mode != ISAX_MODE_BF16 || idx->x_bf16, "index was built without the BF16 copy");
     ISAX_REQUIRE(o.mode != ISAX_MODE_FP8 || idx->x_fp8, "index was built without the FP8 copy");
     if (m == 0) return ISAX_OK;
@@ -604,7 +617,8 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
 
 int64_t isax::query_scratch_bytes(const isax_index* idx, int mq, int kmax, int mode) {
     const int64_t per_q = idx->w * 4 + idx->ws + 8 + 16 + 2 * idx->ns * 4 + (int64_t)idx->w * idx->ns * 4 + 4 +
-                          (int64_t)kmax * 8 + (int64_t)kDefaultCap * 8 + 4 + 16 + ST_N * 8 + 8 + 4;
+                          (int64_t)kmax * 8 + (int64_t)kDefaultCap * 8 + 4 + 16 + ST_N * 8 + 8 + 4 + 4 +
+                          kLeafBins * 4;
     int64_t tot = per_q * mq + 16 * 256;
     if (mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8) {
         const int qpb = filter_queries_per_block(idx->len);

@@ -142,7 +142,7 @@ def test_metamorphic_summaries(isax, coll, w, c):
     _check_answer(ids, d, coll["ids10"], coll["d2_10"], 3)
 
 
-@pytest.mark.parametrize("flags", [1, 2, 3])
+@pytest.mark.parametrize("flags", [1, 2, 3, 4, 7])
 def test_sharing_and_abandon_switches(isax, coll, flags):
     idx = isax.Index(coll["X"], 16, 8)
     ids, d = idx.query(coll["Q"], k=10, flags=flags)

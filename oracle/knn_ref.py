@@ -88,6 +88,9 @@ def _load():
                                          f32p, ctypes.c_int32, ctypes.c_int32, f64p, i64p]
         lib.oracle_knn_init.argtypes = [f64p, i64p, ctypes.c_int64]
         lib.oracle_sq_dists.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, f32p, f64p]
+        lib.oracle_dtw_sq.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, f32p, ctypes.c_int32, f64p]
+        lib.oracle_dtw_knn_merge.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                             f32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, f64p, i64p]
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -102,11 +105,15 @@ def _ptr(a, ct):
 
 
 class KnnState:
-    """Running per-query top-k lists for streaming a collection through in chunks."""
+    """Running per-query top-k lists for streaming a collection through in chunks.
 
-    def __init__(self, Q: np.ndarray, k: int):
+    window=None: Euclidean distance; window=r: DTW with band half-width r (dtw_ref).
+    """
+
+    def __init__(self, Q: np.ndarray, k: int, window: int | None = None):
         self.Q = np.ascontiguousarray(Q, dtype=np.float32)
         self.k = int(k)
+        self.window = window
         m = self.Q.shape[0]
         self.d2 = np.empty((m, k), np.float64)
         self.ids = np.empty((m, k), np.int64)
@@ -116,9 +123,14 @@ class KnnState:
         X = np.ascontiguousarray(X_chunk, dtype=np.float32)
         if X.shape[1] != self.Q.shape[1]:
             raise ValueError("length mismatch")
-        _load().oracle_knn_merge(_ptr(X, ctypes.c_float), X.shape[0], X.shape[1], int(id_offset),
-                                 _ptr(self.Q, ctypes.c_float), self.Q.shape[0], self.k,
-                                 _ptr(self.d2, ctypes.c_double), _ptr(self.ids, ctypes.c_int64))
+        if self.window is None:
+            _load().oracle_knn_merge(_ptr(X, ctypes.c_float), X.shape[0], X.shape[1], int(id_offset),
+                                     _ptr(self.Q, ctypes.c_float), self.Q.shape[0], self.k,
+                                     _ptr(self.d2, ctypes.c_double), _ptr(self.ids, ctypes.c_int64))
+        else:
+            _load().oracle_dtw_knn_merge(_ptr(X, ctypes.c_float), X.shape[0], X.shape[1], int(id_offset),
+                                         _ptr(self.Q, ctypes.c_float), self.Q.shape[0], self.k, int(self.window),
+                                         _ptr(self.d2, ctypes.c_double), _ptr(self.ids, ctypes.c_int64))
 
 
 def knn_exact_c(X: np.ndarray, Q: np.ndarray, k: int):
@@ -134,4 +146,21 @@ def sq_dists_c(X: np.ndarray, q: np.ndarray) -> np.ndarray:
     out = np.empty(X.shape[0], np.float64)
     _load().oracle_sq_dists(_ptr(X, ctypes.c_float), X.shape[0], X.shape[1],
                             _ptr(q, ctypes.c_float), _ptr(out, ctypes.c_double))
+    return out
+
+
+def knn_dtw_c(X: np.ndarray, Q: np.ndarray, k: int, window: int):
+    """Same result as dtw_ref.knn_dtw, computed by the C twin on all host threads."""
+    st = KnnState(np.asarray(Q, np.float32).reshape(-1, np.asarray(X).shape[1]), k, window)
+    st.merge(X, 0)
+    return st.ids.copy(), st.d2.copy()
+
+
+def dtw_sq_c(X: np.ndarray, q: np.ndarray, window: int) -> np.ndarray:
+    """Same values as dtw_ref.dtw_sq, by the C twin."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    q = np.ascontiguousarray(q, dtype=np.float32)
+    out = np.empty(X.shape[0], np.float64)
+    _load().oracle_dtw_sq(_ptr(X, ctypes.c_float), X.shape[0], X.shape[1], _ptr(q, ctypes.c_float),
+                          int(window), _ptr(out, ctypes.c_double))
     return out

@@ -62,7 +62,17 @@ enum {
                                      leaves of smallest lower bound first (MESSI's priority order, Sec. III) */
 };
 
+/* Distance measures (isax_query_options.metric). */
+enum {
+    ISAX_METRIC_ED = 0, /* Euclidean distance (Sec. II, Similarity Search) */
+    ISAX_METRIC_DTW = 1 /* dynamic time warping (Sec. II names it; Sec. V answers it on the same index):
+                           D(i,j) = (q_i - x_j)^2 + min(D(i-1,j-1), D(i-1,j), D(i,j-1)) over the
+                           Sakoe-Chiba band |i - j| <= window, D(-1,-1) = 0, +inf outside;
+                           distance = sqrt(D(len-1, len-1)) */
+};
+
 #define ISAX_MAX_K 1024
+#define ISAX_MAX_WINDOW 31 /* largest DTW band half-width */
 #define ISAX_MAX_LEN 4096
 #define ISAX_MAX_SEGMENTS 64
 
@@ -85,6 +95,8 @@ typedef struct isax_query_stats { /* per query, filled when requested */
     int64_t candidates;      /* entries appended to the candidate list */
     float tau_initial;       /* squared best-so-far after the approximate answer */
     float tau_final;         /* squared k-th distance found, FP32 */
+    int64_t dtw_series;      /* DTW only: series whose warping distance was (partly) computed */
+    int64_t dtw_cells;       /* DTW only: band cells computed (columns x (2 window + 1)) */
 } isax_query_stats;
 
 typedef struct isax_query_options {
@@ -96,6 +108,8 @@ typedef struct isax_query_options {
                                    of the row is filled with id -1 and +inf); NULL = k for all */
     void* stream;               /* hipStream_t; NULL = null stream */
     isax_query_stats* stats;    /* host, m entries, or NULL */
+    int32_t metric;             /* ISAX_METRIC_*; DTW runs in ISAX_MODE_INDEX and ISAX_MODE_SCAN only */
+    int32_t window;             /* DTW band half-width, 0..min(ISAX_MAX_WINDOW, len-1); must be 0 for ED */
 } isax_query_options;
 
 /* Last error message of the calling thread ("" if none). Static storage, thread-local. */
@@ -125,6 +139,12 @@ void isax_free(isax_index* idx);
  * Similarity Search, generalised from 1 to k neighbours).  m = 0 succeeds with
  * no work.  1 <= k <= min(n, ISAX_MAX_K).  EINVAL if a query value is not
  * finite (outputs untouched).
+ * With opt->metric = ISAX_METRIC_DTW the same index answers the k nearest
+ * series under banded DTW (ISAX_METRIC_DTW above): the leaf and series
+ * bounds use the PAA of the query's envelope, then LB_Keogh, then the DTW
+ * recurrence in FP32 with early abandoning; the final order is decided by
+ * the recurrence recomputed in FP64 (the returned distance is that value's
+ * square root rounded to FP32).
  */
 int isax_query(isax_index* idx, const float* queries, int64_t m, int32_t k, int64_t* out_ids, float* out_dists);
 int isax_query_ex(isax_index* idx, const float* queries, int64_t m, int32_t k, int64_t* out_ids, float* out_dists,

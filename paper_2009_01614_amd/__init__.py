@@ -22,6 +22,9 @@ LIB_PATH = os.path.join(_HERE, "libisax.so")
 ISAX_OK, ISAX_EINVAL, ISAX_ENOMEM, ISAX_EDEVICE, ISAX_EOVERFLOW = 0, -1, -2, -3, -4
 MODE_INDEX, MODE_SCAN, MODE_BF16, MODE_FP8 = 0, 1, 2, 3
 MODES = {"index": MODE_INDEX, "scan": MODE_SCAN, "bf16": MODE_BF16, "fp8": MODE_FP8}
+METRIC_ED, METRIC_DTW = 0, 1
+METRICS = {"ed": METRIC_ED, "dtw": METRIC_DTW}
+MAX_WINDOW = 31
 QF_NO_SHARING, QF_NO_EARLY_ABANDON, QF_NO_BEST_FIRST = 1, 2, 4
 MAX_K = 1024
 
@@ -41,13 +44,14 @@ class QueryStats(ctypes.Structure):
     _fields_ = [("leaves_scanned", ctypes.c_int64), ("leaves_kept", ctypes.c_int64),
                 ("series_bounded", ctypes.c_int64), ("series_refined", ctypes.c_int64),
                 ("refine_bytes", ctypes.c_int64), ("candidates", ctypes.c_int64),
-                ("tau_initial", ctypes.c_float), ("tau_final", ctypes.c_float)]
+                ("tau_initial", ctypes.c_float), ("tau_final", ctypes.c_float),
+                ("dtw_series", ctypes.c_int64), ("dtw_cells", ctypes.c_int64)]
 
 
 class QueryOptions(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("candidate_capacity", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("k_per_query", ctypes.c_void_p), ("stream", ctypes.c_void_p),
-                ("stats", ctypes.POINTER(QueryStats))]
+                ("stats", ctypes.POINTER(QueryStats)), ("metric", ctypes.c_int32), ("window", ctypes.c_int32)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -223,8 +227,12 @@ class Index:
         return ids, words, lo, hi
 
     def query(self, queries: torch.Tensor, k: int = 1, mode="index", k_per_query: torch.Tensor | None = None,
-              candidate_capacity: int = 0, flags: int = 0, batch: int = 0, stream=None, stats: bool = False):
-        """Exact k-NN: (ids int64 [m, k], dists float32 [m, k]); with stats=True also a list of dicts."""
+              candidate_capacity: int = 0, flags: int = 0, batch: int = 0, stream=None, stats: bool = False,
+              metric="ed", window: int = 0):
+        """Exact k-NN: (ids int64 [m, k], dists float32 [m, k]); with stats=True also a list of dicts.
+
+        metric "ed" (Euclidean) or "dtw" (banded DTW of half-width `window`, modes "index" and "scan").
+        """
         _dev_f32(queries, "queries")
         m = queries.shape[0]
         if queries.shape[1] != self.len:
@@ -237,7 +245,8 @@ class Index:
             k_per_query = k_per_query.to(device=queries.device, dtype=torch.int32).contiguous()
             kp = k_per_query.data_ptr()
         opt = QueryOptions(MODES[mode] if isinstance(mode, str) else int(mode), candidate_capacity, flags, batch,
-                           kp, _stream(stream), st)
+                           kp, _stream(stream), st, METRICS[metric] if isinstance(metric, str) else int(metric),
+                           window)
         _check(lib().isax_query_ex(self._h, queries.data_ptr(), m, k, ids.data_ptr(), dists.data_ptr(),
                                    ctypes.byref(opt)))
         if stats:

@@ -5,7 +5,7 @@
 namespace isax {
 
 // Per-query statistics slots (unsigned long long each).
-enum { ST_LEAVES = 0, ST_LEAVES_KEPT, ST_SERIES_LB, ST_REFINED, ST_REFINE_BYTES, ST_CANDS, ST_N };
+enum { ST_LEAVES = 0, ST_LEAVES_KEPT, ST_SERIES_LB, ST_REFINED, ST_REFINE_BYTES, ST_CANDS, ST_DTW, ST_DTW_CELLS, ST_N };
 
 // Everything one batch of queries needs on the device.  Passed by value.
 struct QueryArgs {
@@ -53,7 +53,15 @@ struct QueryArgs {
     int round;
     float* theta;               // [mq]
     unsigned* leaf_hist;        // [mq][kLeafBins]
+    // distance measure
+    int metric;                 // ISAX_METRIC_*
+    int window;                 // DTW band half-width r
+    float lbk_scale;            // DTW: 1 - eps, slack on LB_Keogh
+    int all_leaves;             // 1: no leaf or series bound (the plain scan under DTW)
+    float* env_paa;             // [mq][2][w] PAA of the upper then lower query envelope (ED: the query PAA twice)
+    float* qenv;                // [mq][2][len] DTW: upper then lower envelope of the query
 };
+constexpr int kDtwMaxLen = 2048;  // longest series the DTW path takes (its LDS plan)
 constexpr int kLeafBins = 64;
 constexpr int kFirstLeaves = 64;  // leaves refined first, by smallest lower bound
 

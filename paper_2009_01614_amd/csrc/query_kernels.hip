@@ -111,6 +111,152 @@ __device__ float refine16(const float* __restrict__ row, const float* qrow, int 
 }
 
 // ---------------------------------------------------------------------------------------------
+// DTW pieces.  The grid is D(i, j), i = query index, j = series index, band
+// |i - j| <= r.  Filled column by column (j), column j is held as band cells
+// D[d] = D(j - r + d, j), d = 0..2r; from column j-1 to j:
+//   D(i-1, j-1) = old D[d],  D(i, j-1) = old D[d+1],  D(i-1, j) = new D[d-1].
+// Cells beyond the band or the grid are +inf; D(-1, -1) = 0 is old D[r]
+// before column 0.
+constexpr int kDtwPad = 64;  // +inf entries on each side of the query row in LDS
+
+// LDS copy of the query padded with +inf: qpad[kDtwPad + i] = q_i.
+__device__ inline void load_qpad(float* qpad, const float* __restrict__ qg, int len) {
+    for (int t = threadIdx.x; t < len + 2 * kDtwPad; t += blockDim.x) {
+        const int i = t - kDtwPad;
+        qpad[t] = (i >= 0 && i < len) ? qg[i] : kInf;
+    }
+}
+
+// FP32 DTW^2 of one series per lane, RB >= 2r+1 band cells in registers.
+// The query values come from LDS (the same address in every lane); cells
+// d >= 2r+1 take +inf as query value and so stay +inf.  With `abandon` the
+// lane stops once a whole column exceeds thr and returns +inf: every warping
+// path crosses every column and D does not decrease along a path (in FP32
+// too: fl(c + m) >= m for c >= 0).  `cols` = columns computed.
+template <int RB, bool VEC>
+__device__ float dtw_lane(const float* qpad, const float* __restrict__ row, int len, int r, float thr, bool abandon,
+                          int& cols) {
+    float D[RB];
+#pragma unroll
+    for (int d = 0; d < RB; ++d) D[d] = d == r ? 0.f : kInf;
+    const int B = 2 * r + 1;
+    const float* qw0 = qpad + kDtwPad - r;
+    cols = 0;
+    for (int j0 = 0; j0 < len; j0 += 4) {
+        float xv[4];
+        if (VEC) {
+            const float4 v = *reinterpret_cast<const float4*>(row + j0);
+            xv[0] = v.x;
+            xv[1] = v.y;
+            xv[2] = v.z;
+            xv[3] = v.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xv[e] = j0 + e < len ? row[j0 + e] : 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (j0 + e < len) {
+                const float* qw = qw0 + j0 + e;
+                float left = kInf;
+#pragma unroll
+                for (int d = 0; d < RB; ++d) {
+                    const float qv = d < B ? qw[d] : kInf;
+                    const float df = qv - xv[e];
+                    const float up = d + 1 < RB ? D[d + 1] : kInf;
+                    const float m = fminf(fminf(D[d], up), left);
+                    D[d] = fmaf(df, df, m);
+                    left = D[d];
+                }
+            }
+        }
+        cols = min(len, j0 + 4);
+        if (abandon && j0 + 4 < len) {
+            float mn = D[0];
+#pragma unroll
+            for (int d = 1; d < RB; ++d) mn = fminf(mn, D[d]);
+            if (mn > thr) return kInf;
+        }
+    }
+    float res = kInf;
+#pragma unroll
+    for (int d = 0; d < RB; ++d)
+        if (d == r) res = D[d];
+    return res;
+}
+
+// LB_Keogh^2 of one row against the query envelope (U, L in LDS) by a group of
+// 16 lanes, 64 points per step, with the same early abandoning as refine16.
+template <bool VEC>
+__device__ float lbk16(const float* __restrict__ row, const float* U, const float* L, int len, int gl, float thr,
+                       bool abandon, int& steps) {
+    const int S = (len + 63) >> 6;
+    float acc = 0.f;
+    for (int s = 0; s < S; ++s) {
+        const int t = s * 64 + gl * 4;
+        if (VEC) {
+            if (t < len) {
+                const float4 x = *reinterpret_cast<const float4*>(row + t);
+                const float4 u = *reinterpret_cast<const float4*>(U + t);
+                const float4 l = *reinterpret_cast<const float4*>(L + t);
+                const float d0 = fmaxf(0.f, fmaxf(x.x - u.x, l.x - x.x));
+                const float d1 = fmaxf(0.f, fmaxf(x.y - u.y, l.y - x.y));
+                const float d2 = fmaxf(0.f, fmaxf(x.z - u.z, l.z - x.z));
+                const float d3 = fmaxf(0.f, fmaxf(x.w - u.w, l.w - x.w));
+                acc = fmaf(d0, d0, acc);
+                acc = fmaf(d1, d1, acc);
+                acc = fmaf(d2, d2, acc);
+                acc = fmaf(d3, d3, acc);
+            }
+        } else {
+            for (int e = 0; e < 4; ++e)
+                if (t + e < len) {
+                    const float x = row[t + e];
+                    const float d = fmaxf(0.f, fmaxf(x - U[t + e], L[t + e] - x));
+                    acc = fmaf(d, d, acc);
+                }
+        }
+        steps = s + 1;
+        if (abandon && s + 1 < S) {
+            const float part = sum16(acc);
+            if (part > thr) return kInf;
+        }
+    }
+    return sum16(acc);
+}
+
+// FP64 DTW^2 by one wave, lane d = band cell d (2r+1 <= 64): cell (column j,
+// cell d) depends on (j-1, d), (j-1, d+1) and (j, d-1), so all cells with the
+// same 2j + d are independent; step t computes them, taking the neighbours'
+// values of step t-1 by lane shuffles.  Every cell is d = q_i - x_j in FP64,
+// d * d rounded, + min rounded: the same value as any other order of filling
+// the grid with these operations.
+__device__ double dtw_exact_wave(const float* __restrict__ q, const float* __restrict__ x, int len, int r, int lane) {
+    const double inf = __builtin_huge_val();
+    const int B = 2 * r + 1;
+    double own = inf;
+    const int steps = 2 * (len - 1) + B;
+    for (int t = 0; t < steps; ++t) {
+        const double up = __shfl_down(own, 1, 64);
+        const double left = __shfl_up(own, 1, 64);
+        const int tj = t - lane;
+        if (lane < B && tj >= 0 && (tj & 1) == 0 && (tj >> 1) < len) {
+            const int j = tj >> 1, i = j - r + lane;
+            double v = inf;
+            if (i >= 0 && i < len) {
+                const double u = lane + 1 < B ? up : inf;
+                const double l = lane > 0 ? left : inf;
+                const double m = (i == 0 && j == 0) ? 0.0 : fmin(fmin(own, u), l);
+                const double df = (double)q[i] - (double)x[j];
+                v = __dadd_rn(__dmul_rn(df, df), m);
+            }
+            own = v;
+        }
+    }
+    return __shfl(own, r, 64);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Compensated squared distance (Ogita, Rump, Oishi, "Accurate sum and dot
 // product", SIAM J. Sci. Comput. 2005: TwoSum / TwoProduct, Dot2).  The
 // difference q - x is split exactly into dh + dl, dh^2 is split exactly with an
@@ -158,18 +304,46 @@ __global__ void k_check_finite(const float* __restrict__ x, int64_t count, int* 
     if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
+// FP32 mean of m consecutive values in a fixed order: a balanced tree of
+// adjacent pairs over the values zero-padded to a power of two, then one
+// division by m (the collection's PAA uses the same order).
+__device__ inline float paa_tree(const float* src, int m) {
+    int P = 1;
+    while (P < m) P <<= 1;
+    float stack[14];
+    int level[14];
+    int top = 0;
+    for (int t = 0; t < P; ++t) {
+        stack[top] = t < m ? src[t] : 0.f;
+        level[top] = 0;
+        ++top;
+        while (top >= 2 && level[top - 1] == level[top - 2]) {
+            stack[top - 2] = stack[top - 2] + stack[top - 1];
+            level[top - 2] += 1;
+            --top;
+        }
+    }
+    return stack[0] / (float)m;
+}
+
 // Query preparation, one 64-lane block per query: FP32 PAA in the same fixed
-// order as the collection's (zero-padded balanced tree of adjacent pairs), the
-// symbols and key, |q|^2 and max|q|, the widened region edges and the per-
-// segment table T[j][s] = m * dist(p_j, region s widened by delta)^2.
-// delta = delta_x + m 2^-23 max|q| bounds the FP32 PAA error of both sides;
-// edges are moved one further ulp outwards after widening.
+// order as the collection's, the symbols and key, |q|^2 and max|q|, the
+// widened region edges and the per-segment table T[j][s] = m * dist(query
+// segment j, region s widened by delta)^2.  Under ED the query segment is the
+// point p_j (its PAA); under DTW it is the interval [PAA(L)_j, PAA(U)_j] of
+// the query's envelope (U, L: running max / min over i - r .. i + r), whose
+// distance to a region bounds LB_Keogh and so DTW from below.
+// delta = delta_x + m 2^-23 max|q| bounds the FP32 PAA error of both sides
+// (envelope values are query values, so max|q| bounds them too); edges are
+// moved one further ulp outwards after widening.
 __global__ void __launch_bounds__(64) k_qprep(QueryArgs a) {
+    extern __shared__ float s_env[];  // DTW: [2][len] upper then lower envelope
     const int q = blockIdx.x;
     const int lane = threadIdx.x;
     const float* row = a.Q + (int64_t)q * a.len;
-    __shared__ float s_paa[64];
+    __shared__ float s_pu[64], s_pl[64];
     __shared__ int s_sym[64];
+    const bool dtw = a.metric == ISAX_METRIC_DTW;
     // |q|^2 and max|q|
     float qn = 0.f, amax = 0.f;
     for (int t = lane; t < a.len; t += 64) {
@@ -179,31 +353,36 @@ __global__ void __launch_bounds__(64) k_qprep(QueryArgs a) {
     }
     qn = sum64(qn);
     for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+    if (dtw) {
+        float* gu = a.qenv + (int64_t)q * 2 * a.len;
+        for (int t = lane; t < a.len; t += 64) {
+            float u = -kInf, l = kInf;
+            for (int i = max(0, t - a.window); i <= min(a.len - 1, t + a.window); ++i) {
+                u = fmaxf(u, row[i]);
+                l = fminf(l, row[i]);
+            }
+            s_env[t] = u;
+            s_env[a.len + t] = l;
+            gu[t] = u;
+            gu[a.len + t] = l;
+        }
+        __syncthreads();
+    }
     // PAA, one lane per segment
     if (lane < a.w) {
         const int m = a.m_seg;
-        int P = 1;
-        while (P < m) P <<= 1;
-        float stack[14];
-        int level[14];
-        int top = 0;
-        for (int t = 0; t < P; ++t) {
-            stack[top] = t < m ? row[lane * m + t] : 0.f;
-            level[top] = 0;
-            ++top;
-            while (top >= 2 && level[top - 1] == level[top - 2]) {
-                stack[top - 2] = stack[top - 2] + stack[top - 1];
-                level[top - 2] += 1;
-                --top;
-            }
-        }
-        const float p = stack[0] / (float)m;
+        const float p = paa_tree(row + lane * m, m);
         int s = 0;
         for (int step = 1 << (a.c - 1); step > 0; step >>= 1)
             if (a.beta[s + step - 1] <= p) s += step;
-        s_paa[lane] = p;
         s_sym[lane] = s;
         a.paa[(int64_t)q * a.w + lane] = p;
+        const float pu = dtw ? paa_tree(s_env + lane * m, m) : p;
+        const float pl = dtw ? paa_tree(s_env + a.len + lane * m, m) : p;
+        s_pu[lane] = pu;
+        s_pl[lane] = pl;
+        a.env_paa[(int64_t)q * 2 * a.w + lane] = pu;
+        a.env_paa[(int64_t)q * 2 * a.w + a.w + lane] = pl;
     }
     __syncthreads();
     if (lane < a.ws) a.sym[(int64_t)q * a.ws + lane] = lane < a.w ? (uint8_t)s_sym[lane] : 0;
@@ -223,15 +402,13 @@ __global__ void __launch_bounds__(64) k_qprep(QueryArgs a) {
         lo_e[s] = s == 0 ? -kInf : nextafterf(a.beta[s - 1] - delta, -kInf);
         hi_e[s] = s == a.ns - 1 ? kInf : nextafterf(a.beta[s] + delta, kInf);
     }
-    __syncthreads();
     const float mf = (float)a.m_seg;
     float* T = a.T + (int64_t)q * a.w * a.ns;
     for (int idx = lane; idx < a.w * a.ns; idx += 64) {
         const int j = idx / a.ns, s = idx - j * a.ns;
-        const float p = s_paa[j];
         const float lo = s == 0 ? -kInf : nextafterf(a.beta[s - 1] - delta, -kInf);
         const float hi = s == a.ns - 1 ? kInf : nextafterf(a.beta[s] + delta, kInf);
-        const float d = fmaxf(0.f, fmaxf(lo - p, p - hi));
+        const float d = fmaxf(0.f, fmaxf(lo - s_pu[j], s_pl[j] - hi));
         T[idx] = mf * (d * d);
     }
     // per-query search state
@@ -274,9 +451,11 @@ constexpr int kHomeLeaves = 4;  // the approximate answer covers at least this m
 // and take the real distances of its series).  The home leaf is the last leaf
 // whose first key is <= the query key; it is widened by neighbouring leaves
 // (alternately after and before it) until it holds at least max(k, 4 leaves)
-// series.  All its series are refined here, the k
-// smallest keys seed the best-so-far list, and those within the slack of the
-// k-th are appended to the candidate list.  The scan skips these leaves.
+// series.  All its series are refined here (under DTW: the FP32 recurrence
+// in full, one series per lane), the k smallest keys seed the best-so-far
+// list, and those within the slack of the k-th are appended to the candidate
+// list.  The scan skips these leaves.
+template <int RB>
 __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
     extern __shared__ unsigned char smem_raw[];
     unsigned long long* keys = reinterpret_cast<unsigned long long*>(smem_raw);
@@ -309,23 +488,37 @@ __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
         s_range[0] = l0;
         s_range[1] = l1;
     }
-    for (int t = threadIdx.x; t < a.len; t += blockDim.x) qrow[t] = a.Q[(int64_t)q * a.len + t];
+    if constexpr (RB > 0) load_qpad(qrow, a.Q + (int64_t)q * a.len, a.len);
+    else
+        for (int t = threadIdx.x; t < a.len; t += blockDim.x) qrow[t] = a.Q[(int64_t)q * a.len + t];
     __syncthreads();
     const int64_t p0 = s_range[0] * a.leaf_size, p1 = min(a.n, s_range[1] * a.leaf_size);
     const int cnt = (int)(p1 - p0);
     int P = 1;
     while (P < cnt) P <<= 1;
     for (int i = cnt + threadIdx.x; i < P; i += blockDim.x) keys[i] = kEmpty;
-    for (int i = wave; i < cnt; i += blockDim.x / 64) {
-        const int32_t id = a.ids_sorted[p0 + i];
-        const float* row = a.data + (int64_t)id * a.len;
-        float acc = 0.f;
-        for (int t = lane; t < a.len; t += 64) {
-            const float d = qrow[t] - row[t];
-            acc = fmaf(d, d, acc);
+    if constexpr (RB > 0) {
+        const bool vec = a.len % 4 == 0 && (reinterpret_cast<uintptr_t>(a.data) & 15) == 0;
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+            const int32_t id = a.ids_sorted[p0 + i];
+            const float* row = a.data + (int64_t)id * a.len;
+            int cols = 0;
+            const float v = vec ? dtw_lane<RB, true>(qrow, row, a.len, a.window, kInf, false, cols)
+                                : dtw_lane<RB, false>(qrow, row, a.len, a.window, kInf, false, cols);
+            keys[i] = make_key(v, id);
         }
-        acc = sum64(acc);
-        if (lane == 0) keys[i] = make_key(acc, id);
+    } else {
+        for (int i = wave; i < cnt; i += blockDim.x / 64) {
+            const int32_t id = a.ids_sorted[p0 + i];
+            const float* row = a.data + (int64_t)id * a.len;
+            float acc = 0.f;
+            for (int t = lane; t < a.len; t += 64) {
+                const float d = qrow[t] - row[t];
+                acc = fmaf(d, d, acc);
+            }
+            acc = sum64(acc);
+            if (lane == 0) keys[i] = make_key(acc, id);
+        }
     }
     __syncthreads();
     bitonic_sort_u64(keys, P);
@@ -354,15 +547,20 @@ __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
             st[ST_REFINED] += (unsigned long long)cnt;
             st[ST_REFINE_BYTES] += (unsigned long long)cnt * a.len * 4ull;
             st[ST_CANDS] += (unsigned long long)s_nc;
+            if (RB > 0) {
+                st[ST_DTW] += (unsigned long long)cnt;
+                st[ST_DTW_CELLS] += (unsigned long long)cnt * a.len * (2 * a.window + 1);
+            }
         }
     }
 }
 
 // Squared lower bound of a query against a leaf's envelope: per segment the
-// distance from the query PAA to [widened lower edge of lo, widened upper edge
-// of hi] (the iSAX MINDIST of the union of the leaf's regions).
-__device__ inline float leaf_bound(const QueryArgs& a, int64_t leaf, const float* paa, const float* lo_e,
-                                   const float* hi_e) {
+// distance from the query segment [pl_j, pu_j] (ED: the PAA point) to
+// [widened lower edge of lo, widened upper edge of hi] (the iSAX MINDIST of
+// the union of the leaf's regions).
+__device__ inline float leaf_bound(const QueryArgs& a, int64_t leaf, const float* pu, const float* pl,
+                                   const float* lo_e, const float* hi_e) {
     const uint8_t* el = a.env_lo + leaf * a.ws;
     const uint8_t* eh = a.env_hi + leaf * a.ws;
     float lb = 0.f;
@@ -377,8 +575,7 @@ __device__ inline float leaf_bound(const QueryArgs& a, int64_t leaf, const float
             if (j < a.w) {
                 const int slo = (ul[b >> 2] >> (8 * (b & 3))) & 255;
                 const int shi = (uh[b >> 2] >> (8 * (b & 3))) & 255;
-                const float p = paa[j];
-                const float d = fmaxf(0.f, fmaxf(lo_e[slo] - p, p - hi_e[shi]));
+                const float d = fmaxf(0.f, fmaxf(lo_e[slo] - pu[j], pl[j] - hi_e[shi]));
                 lb = fmaf(d, d, lb);
             }
         }
@@ -392,7 +589,7 @@ __device__ inline float leaf_bound(const QueryArgs& a, int64_t leaf, const float
 // leaves lie.  Round 1 then refines those leaves, which lowers the
 // best-so-far before round 2 bounds the rest.
 __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
-    __shared__ float lo_e[256], hi_e[256], paa[64];
+    __shared__ float lo_e[256], hi_e[256], pu[64], pl[64];
     __shared__ unsigned hist[kLeafBins];
     const int q = blockIdx.y;
     const int64_t leaf = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -401,12 +598,15 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
         lo_e[s] = a.edges[(int64_t)q * 2 * a.ns + s];
         hi_e[s] = a.edges[(int64_t)q * 2 * a.ns + a.ns + s];
     }
-    if (threadIdx.x < a.w) paa[threadIdx.x] = a.paa[(int64_t)q * a.w + threadIdx.x];
+    if (threadIdx.x < a.w) {
+        pu[threadIdx.x] = a.env_paa[(int64_t)q * 2 * a.w + threadIdx.x];
+        pl[threadIdx.x] = a.env_paa[(int64_t)q * 2 * a.w + a.w + threadIdx.x];
+    }
     if (threadIdx.x < kLeafBins) hist[threadIdx.x] = 0u;
     __syncthreads();
     const float thr = read_tau(a, q, a.kq[q]) * a.tau_scale;
     if (leaf < a.n_leaves && !(leaf >= h0 && leaf < h1)) {
-        const float lb = leaf_bound(a, leaf, paa, lo_e, hi_e);
+        const float lb = leaf_bound(a, leaf, pu, pl, lo_e, hi_e);
         if (lb * a.lb_scale <= thr) {
             // thr may be 0 (an exact duplicate) or +inf: keep the bin index in range
             const float f = thr > 0.f ? lb / thr * (float)kLeafBins : 0.f;
@@ -442,38 +642,51 @@ __global__ void k_leaf_theta(QueryArgs a) {
 //  2. for every surviving leaf, one wave computes the lower bound of each
 //     series from its word with the per-segment LDS table (ParIS / MESSI
 //     lower-bound calculation on the iSAX summaries);
-//  3. each surviving series is refined by 16 lanes with early abandoning,
-//     and results within the slack of the current BSF are emitted (candidate
-//     list + best-so-far update).
+//  3. ED (RB = 0): each surviving series is refined by 16 lanes with early
+//     abandoning, and results within the slack of the current BSF are
+//     emitted (candidate list + best-so-far update).
+//     DTW (RB = band registers): 16 lanes compute LB_Keogh with early
+//     abandoning; the survivors queue up per wave and, 64 at a time, get the
+//     FP32 DTW recurrence, one series per lane, with early abandoning.
+// With all_leaves (the plain scan under DTW) steps 1 and 2 keep everything.
 struct ScanSmem {
-    int off_lo, off_hi, off_paa, off_q, off_T, off_list, off_wl, total;
+    int off_lo, off_hi, off_paa, off_q, off_env, off_T, off_list, off_wl, off_dq, total;
 };
-// The series-bound table sits in LDS when it is at most 32 KB, else it is read
-// from global memory (L2-resident: one table per query).
+// The series-bound table sits in LDS when it is at most 32 KB and the whole
+// plan fits in 64 KB, else it is read from global memory (L2-resident: one
+// table per query).
 constexpr int kTableLdsMax = 32 * 1024;
-__host__ __device__ inline ScanSmem scan_smem(int ns, int w, int len) {
+constexpr int kDtwQueue = 128;  // per-wave queue of series waiting for DTW
+__host__ __device__ inline ScanSmem scan_smem(int ns, int w, int len, bool dtw, bool table_in_lds) {
     ScanSmem s;
     int o = 0;
     s.off_lo = o; o += ns * 4;
     s.off_hi = o; o += ns * 4;
-    s.off_paa = o; o += 64 * 4;
-    s.off_q = o; o += ((len + 3) / 4) * 16;
-    s.off_T = o; o += (w * ns * 4 <= kTableLdsMax) ? w * ns * 4 : 0;
+    s.off_paa = o; o += 128 * 4;
+    s.off_q = o; o += (dtw ? len + 2 * kDtwPad : (len + 3) / 4 * 4) * 4;
+    o = (o + 15) / 16 * 16;
+    s.off_env = o; o += dtw ? 2 * ((len + 3) / 4 * 4) * 4 : 0;
+    s.off_T = o; o += table_in_lds ? w * ns * 4 : 0;
     s.off_list = o; o += 257 * 4;
     o = (o + 15) / 16 * 16;
     s.off_wl = o; o += 4 * 64 * 4;
+    s.off_dq = o; o += dtw ? 4 * kDtwQueue * 4 : 0;
     s.total = o;
     return s;
 }
 
-template <bool VEC, bool T_LDS>
+template <bool VEC, bool T_LDS, int RB>
 __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
+    constexpr bool DTW = RB > 0;
     extern __shared__ unsigned char smem[];
-    const ScanSmem L = scan_smem(a.ns, a.w, a.len);
+    const ScanSmem L = scan_smem(a.ns, a.w, a.len, DTW, T_LDS);
     float* lo_e = reinterpret_cast<float*>(smem + L.off_lo);
     float* hi_e = reinterpret_cast<float*>(smem + L.off_hi);
-    float* paa = reinterpret_cast<float*>(smem + L.off_paa);
-    float* qrow = reinterpret_cast<float*>(smem + L.off_q);
+    float* pu = reinterpret_cast<float*>(smem + L.off_paa);
+    float* pl = pu + 64;
+    float* qrow = reinterpret_cast<float*>(smem + L.off_q);  // DTW: padded query
+    float* envU = reinterpret_cast<float*>(smem + L.off_env);
+    float* envL = envU + (a.len + 3) / 4 * 4;
     const float* T = T_LDS ? reinterpret_cast<const float*>(smem + L.off_T) : a.T + (int64_t)blockIdx.y * a.w * a.ns;
     int* list = reinterpret_cast<int*>(smem + L.off_list);
     int* wl = reinterpret_cast<int*>(smem + L.off_wl);
@@ -491,7 +704,10 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
         lo_e[s] = a.edges[(int64_t)q * 2 * a.ns + s];
         hi_e[s] = a.edges[(int64_t)q * 2 * a.ns + a.ns + s];
     }
-    if (threadIdx.x < a.w) paa[threadIdx.x] = a.paa[(int64_t)q * a.w + threadIdx.x];
+    if (threadIdx.x < a.w) {
+        pu[threadIdx.x] = a.env_paa[(int64_t)q * 2 * a.w + threadIdx.x];
+        pl[threadIdx.x] = a.env_paa[(int64_t)q * 2 * a.w + a.w + threadIdx.x];
+    }
     if (threadIdx.x < ST_N) s_st[threadIdx.x] = 0ull;
     if (threadIdx.x == 0) s_nk = 0;
     __syncthreads();
@@ -500,10 +716,14 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
     const bool valid_leaf = leaf < a.n_leaves && !(leaf >= h0 && leaf < h1);
     bool keep = false;
     if (valid_leaf) {
-        const float lb = leaf_bound(a, leaf, paa, lo_e, hi_e);
-        keep = lb * a.lb_scale <= thr;
-        if (a.round == 1) keep = keep && lb < a.theta[q];
-        if (a.round == 2) keep = keep && !(lb < a.theta[q]);
+        if (DTW && a.all_leaves) {
+            keep = true;
+        } else {
+            const float lb = leaf_bound(a, leaf, pu, pl, lo_e, hi_e);
+            keep = lb * a.lb_scale <= thr;
+            if (a.round == 1) keep = keep && lb < a.theta[q];
+            if (a.round == 2) keep = keep && !(lb < a.theta[q]);
+        }
     }
     {
         const unsigned long long vm = __ballot(valid_leaf), km = __ballot(keep);
@@ -524,12 +744,41 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
             float* Tw = reinterpret_cast<float*>(smem + L.off_T);
             for (int i = threadIdx.x; i < a.w * a.ns; i += 256) Tw[i] = a.T[(int64_t)q * a.w * a.ns + i];
         }
-        for (int t = threadIdx.x; t < a.len; t += 256) qrow[t] = a.Q[(int64_t)q * a.len + t];
+        if constexpr (DTW) {
+            load_qpad(qrow, a.Q + (int64_t)q * a.len, a.len);
+            const float* ge = a.qenv + (int64_t)q * 2 * a.len;
+            for (int t = threadIdx.x; t < a.len; t += 256) {
+                envU[t] = ge[t];
+                envL[t] = ge[a.len + t];
+            }
+        } else {
+            for (int t = threadIdx.x; t < a.len; t += 256) qrow[t] = a.Q[(int64_t)q * a.len + t];
+        }
         __syncthreads();
         const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
         const bool abandon = !(a.flags & ISAX_QF_NO_EARLY_ABANDON);
-        unsigned long long n_lb = 0, n_ref = 0, n_bytes = 0, n_emit = 0;
+        const bool series_lb = !(DTW && a.all_leaves);
+        unsigned long long n_lb = 0, n_ref = 0, n_bytes = 0, n_emit = 0, n_dtw = 0, n_cells = 0;
         int* my_wl = wl + wave * 64;
+        int* dq = reinterpret_cast<int*>(smem + L.off_dq) + wave * kDtwQueue;
+        int dn = 0;  // queued series of this wave (the same in every lane)
+        // DTW of the first cnt queued series, one per lane
+        auto dtw_batch = [&](int cnt) {
+            thr = read_tau(a, q, k) * a.tau_scale;
+            if (lane < cnt) {
+                const int32_t id = dq[lane];
+                int cols = 0;
+                const float d2 = dtw_lane<DTW ? RB : 8, VEC>(qrow, a.data + (int64_t)id * a.len, a.len, a.window,
+                                                             thr, abandon, cols);
+                ++n_dtw;
+                n_cells += (unsigned long long)cols * (2 * a.window + 1);
+                if (d2 <= thr) {
+                    emit(a, q, k, d2, id);
+                    ++n_emit;
+                }
+            }
+            thr = read_tau(a, q, k) * a.tau_scale;
+        };
         for (int li = wave; li < nk; li += 4) {
             const int64_t lf = list[li];
             const int64_t pa = lf * a.leaf_size, pb = min(a.n, pa + a.leaf_size);
@@ -538,7 +787,7 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                 const int64_t pos = base + lane;
                 const bool v = pos < pb;
                 float lb = 0.f;
-                if (v) {
+                if (v && series_lb) {
                     const uint4* wp = reinterpret_cast<const uint4*>(a.words_sorted + pos * a.ws);
                     for (int qc = 0; qc < a.ws / 16; ++qc) {
                         const uint4 vw = wp[qc];
@@ -552,7 +801,7 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                 }
                 const bool pass = v && lb * a.lb_scale <= thr;
                 const unsigned long long pm = __ballot(pass);
-                n_lb += (unsigned long long)__popcll(__ballot(v));
+                if (series_lb) n_lb += (unsigned long long)__popcll(__ballot(v));
                 if (pm == 0ull) continue;
                 if (pass) my_wl[__popcll(pm & lt)] = (int)(pos - pa);
                 __builtin_amdgcn_wave_barrier();
@@ -560,30 +809,67 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                 const int g = lane >> 4, gl = lane & 15;
                 for (int ci = 0; ci < nc; ci += 4) {
                     const int my = ci + g;
-                    if (my < nc) {
-                        const int64_t p2 = pa + my_wl[my];
-                        const int32_t id = a.ids_sorted[p2];
-                        const float* row = a.data + (int64_t)id * a.len;
-                        int steps = 0;
-                        const float d2 = refine16<VEC>(row, qrow, a.len, gl, thr, abandon, steps);
-                        if (gl == 0) {
-                            ++n_ref;
-                            n_bytes += (unsigned long long)min(a.len, steps * 64) * 4ull;
-                            if (d2 <= thr) {
-                                emit(a, q, k, d2, id);
-                                ++n_emit;
+                    if constexpr (DTW) {
+                        bool surv = false;
+                        int32_t id = 0;
+                        if (my < nc) {
+                            id = a.ids_sorted[pa + my_wl[my]];
+                            int steps = 0;
+                            const float lk = lbk16<VEC>(a.data + (int64_t)id * a.len, envU, envL, a.len, gl, thr,
+                                                        abandon, steps);
+                            surv = lk * a.lbk_scale <= thr;
+                            if (gl == 0) {
+                                ++n_ref;
+                                n_bytes += (unsigned long long)min(a.len, steps * 64) * 4ull;
                             }
                         }
+                        const unsigned long long sm = __ballot(surv && gl == 0);
+                        if (surv && gl == 0) dq[dn + __popcll(sm & lt)] = id;
+                        dn += __popcll(sm);
+                        __builtin_amdgcn_wave_barrier();
+                        if (dn >= 64) {
+                            dtw_batch(64);
+                            __builtin_amdgcn_wave_barrier();
+                            const int rest = dn - 64;
+                            const int moved = lane < rest ? dq[64 + lane] : 0;
+                            __builtin_amdgcn_wave_barrier();
+                            if (lane < rest) dq[lane] = moved;
+                            __builtin_amdgcn_wave_barrier();
+                            dn = rest;
+                        }
+                    } else {
+                        if (my < nc) {
+                            const int64_t p2 = pa + my_wl[my];
+                            const int32_t id = a.ids_sorted[p2];
+                            const float* row = a.data + (int64_t)id * a.len;
+                            int steps = 0;
+                            const float d2 = refine16<VEC>(row, qrow, a.len, gl, thr, abandon, steps);
+                            if (gl == 0) {
+                                ++n_ref;
+                                n_bytes += (unsigned long long)min(a.len, steps * 64) * 4ull;
+                                if (d2 <= thr) {
+                                    emit(a, q, k, d2, id);
+                                    ++n_emit;
+                                }
+                            }
+                        }
+                        thr = read_tau(a, q, k) * a.tau_scale;
                     }
-                    thr = read_tau(a, q, k) * a.tau_scale;
                 }
                 __builtin_amdgcn_wave_barrier();
             }
         }
+        if (DTW && dn > 0) dtw_batch(dn);
         atomicAdd(&s_st[ST_SERIES_LB], lane == 0 ? n_lb : 0ull);
         if ((lane & 15) == 0) {
             atomicAdd(&s_st[ST_REFINED], n_ref);
             atomicAdd(&s_st[ST_REFINE_BYTES], n_bytes);
+        }
+        if (DTW) {
+            atomicAdd(&s_st[ST_CANDS], n_emit);
+            atomicAdd(&s_st[ST_DTW], n_dtw);
+            atomicAdd(&s_st[ST_DTW_CELLS], n_cells);
+        } else if ((lane & 15) == 0) {
             atomicAdd(&s_st[ST_CANDS], n_emit);
         }
     }
@@ -769,18 +1055,26 @@ __global__ void __launch_bounds__(256) k_topk(QueryArgs a) {
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float* qrow = a.Q + (int64_t)q * a.len;
+    const bool dtw = a.metric == ISAX_METRIC_DTW;
+    double* hd = reinterpret_cast<double*>(hl);  // DTW: the FP64 value in the same 8 bytes
     for (int i = wave; i < W; i += 4) {
         const int32_t id = key_id(wkeys[i]);
-        const float2 r = dist2_dot2(qrow, a.data + (int64_t)id * a.len, a.len, lane);
-        if (lane == 0) hl[i] = r;
+        if (dtw) {
+            const double v = dtw_exact_wave(qrow, a.data + (int64_t)id * a.len, a.len, a.window, lane);
+            if (lane == 0) hd[i] = v;
+        } else {
+            const float2 r = dist2_dot2(qrow, a.data + (int64_t)id * a.len, a.len, lane);
+            if (lane == 0) hl[i] = r;
+        }
     }
     int PW = 1;
     while (PW < W) PW <<= 1;
     for (int i = W + threadIdx.x; i < PW; i += 256) {
         wkeys[i] = kEmpty;
-        hl[i] = make_float2(kInf, kInf);
+        if (dtw) hd[i] = __builtin_huge_val();
+        else hl[i] = make_float2(kInf, kInf);
     }
-    // bitonic sort of the window by (hi, lo, id)
+    // bitonic sort of the window by (hi, lo, id), under DTW by (FP64 value, id)
     for (int size = 2; size <= PW; size <<= 1)
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             __syncthreads();
@@ -790,7 +1084,13 @@ __global__ void __launch_bounds__(256) k_topk(QueryArgs a) {
                 const bool up = (lo & size) == 0;
                 const float2 x = hl[lo], y = hl[hi];
                 const unsigned ix = (unsigned)(wkeys[lo] & 0xffffffffu), iy = (unsigned)(wkeys[hi] & 0xffffffffu);
-                const bool gt = x.x > y.x || (x.x == y.x && (x.y > y.y || (x.y == y.y && ix > iy)));
+                bool gt;
+                if (dtw) {
+                    const double dx = hd[lo], dy = hd[hi];
+                    gt = dx > dy || (dx == dy && ix > iy);
+                } else {
+                    gt = x.x > y.x || (x.x == y.x && (x.y > y.y || (x.y == y.y && ix > iy)));
+                }
                 if (gt == up) {
                     hl[lo] = y;
                     hl[hi] = x;
@@ -805,7 +1105,7 @@ __global__ void __launch_bounds__(256) k_topk(QueryArgs a) {
         const int64_t o = (int64_t)q * a.kmax + i;
         if (i < k) {
             a.out_ids[o] = (int64_t)key_id(wkeys[i]);
-            a.out_dists[o] = sqrtf(fmaxf(hl[i].x, 0.f));
+            a.out_dists[o] = dtw ? (float)sqrt(hd[i]) : sqrtf(fmaxf(hl[i].x, 0.f));
         } else {
             a.out_ids[o] = -1;
             a.out_dists[o] = kInf;
@@ -854,14 +1154,30 @@ void launch_check_finite(const float* x, int64_t count, int* flag, hipStream_t s
 
 void launch_qprep(const QueryArgs& a, hipStream_t s) {
     ProfScope ps("qprep", s);
-    k_qprep<<<a.mq, 64, 0, s>>>(a);
+    const size_t lds = a.metric == ISAX_METRIC_DTW ? (size_t)a.len * 2 * sizeof(float) : 0;
+    k_qprep<<<a.mq, 64, lds, s>>>(a);
     ISAX_HIP(hipGetLastError());
+}
+
+// Band cells held in registers for a DTW band of half-width r.
+int dtw_band_regs(int r) {
+    const int B = 2 * r + 1;
+    return B <= 8 ? 8 : B <= 16 ? 16 : B <= 32 ? 32 : 64;
 }
 
 void launch_homeleaf(const QueryArgs& a, hipStream_t s) {
     ProfScope ps("homeleaf", s);
-    const size_t lds = kHomeMax * sizeof(unsigned long long) + (size_t)a.len * 4;
-    k_homeleaf<<<a.mq, 256, lds, s>>>(a);
+    const size_t lds = kHomeMax * sizeof(unsigned long long) + (size_t)(a.len + 2 * kDtwPad) * 4;
+    if (a.metric != ISAX_METRIC_DTW) {
+        k_homeleaf<0><<<a.mq, 256, lds, s>>>(a);
+    } else {
+        switch (dtw_band_regs(a.window)) {
+            case 8: k_homeleaf<8><<<a.mq, 256, lds, s>>>(a); break;
+            case 16: k_homeleaf<16><<<a.mq, 256, lds, s>>>(a); break;
+            case 32: k_homeleaf<32><<<a.mq, 256, lds, s>>>(a); break;
+            default: k_homeleaf<64><<<a.mq, 256, lds, s>>>(a); break;
+        }
+    }
     ISAX_HIP(hipGetLastError());
 }
 
@@ -874,16 +1190,33 @@ void launch_leaf_order(const QueryArgs& a, hipStream_t s) {
     ISAX_HIP(hipGetLastError());
 }
 
+template <bool VEC, bool TL>
+void launch_index_scan_t(const QueryArgs& a, const dim3& grid, hipStream_t s) {
+    if (a.metric != ISAX_METRIC_DTW) {
+        const ScanSmem L = scan_smem(a.ns, a.w, a.len, false, TL);
+        k_index_scan<VEC, TL, 0><<<grid, 256, L.total, s>>>(a);
+        return;
+    }
+    const ScanSmem L = scan_smem(a.ns, a.w, a.len, true, TL);
+    switch (dtw_band_regs(a.window)) {
+        case 8: k_index_scan<VEC, TL, 8><<<grid, 256, L.total, s>>>(a); break;
+        case 16: k_index_scan<VEC, TL, 16><<<grid, 256, L.total, s>>>(a); break;
+        case 32: k_index_scan<VEC, TL, 32><<<grid, 256, L.total, s>>>(a); break;
+        default: k_index_scan<VEC, TL, 64><<<grid, 256, L.total, s>>>(a); break;
+    }
+}
+
 void launch_index_scan(const QueryArgs& a, hipStream_t s) {
-    ProfScope ps("index_scan", s);
-    const ScanSmem L = scan_smem(a.ns, a.w, a.len);
+    ProfScope ps(a.metric == ISAX_METRIC_DTW ? "dtw_scan" : "index_scan", s);
+    const bool dtw = a.metric == ISAX_METRIC_DTW;
     const dim3 grid((unsigned)((a.n_leaves + 255) / 256), (unsigned)a.mq);
     const bool vec = a.len % 4 == 0 && (reinterpret_cast<uintptr_t>(a.data) & 15) == 0;
-    const bool tl = a.w * a.ns * 4 <= kTableLdsMax;
-    if (vec && tl) k_index_scan<true, true><<<grid, 256, L.total, s>>>(a);
-    else if (vec) k_index_scan<true, false><<<grid, 256, L.total, s>>>(a);
-    else if (tl) k_index_scan<false, true><<<grid, 256, L.total, s>>>(a);
-    else k_index_scan<false, false><<<grid, 256, L.total, s>>>(a);
+    const bool tl = a.w * a.ns * 4 <= kTableLdsMax && scan_smem(a.ns, a.w, a.len, dtw, true).total <= 64 * 1024;
+    ISAX_REQUIRE(scan_smem(a.ns, a.w, a.len, dtw, tl).total <= 64 * 1024, "series too long for the scan's LDS plan");
+    if (vec && tl) launch_index_scan_t<true, true>(a, grid, s);
+    else if (vec) launch_index_scan_t<true, false>(a, grid, s);
+    else if (tl) launch_index_scan_t<false, true>(a, grid, s);
+    else launch_index_scan_t<false, false>(a, grid, s);
     ISAX_HIP(hipGetLastError());
 }
 

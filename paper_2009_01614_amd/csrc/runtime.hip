@@ -273,8 +273,20 @@ struct Batch {
     int fcap0 = 0;  // initial filter-candidate capacity (0: default)
 };
 
+// Slack of comparisons with a DTW best-so-far: the FP32 recurrence sums at
+// most 2 len - 1 cells of 3 roundings each along its path, so a value is
+// within (2 len + 3) 2^-24 relative of the exact one; the ratio of two such
+// values stays below 1 + 8 len 2^-24 (power of two, at least 2^-13).
+float dtw_tau_eps(int len) {
+    double e = 8.0 * len * std::ldexp(1.0, -24);
+    double p = std::ldexp(1.0, -13);
+    while (p < e) p *= 2;
+    return (float)p;
+}
+
 void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const int32_t* kq_dev, int kmax, int cap,
-                 int flags, int64_t* out_ids, float* out_dists, hipStream_t s) {
+                 int flags, int64_t* out_ids, float* out_dists, hipStream_t s, int metric = ISAX_METRIC_ED,
+                 int window = 0) {
     QueryArgs& a = b.a;
     std::memset(&a, 0, sizeof(a));
     a.data = idx->data;
@@ -305,6 +317,13 @@ void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const 
     a.rerun = 0;
     a.out_ids = out_ids;
     a.out_dists = out_dists;
+    a.metric = metric;
+    a.window = window;
+    if (metric == ISAX_METRIC_DTW) {
+        // LB_Keogh: FP32 sums of at most len / 16 + 4 terms per lane, then 4 adds
+        a.tau_scale = 1.0f + dtw_tau_eps(idx->len);
+        a.lbk_scale = 1.0f - dtw_tau_eps(idx->len);
+    }
     Arena ar;
     ar.add(&a.paa, (size_t)mq * idx->w);
     ar.add(&a.sym, (size_t)mq * idx->ws);
@@ -322,6 +341,8 @@ void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const 
     ar.add(&a.status, mq);
     ar.add(&a.theta, mq);
     ar.add(&a.leaf_hist, (size_t)mq * kLeafBins);
+    ar.add(&a.env_paa, (size_t)mq * 2 * idx->w);
+    if (metric == ISAX_METRIC_DTW) ar.add(&a.qenv, (size_t)mq * 2 * idx->len);
     b.mem = ar.commit(s);
 }
 
@@ -344,6 +365,8 @@ void fill_stats(const Batch& b, isax_query_stats* out, hipStream_t s) {
         out[i].candidates = (int64_t)r[ST_CANDS];
         out[i].tau_initial = qi[i].w;
         out[i].tau_final = qi[i].y;
+        out[i].dtw_series = (int64_t)r[ST_DTW];
+        out[i].dtw_cells = (int64_t)r[ST_DTW_CELLS];
     }
 }
 
@@ -367,7 +390,14 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s);  // d
 void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     QueryArgs& a = b.a;
     launch_qprep(a, s);
-    if (mode == ISAX_MODE_INDEX) {
+    const bool dtw = a.metric == ISAX_METRIC_DTW;
+    if (dtw && mode == ISAX_MODE_SCAN) {
+        // the plain scan under DTW: the home leaves seed the bound, then every
+        // series gets LB_Keogh and the early-abandoning recurrence
+        a.all_leaves = 1;
+        launch_homeleaf(a, s);
+        launch_index_scan(a, s);
+    } else if (mode == ISAX_MODE_INDEX) {
         launch_homeleaf(a, s);
         if (a.flags & ISAX_QF_NO_BEST_FIRST) {
             a.round = 0;
@@ -379,7 +409,7 @@ void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
             a.round = 2;
             launch_index_scan(a, s);
         }
-        if (profiling_on()) profile_add_bytes("index_scan", scan_bytes(b, idx, s));
+        if (profiling_on()) profile_add_bytes(dtw ? "dtw_scan" : "index_scan", scan_bytes(b, idx, s));
     } else if (mode == ISAX_MODE_SCAN) {
         launch_seed(a, s);
         launch_brute_scan(a, s);
@@ -403,7 +433,7 @@ void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
         if (round >= 8) throw Error{ISAX_EOVERFLOW, "candidate list overflowed on 8 re-runs"};
         a.rerun = 1;
         launch_rerun_reset(a, s);
-        if (mode == ISAX_MODE_INDEX) {
+        if (mode == ISAX_MODE_INDEX || dtw) {
             launch_homeleaf(a, s);
             a.round = 0;  // the bound is frozen: one pass over every leaf
             launch_index_scan(a, s);
@@ -429,6 +459,16 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
                  "unknown flag");
     ISAX_REQUIRE(o.mode != ISAX_MODE_BF16 || idx->x_bf16, "index was built without the BF16 copy");
     ISAX_REQUIRE(o.mode != ISAX_MODE_FP8 || idx->x_fp8, "index was built without the FP8 copy");
+    ISAX_REQUIRE(o.metric == ISAX_METRIC_ED || o.metric == ISAX_METRIC_DTW, "unknown metric");
+    if (o.metric == ISAX_METRIC_ED) {
+        ISAX_REQUIRE(o.window == 0, "window must be 0 for the Euclidean metric");
+    } else {
+        ISAX_REQUIRE(o.mode == ISAX_MODE_INDEX || o.mode == ISAX_MODE_SCAN,
+                     "DTW runs in ISAX_MODE_INDEX or ISAX_MODE_SCAN");
+        ISAX_REQUIRE(o.window >= 0 && o.window <= ISAX_MAX_WINDOW && o.window < idx->len,
+                     "window must be in 0..min(ISAX_MAX_WINDOW, len - 1)");
+        ISAX_REQUIRE(idx->len <= kDtwMaxLen, "DTW takes series of at most 2048 points");
+    }
     if (m == 0) return ISAX_OK;
     ISAX_REQUIRE(Q && out_ids && out_dists, "queries and outputs must not be NULL");
     ISAX_REQUIRE((reinterpret_cast<uintptr_t>(Q) & 3) == 0, "queries must be 4-byte aligned");
@@ -470,7 +510,8 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     for (int64_t q0 = 0; q0 < m; q0 += B) {
         const int mq = (int)std::min<int64_t>(B, m - q0);
         Batch b;
-        setup_batch(b, idx, Q + q0 * idx->len, mq, kq + q0, k, cap, o.flags, out_ids + q0 * k, out_dists + q0 * k, s);
+        setup_batch(b, idx, Q + q0 * idx->len, mq, kq + q0, k, cap, o.flags, out_ids + q0 * k, out_dists + q0 * k, s,
+                    o.metric, o.window);
         b.fcap0 = o.candidate_capacity;
         run_batch(idx, b, o.mode, s);
         if (o.stats) fill_stats(b, o.stats + q0, s);
@@ -618,7 +659,7 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
 int64_t isax::query_scratch_bytes(const isax_index* idx, int mq, int kmax, int mode) {
     const int64_t per_q = idx->w * 4 + idx->ws + 8 + 16 + 2 * idx->ns * 4 + (int64_t)idx->w * idx->ns * 4 + 4 +
                           (int64_t)kmax * 8 + (int64_t)kDefaultCap * 8 + 4 + 16 + ST_N * 8 + 8 + 4 + 4 +
-                          kLeafBins * 4;
+                          kLeafBins * 4 + 2 * idx->w * 4;
     int64_t tot = per_q * mq + 16 * 256;
     if (mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8) {
         const int qpb = filter_queries_per_block(idx->len);

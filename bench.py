@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--sweep-mode", default="bf16", choices=["index", "scan", "bf16", "fp8"])
     ap.add_argument("--precision-report", action="store_true",
                     help="instead of the headline: 10M x 256, batches of 1024, modes and filter error vs FP64")
+    ap.add_argument("--next-report", action="store_true",
+                    help="instead of the headline: DTW on the index, raw data in pinned host memory, embeddings")
+    ap.add_argument("--next-n", type=int, default=10_000_000, help="collection size of the next-rows report")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many bytes (3 times) to scale HBM counters")
     args = ap.parse_args()
@@ -70,6 +73,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.serving_sweep:
         return serving_sweep(args, dev)
+    if args.next_report:
+        return next_report(args, dev)
     if args.precision_report:
         return precision_report(args, dev)
     n, L, m, k = args.n, args.len, args.m, args.k
@@ -397,6 +402,126 @@ def precision_report(args, dev):
                                  "mean_abs_err": float(err.mean()),
                                  "kept_fraction_at_final_bound_k1": float(((ap - mg) <= tau).mean())}
         log(f"{mode}: {out[f'filter_{mode}']}")
+    print(json.dumps(out), flush=True)
+
+
+# ALU bound of the DTW recurrence: a band cell takes at least 3 VALU lane operations
+# (subtract, three-way minimum, fused multiply-add); 256 CUs x 64 FP32 lanes per
+# clock (no packed FP32) x 2.4 GHz = 39.3 T lane operations/s.
+PEAK_VALU_OPS = 256 * 64 * 2.4e9
+DTW_OPS_PER_CELL = 3
+
+
+def _timed_query(isax, idx, Q, **kw):
+    import torch
+    isax.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = idx.query(Q, **kw)
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0, isax.profile_read()
+
+
+def next_report(args, dev):
+    """Next rows, each exact (answers compared across modes and with the oracle on a sample).
+
+    DTW: n x 256 random walks, Sakoe-Chiba half-width 25 (10 %), 100 noisy
+    queries, k = 1 and 10, index and plain-scan modes; DTW cells/s against the
+    ALU bound.  Host-resident raw data: the same collection in pinned host
+    memory (summaries, layout and the BF16 copy in HBM), 1000 queries, index and
+    BF16 modes.  Embeddings: n x 128 and n x 384 clustered vectors, 1000 queries.
+    """
+    import numpy as np
+    import torch
+
+    import paper_2009_01614_amd as isax
+    import workload
+    from oracle import knn_ref
+
+    n, L, r = args.next_n, 256, 25
+    out = {"metric": "exact k-NN queries/s, next rows", "config": {"n": n}, "dtw": {}, "host_resident": {},
+           "embeddings": {}}
+    isax.profile_enable(True)
+    log(f"generating {n} x {L}")
+    X = workload.random_walks(n, L, seed=20090165, device=dev)
+    Q100, _, _ = workload.noisy_queries(X, 100, seed=20091165)
+    idx = isax.Index(X, 16, 8, precision=1)
+    # ---- DTW
+    res = {}
+    for k in (1, 10):
+        for mode in ("index", "scan"):
+            idx.query(Q100[:8].contiguous(), k=k, mode=mode, metric="dtw", window=r)
+            (ids, d, st), dt, prof = _timed_query(isax, idx, Q100, k=k, mode=mode, metric="dtw", window=r, stats=True)
+            cells = sum(s_["dtw_cells"] for s_ in st)
+            kern_ms = prof.get("dtw_scan", {}).get("total_ms", 0.0) + prof.get("homeleaf", {}).get("total_ms", 0.0)
+            cps = cells / (kern_ms / 1e3) if kern_ms > 0 else 0.0
+            res[(k, mode)] = ids
+            out["dtw"][f"{mode}_k{k}"] = {
+                "qps": round(100 / dt, 2), "dtw_series_per_query": round(sum(s_["dtw_series"] for s_ in st) / 100),
+                "lb_keogh_per_query": round(sum(s_["series_refined"] for s_ in st) / 100),
+                "cells_per_s": cps, "alu_frac": cps * DTW_OPS_PER_CELL / PEAK_VALU_OPS}
+            log(f"dtw k={k} {mode}: {out['dtw'][f'{mode}_k{k}']}")
+        assert torch.equal(res[(k, "index")], res[(k, "scan")]), "DTW index and scan disagree"
+    log("DTW oracle on 1 query (all host threads)")
+    Xh = X.cpu().numpy()
+    t0 = time.perf_counter()
+    ref_ids, _ = knn_ref.knn_dtw_c(Xh, Q100[:1].cpu().numpy(), 10, r)
+    cpu_s = time.perf_counter() - t0
+    assert np.array_equal(res[(10, "index")][:1].cpu().numpy(), ref_ids), "DTW differs from the oracle"
+    out["dtw"]["config"] = {"workload": f"{n} x {L} random walks, window {r}, 100 noisy queries"}
+    out["dtw"]["roofline"] = {"bound": "alu", "peak_cells_per_s": PEAK_VALU_OPS / DTW_OPS_PER_CELL,
+                              "ops_per_cell": DTW_OPS_PER_CELL}
+    out["dtw"]["cpu_baseline"] = {"value": round(1 / cpu_s, 4), "unit": "queries/s", "cores": knn_ref.num_threads(),
+                                  "kind": "oracle", "sample": "1 query against the whole collection, k = 10"}
+    # ---- raw data in pinned host memory
+    Q = workload.noisy_queries(X, 1000, seed=20091166)[0]
+    dev_ids = {}
+    for mode in ("index", "bf16"):
+        idx.query(Q[:64].contiguous(), k=1, mode=mode)
+        (ids, _), dt, _ = _timed_query(isax, idx, Q, k=1, mode=mode)
+        dev_ids[mode] = ids
+        out["host_resident"][f"device_{mode}_qps"] = round(1000 / dt, 1)
+    idx.close()
+    Xp = torch.empty(X.shape, dtype=torch.float32, pin_memory=True)
+    Xp.copy_(X)
+    del X
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    idx_h = isax.Index(Xp, 16, 8, precision=1)
+    torch.cuda.synchronize()
+    out["host_resident"]["build_s"] = round(time.perf_counter() - t0, 3)
+    for mode in ("index", "bf16"):
+        idx_h.query(Q[:64].contiguous(), k=1, mode=mode)
+        (ids, _), dt, _ = _timed_query(isax, idx_h, Q, k=1, mode=mode)
+        assert torch.equal(ids, dev_ids[mode]), f"host-resident {mode} differs"
+        out["host_resident"][f"host_{mode}_qps"] = round(1000 / dt, 1)
+        log(f"host-resident {mode}: {out['host_resident'][f'host_{mode}_qps']} q/s")
+    out["host_resident"]["device_bytes"] = idx_h.info()["device_bytes"]
+    idx_h.close()
+    del Xp
+    # ---- embeddings
+    for dim in (128, 384):
+        g = torch.Generator(device=dev).manual_seed(dim)
+        centres = torch.randn(1000, dim, device=dev, generator=g) * 3.0
+        E = torch.empty((n, dim), dtype=torch.float32, device=dev)
+        for c0 in range(0, n, 1 << 22):
+            c1 = min(n, c0 + (1 << 22))
+            lab = torch.randint(0, 1000, (c1 - c0,), device=dev, generator=g)
+            E[c0:c1] = centres[lab] + torch.randn(c1 - c0, dim, device=dev, generator=g) * 0.7
+        QE = (centres[torch.randint(0, 1000, (1000,), device=dev, generator=g)] +
+              torch.randn(1000, dim, device=dev, generator=g) * 0.7).contiguous()
+        ie = isax.Index(E, 16, 8, precision=1)
+        ref = None
+        for mode in ("bf16", "index", "scan"):
+            ie.query(QE[:64].contiguous(), k=10, mode=mode)
+            (ids, _), dt, _ = _timed_query(isax, ie, QE, k=10, mode=mode)
+            ref = ids if ref is None else ref
+            assert torch.equal(ids, ref), f"embeddings {mode} disagrees"
+            out["embeddings"][f"d{dim}_{mode}_k10_qps"] = round(1000 / dt, 1)
+            log(f"embeddings d={dim} {mode}: {out['embeddings'][f'd{dim}_{mode}_k10_qps']} q/s")
+        ie.close()
+        del E
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

@@ -137,9 +137,11 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
-    if not (t.is_cuda and t.dtype == torch.float32 and t.dim() == 2 and t.is_contiguous()):
-        raise ValueError(f"{name} must be a contiguous 2-D float32 CUDA tensor")
+def _dev_f32(t: torch.Tensor, name: str, allow_pinned: bool = False) -> torch.Tensor:
+    where = t.is_cuda or (allow_pinned and t.is_pinned())
+    if not (where and t.dtype == torch.float32 and t.dim() == 2 and t.is_contiguous()):
+        kind = "CUDA or pinned host" if allow_pinned else "CUDA"
+        raise ValueError(f"{name} must be a contiguous 2-D float32 {kind} tensor")
     return t
 
 
@@ -182,11 +184,15 @@ def profile_read() -> dict:
 
 # ----------------------------------------------------------------------------- index
 class Index:
-    """An iSAX index over a resident FP32 collection (the tensor is borrowed, keep it alive)."""
+    """An iSAX index over a resident FP32 collection (the tensor is borrowed, keep it alive).
+
+    The collection may sit in device memory or in pinned host memory (read over
+    the bus; the summaries, the layout and any reduced-precision copy are in HBM).
+    """
 
     def __init__(self, data: torch.Tensor, segments: int = 16, card_bits: int = 8, leaf_size: int = 0,
                  key_bits: int = 0, precision: int = 0, stream=None):
-        _dev_f32(data, "data")
+        _dev_f32(data, "data", allow_pinned=True)
         self.data = data
         self.n, self.len = data.shape
         opt = BuildOptions(leaf_size, key_bits, precision, 0, _stream(stream))
@@ -218,7 +224,7 @@ class Index:
     def export(self):
         """(ids_sorted int32 [n], words_sorted uint8 [n, w], env_lo, env_hi uint8 [n_leaves, w]) on the device."""
         inf = self.info()
-        dev = self.data.device
+        dev = self.data.device if self.data.is_cuda else torch.device("cuda", torch.cuda.current_device())
         ids = torch.empty(self.n, dtype=torch.int32, device=dev)
         words = torch.empty((self.n, inf["segments"]), dtype=torch.uint8, device=dev)
         lo = torch.empty((inf["n_leaves"], inf["segments"]), dtype=torch.uint8, device=dev)

@@ -188,13 +188,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
             }
         }
     }
-    // per-row thresholds H = tau (1 + eps) - |q|^2 (refreshed periodically) and FP8 row scales
+    // per-row thresholds H = tau (1 + eps) - |q|^2 (refreshed periodically; BF16 keeps H / 2)
+    // and FP8 row scales
     auto refresh_H = [&]() {
         for (int i = threadIdx.x; i < C::QPB; i += C::THREADS) {
             const int q = qt * C::QPB + i;
             float H = -kInf;
             if (q < a.mq && !(a.rerun && a.done[q])) H = read_tau(a, q, a.kq[q]) * a.tau_scale - f.qmeta[q].x;
-            s_H[i] = H;
+            s_H[i] = KIND == 0 ? 0.5f * H : H;
         }
     };
     refresh_H();
@@ -330,6 +331,41 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
                         f.out_margin[(int64_t)q * a.n + id] = mx;
                     }
                 }
+        } else if constexpr (KIND == 0) {
+            // candidate iff fl(acc + H/2) >= G/2 (the test fma(-2, acc, G) <= H halved; near the
+            // threshold the sum is about G/2, so its one rounding is within the kappa slack).  A lane
+            // first takes the maximum over its 16 MT rows (one add and half a max3 per element);
+            // only lanes whose maximum passes look at the rows one by one.
+            const float Gh = 0.5f * G;
+            float best = -kInf;
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const float4 H4 = *reinterpret_cast<const float4*>(&s_H[wave * 32 * MT + 32 * t + 8 * g + 4 * h]);
+                    best = fmaxf(best, fmaxf(acc[t][4 * g] + H4.x, acc[t][4 * g + 1] + H4.y));
+                    best = fmaxf(best, fmaxf(acc[t][4 * g + 2] + H4.z, acc[t][4 * g + 3] + H4.w));
+                }
+            if (__ballot(best >= Gh)) {
+                unsigned hit = 0u;
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int row = 32 * t + 8 * (e >> 2) + 4 * h + (e & 3);
+                        hit |= (acc[t][e] + s_H[wave * 32 * MT + row] >= Gh ? 1u : 0u) << (16 * t + e);
+                    }
+                while (hit) {
+                    const int bit = __ffs(hit) - 1;
+                    hit &= hit - 1u;
+                    const int q = q_base + 32 * (bit >> 4) + 8 * ((bit & 15) >> 2) + 4 * h + (bit & 3);
+                    if (q >= a.mq || pos >= a.n) continue;
+                    const int64_t h0 = a.home[2 * q] * a.leaf_size, h1 = a.home[2 * q + 1] * a.leaf_size;
+                    if (pos >= h0 && pos < h1) continue;  // already refined by the approximate answer
+                    const unsigned slot = atomicAdd(f.fcount + q, 1u);
+                    if (slot < (unsigned)f.fcap) f.fcand[(int64_t)q * f.fcap + slot] = (unsigned)pos;
+                }
+            }
         } else {
             unsigned hit = 0u;
 #pragma unroll

@@ -34,6 +34,7 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr float kInf = __builtin_huge_valf();
 constexpr int kNT = 32;         // series per tile
+constexpr int kBAhead = 6;      // BF16 B fragments in flight ahead of their MFMAs
 
 __device__ inline unsigned long long make_key(float d2, int32_t id) {
     return ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned)id;
@@ -148,6 +149,17 @@ struct FilterCfg {
     static constexpr int QPB = WAVES * 32 * MT;                // queries per block
 };
 
+// Scheduling groups of the BF16 step loop: per step one LDS read (while any
+// are left) followed by the step's MT MFMAs.
+template <int PF, int MT, int S, int KS>
+__device__ inline void pin_schedule() {
+    if constexpr (S < KS) {
+        if constexpr (S + PF < KS) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, MT, 0);
+        pin_schedule<PF, MT, S + 1, KS>();
+    }
+}
+
 template <int KIND, int KS, int MT, int WAVES, bool INSPECT>
 __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f, int qtiles, int n_streams,
                                                         const unsigned* __restrict__ qmax) {
@@ -212,11 +224,13 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
         }
 
     // tiles of this phase, enumerated as virtual tiles v = 0 .. n_vt-1
-    const int64_t n_tiles = (a.n + kNT - 1) / kNT;
-    const int64_t n_sub = (n_tiles + f.sub - 1) / f.sub;
-    const int64_t n_vt = f.phase == 0 ? n_tiles : f.phase == 1 ? n_sub : n_tiles - n_sub;
-    auto tile_of = [&](int64_t v) -> int64_t {
-        return f.phase == 0 ? v : f.phase == 1 ? v * f.sub : v + v / (f.sub - 1) + 1;
+    // (n < 2^31, so tile numbers fit in 32 bits; kFilterSub is a constant, so the
+    // division below is a multiply)
+    const int n_tiles = (int)((a.n + kNT - 1) / kNT);
+    const int n_sub = (n_tiles + kFilterSub - 1) / kFilterSub;
+    const int n_vt = f.phase == 0 ? n_tiles : f.phase == 1 ? n_sub : n_tiles - n_sub;
+    auto tile_of = [&](int v) -> int64_t {
+        return f.phase == 0 ? v : f.phase == 1 ? v * kFilterSub : v + v / (kFilterSub - 1) + 1;
     };
     const unsigned char* X = static_cast<const unsigned char*>(f.xq);
     auto load_tile = [&](int64_t tl, i32x4* stage) {
@@ -244,7 +258,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
     };
 
     i32x4 stage[C::CPT];
-    int64_t v = stream;
+    int v = stream;
     // per-series metadata of the current tile, fetched one tile ahead
     auto load_meta = [&](int64_t tile) -> float4 {
         const int64_t p = tile * kNT + r;
@@ -274,19 +288,26 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
         const unsigned char* bsrc = &tile[buf][r * C::STRIDE + h * C::HALF];
-        // B fragments read two steps ahead of the MFMAs that use them
+        // B fragments read kBAhead steps ahead of the MFMAs that use them; the schedule is pinned
+        // (reads first, then per step MT MFMAs and the next read) so that the LDS latency stays
+        // hidden behind the matrix work instead of being waited for every second step
         if constexpr (KIND == 0) {
-            bf16x8 bq[3];
-            bq[0] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(bsrc));
-            if (KS > 1) bq[1] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(bsrc + 16));
+            constexpr int PF = KS < kBAhead ? KS : kBAhead;
+            bf16x8 bq[PF + 1];
+#pragma unroll
+            for (int s = 0; s < PF; ++s)
+                bq[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(bsrc + s * 16));
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
-                if (s + 2 < KS)
-                    bq[(s + 2) % 3] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(bsrc + (s + 2) * 16));
+                if (s + PF < KS)
+                    bq[(s + PF) % (PF + 1)] =
+                        __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(bsrc + (s + PF) * 16));
 #pragma unroll
                 for (int t = 0; t < MT; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[t][s], bq[s % 3], acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[t][s], bq[s % (PF + 1)], acc[t], 0, 0, 0);
             }
+            __builtin_amdgcn_sched_group_barrier(0x100, PF, 0);  // DS reads
+            pin_schedule<PF, MT, 0, KS>();
         } else {
             i32x8 bq[2];
             auto rd = [&](int s) {
@@ -513,14 +534,13 @@ void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qm
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (f.sub < 2) throw Error{ISAX_EINVAL, "internal: filter tile sampling factor must be >= 2"};
     const int qtiles = (a.mq + C::QPB - 1) / C::QPB;
     // the kernel reads query rows [0, qtiles * QPB): they must exist in the padded codes
     if ((int64_t)qtiles * C::QPB > f.mq_pad)
         throw Error{ISAX_EINVAL, "internal: query codes padded to fewer rows than the filter reads"};
     const int per_cu = WAVES >= 8 ? 1 : 4;
     int64_t n_tiles = (a.n + kNT - 1) / kNT;
-    const int64_t n_sub = (n_tiles + f.sub - 1) / f.sub;
+    const int64_t n_sub = (n_tiles + kFilterSub - 1) / kFilterSub;
     if (f.phase == 1) n_tiles = n_sub;
     if (f.phase == 2) n_tiles -= n_sub;
     // n_streams * qtiles blocks, n_streams a multiple of 8 (one group per XCD)

@@ -61,7 +61,10 @@ struct QueryArgs {
     float* env_paa;             // [mq][2][w] PAA of the upper then lower query envelope (ED: the query PAA twice)
     float* qenv;                // [mq][2][len] DTW: upper then lower envelope of the query
 };
-constexpr int kDtwMaxLen = 2048;  // longest series the DTW path takes (its LDS plan)
+constexpr int kDtwMaxLen = 2048;
+// The filter's first phase reads one tile in kFilterSub (an even sample of the
+// collection) whose candidates tighten the bound before the other tiles.
+constexpr int kFilterSub = 64;  // longest series the DTW path takes (its LDS plan)
 constexpr int kLeafBins = 64;
 constexpr int kFirstLeaves = 64;  // leaves refined first, by smallest lower bound
 
@@ -91,8 +94,7 @@ struct FilterArgs {
     int fcap;
     float* out_approx;        // optional [mq][n] (inspection)
     float* out_margin;        // optional [mq][n]
-    int phase;                // 0: every tile; 1: tiles t % sub == 0; 2: the other tiles
-    int sub;
+    int phase;                // 0: every tile; 1: tiles t % kFilterSub == 0; 2: the other tiles
 };
 int filter_len_pad(int len);              // rows of the reduced-precision copies are padded to this
 int filter_queries_per_block(int len);    // query codes are padded to a multiple of this

@@ -579,7 +579,6 @@ void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, 
     f.xmeta = f.kind == 0 ? idx->meta_bf16 : idx->meta_fp8;
     filter_constants(idx->len, &f.gamma, &f.kappa);
     f.phase = 0;
-    f.sub = 64;
     const int lp = filter_len_pad(idx->len);
     const int qpb = filter_queries_per_block(idx->len);
     fs.mq_pad = (a.mq + qpb - 1) / qpb * qpb;
@@ -604,7 +603,7 @@ void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, 
 // buffer grows to fit; in a first pass the stored candidates are refined first,
 // which tightens the bound (kept in tau0 while the per-query state restarts),
 // and the phases run again.
-constexpr int kSub = 64;  // equals FilterArgs::sub set in setup_filter
+constexpr int kSub = kFilterSub;
 
 void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     QueryArgs& a = b.a;

@@ -185,6 +185,126 @@ __device__ float dtw_lane(const float* qpad, const float* __restrict__ row, int 
     return res;
 }
 
+// DTW of the queued series dq[0..dn) by one wave, one series per lane, with
+// refill: a lane that finishes or abandons takes the next queued series, so
+// lanes do not idle while the longest series of a batch runs to the end.  The
+// grid is walked row by row here (i = query index), band cells D[d] =
+// D(i, i - r + d) and the matching series values xw[d] = x_{i-r+d} in
+// registers (+inf outside the series or the band); from row i-1 to i:
+//   D(i-1, j-1) = old D[d],  D(i-1, j) = old D[d+1],  D(i, j-1) = new D[d-1],
+// and the x window moves down one cell, x_{i+r+1} entering at cell 2r.
+// A lane abandons once a whole row exceeds the bound (every warping path
+// crosses every row).  Results within the bound are emitted.
+template <int RB, bool VEC>
+__device__ void dtw_drain(const QueryArgs& a, int q, int k, const float* qpad, const int* dq, int dn, bool abandon,
+                          int lane, unsigned long long lt, unsigned long long& n_dtw, unsigned long long& n_cells,
+                          unsigned long long& n_emit) {
+    const int r = a.window, B = 2 * r + 1, len = a.len;
+    float D[RB], xw[RB];
+#pragma unroll
+    for (int d = 0; d < RB; ++d) {
+        D[d] = kInf;
+        xw[d] = kInf;
+    }
+    int row = len;  // >= len: no series
+    int32_t id = 0;
+    const float* x = a.data;
+    int head = 0;
+    float thr = read_tau(a, q, k) * a.tau_scale;
+    float xn[4];  // series values entering the window in the next four rows, loaded a step ahead
+    auto load_xn = [&]() {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int jn = row + e + 1 + r;
+            xn[e] = jn < len ? x[jn] : kInf;
+        }
+    };
+    for (int it = 0;; ++it) {
+        const bool idle = row >= len;
+        const unsigned long long im = __ballot(idle);
+        const int avail = dn - head;
+        if (avail <= 0 && im == ~0ull) break;
+        if (idle) {
+            const int rank = __popcll(im & lt);
+            if (rank < avail) {
+                id = dq[head + rank];
+                x = a.data + (int64_t)id * len;
+                row = 0;
+#pragma unroll
+                for (int d = 0; d < RB; ++d) {
+                    const int j = d - r;
+                    D[d] = d == r ? 0.f : kInf;
+                    xw[d] = (d < B && j >= 0 && j < len) ? x[j] : kInf;
+                }
+                load_xn();
+                ++n_dtw;
+            }
+        }
+        if (avail > 0) head += min(avail, __popcll(im));
+        if ((it & 7) == 7) thr = read_tau(a, q, k) * a.tau_scale;
+        // the step runs in every lane (an idle lane computes on its stale state and discards it):
+        // no per-lane branch around it, so the band is not held twice
+        const bool active = row < len;
+        {
+            float qv[4];
+            if (VEC) {
+                const float4 q4 = *reinterpret_cast<const float4*>(qpad + kDtwPad + row);
+                qv[0] = q4.x;
+                qv[1] = q4.y;
+                qv[2] = q4.z;
+                qv[3] = q4.w;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) qv[e] = qpad[kDtwPad + row + e];
+            }
+            float xc[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xc[e] = xn[e];
+            row += 4;
+            load_xn();  // next step's values (+inf past the end), in flight during this step
+            row -= 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                // with len % 4 == 0 (VEC) every row of the step exists: no per-lane branch, so
+                // the band is not held twice across it
+                if (VEC || row + e < len) {
+                    float left = kInf;
+#pragma unroll
+                    for (int d = 0; d < RB; ++d) {
+                        const float df = qv[e] - xw[d];
+                        const float up = d + 1 < RB ? D[d + 1] : kInf;
+                        const float m = fminf(fminf(D[d], up), left);
+                        D[d] = fmaf(df, df, m);
+                        left = D[d];
+                    }
+#pragma unroll
+                    for (int d = 0; d < RB; ++d) xw[d] = d + 1 == B ? xc[e] : (d + 1 < RB ? xw[d + 1] : kInf);
+                }
+            }
+        }
+        if (active) {
+            const int done_rows = min(4, len - row);
+            n_cells += (unsigned long long)done_rows * B;
+            row += 4;
+            if (row >= len) {
+                float res = kInf;
+#pragma unroll
+                for (int d = 0; d < RB; ++d)
+                    if (d == r) res = D[d];
+                if (res <= thr) {
+                    emit(a, q, k, res, id);
+                    ++n_emit;
+                }
+            } else if (abandon) {
+                float mn = D[0];
+#pragma unroll
+                for (int d = 1; d < RB; ++d) mn = fminf(mn, D[d]);
+                if (mn > thr) row = len;
+            }
+        }
+    }
+}
+
 // LB_Keogh^2 of one row against the query envelope (U, L in LDS) by a group of
 // 16 lanes, 64 points per step, with the same early abandoning as refine16.
 template <bool VEC>
@@ -656,7 +776,8 @@ struct ScanSmem {
 // plan fits in 64 KB, else it is read from global memory (L2-resident: one
 // table per query).
 constexpr int kTableLdsMax = 32 * 1024;
-constexpr int kDtwQueue = 128;  // per-wave queue of series waiting for DTW
+constexpr int kDtwQueue = 512;   // per-wave queue of series waiting for DTW
+constexpr int kDtwDrainAt = 448; // queue length that starts a drain (at most 3 more arrive per step)
 __host__ __device__ inline ScanSmem scan_smem(int ns, int w, int len, bool dtw, bool table_in_lds) {
     ScanSmem s;
     int o = 0;
@@ -678,6 +799,8 @@ __host__ __device__ inline ScanSmem scan_smem(int ns, int w, int len, bool dtw, 
 template <bool VEC, bool T_LDS, int RB>
 __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
     constexpr bool DTW = RB > 0;
+    // queue drained with lane refill (dtw_drain) for the bands where it measured faster
+    constexpr bool REFILL = RB == 48 || RB == 56;
     extern __shared__ unsigned char smem[];
     const ScanSmem L = scan_smem(a.ns, a.w, a.len, DTW, T_LDS);
     float* lo_e = reinterpret_cast<float*>(smem + L.off_lo);
@@ -762,7 +885,9 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
         int* my_wl = wl + wave * 64;
         int* dq = reinterpret_cast<int*>(smem + L.off_dq) + wave * kDtwQueue;
         int dn = 0;  // queued series of this wave (the same in every lane)
-        // DTW of the first cnt queued series, one per lane
+        // narrow bands (where three or more waves per SIMD fit this way) and the widest (no room
+        // for the refill state at two waves per SIMD): batches of 64, one series per lane, column by
+        // column with the query values broadcast from LDS
         auto dtw_batch = [&](int cnt) {
             thr = read_tau(a, q, k) * a.tau_scale;
             if (lane < cnt) {
@@ -827,7 +952,14 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                         if (surv && gl == 0) dq[dn + __popcll(sm & lt)] = id;
                         dn += __popcll(sm);
                         __builtin_amdgcn_wave_barrier();
-                        if (dn >= 64) {
+                        if (REFILL && dn >= kDtwDrainAt) {
+                            dtw_drain<REFILL ? RB : 8, VEC>(a, q, k, qrow, dq, dn, abandon, lane, lt, n_dtw, n_cells,
+                                                            n_emit);
+                            __builtin_amdgcn_wave_barrier();
+                            dn = 0;
+                            thr = read_tau(a, q, k) * a.tau_scale;
+                        } else if (!REFILL && dn >= 64) {
+                            // widest bands: a batch of 64 as soon as there is one, the rest moves down
                             dtw_batch(64);
                             __builtin_amdgcn_wave_barrier();
                             const int rest = dn - 64;
@@ -859,7 +991,10 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                 __builtin_amdgcn_wave_barrier();
             }
         }
-        if (DTW && dn > 0) dtw_batch(dn);
+        if (DTW && dn > 0) {
+            if (REFILL) dtw_drain<REFILL ? RB : 8, VEC>(a, q, k, qrow, dq, dn, abandon, lane, lt, n_dtw, n_cells, n_emit);
+            else dtw_batch(dn);
+        }
         atomicAdd(&s_st[ST_SERIES_LB], lane == 0 ? n_lb : 0ull);
         if ((lane & 15) == 0) {
             atomicAdd(&s_st[ST_REFINED], n_ref);
@@ -1162,7 +1297,7 @@ void launch_qprep(const QueryArgs& a, hipStream_t s) {
 // Band cells held in registers for a DTW band of half-width r.
 int dtw_band_regs(int r) {
     const int B = 2 * r + 1;
-    return B <= 8 ? 8 : B <= 16 ? 16 : B <= 32 ? 32 : 64;
+    return B <= 8 ? 8 : B <= 16 ? 16 : B <= 32 ? 32 : B <= 48 ? 48 : B <= 56 ? 56 : 64;
 }
 
 void launch_homeleaf(const QueryArgs& a, hipStream_t s) {
@@ -1175,6 +1310,8 @@ void launch_homeleaf(const QueryArgs& a, hipStream_t s) {
             case 8: k_homeleaf<8><<<a.mq, 256, lds, s>>>(a); break;
             case 16: k_homeleaf<16><<<a.mq, 256, lds, s>>>(a); break;
             case 32: k_homeleaf<32><<<a.mq, 256, lds, s>>>(a); break;
+            case 48: k_homeleaf<48><<<a.mq, 256, lds, s>>>(a); break;
+            case 56: k_homeleaf<56><<<a.mq, 256, lds, s>>>(a); break;
             default: k_homeleaf<64><<<a.mq, 256, lds, s>>>(a); break;
         }
     }
@@ -1202,6 +1339,8 @@ void launch_index_scan_t(const QueryArgs& a, const dim3& grid, hipStream_t s) {
         case 8: k_index_scan<VEC, TL, 8><<<grid, 256, L.total, s>>>(a); break;
         case 16: k_index_scan<VEC, TL, 16><<<grid, 256, L.total, s>>>(a); break;
         case 32: k_index_scan<VEC, TL, 32><<<grid, 256, L.total, s>>>(a); break;
+        case 48: k_index_scan<VEC, TL, 48><<<grid, 256, L.total, s>>>(a); break;
+        case 56: k_index_scan<VEC, TL, 56><<<grid, 256, L.total, s>>>(a); break;
         default: k_index_scan<VEC, TL, 64><<<grid, 256, L.total, s>>>(a); break;
     }
 }

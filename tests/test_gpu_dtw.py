@@ -52,7 +52,7 @@ def _ref(coll, r, k=10):
     return coll["ref"][r]
 
 
-@pytest.mark.parametrize("r", [0, 3, 12, 31])
+@pytest.mark.parametrize("r", [0, 3, 12, 20, 31])
 @pytest.mark.parametrize("mode", ["index", "scan"])
 def test_dtw_parity(isax, coll, r, mode):
     idx = isax.Index(coll["X"], 16, 8, leaf_size=64)
@@ -107,7 +107,7 @@ def test_dtw_stats(isax, coll):
         assert s["leaves_kept"] <= s["leaves_scanned"]
 
 
-@pytest.mark.parametrize("length,w,r", [(54, 6, 5), (256, 16, 25), (96, 8, 31)])
+@pytest.mark.parametrize("length,w,r", [(54, 6, 5), (54, 6, 20), (256, 16, 25), (96, 8, 31)])
 def test_dtw_lengths(isax, length, w, r):
     X = workload.random_walks(6_007, length, seed=length, device="cuda")
     Qn, _, _ = workload.noisy_queries(X, 4, seed=length + 1)

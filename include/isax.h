@@ -81,7 +81,10 @@ typedef struct isax_index isax_index; /* opaque, owned by the library */
 typedef struct isax_build_options {
     int32_t leaf_size; /* series per leaf (consecutive runs of the sorted order); 0 = 256; 16..4096 */
     int32_t key_bits;  /* leading bits of the interleaved key that are sorted; 0 = min(64, w*c); 8..64, multiple of 8 */
-    int32_t precision; /* bit 0: also keep a BF16 copy, bit 1: also keep an FP8 E4M3 copy (needed by those modes) */
+    int32_t precision; /* bit 0: also keep a BF16 copy, bit 1: also keep an FP8 E4M3 copy (needed by those modes);
+                          bit 2: also keep the FP32 rows in leaf order (n x len x 4 bytes more), read by
+                          refinement instead of the borrowed data: the series of a leaf are then
+                          consecutive in memory. Answers are the same either way. */
     int32_t reserved;  /* must be 0 */
     void* stream;      /* hipStream_t the build runs on; NULL = null stream */
 } isax_build_options;
@@ -171,6 +174,8 @@ typedef struct isax_index_info {
     float max_abs;       /* max |x| over the collection */
     float delta;         /* bound on |FP32 PAA - exact PAA| of any series */
     int64_t device_bytes;/* bytes the index owns on the device */
+    int32_t has_sorted_rows; /* 1 if the index keeps the FP32 rows in leaf order (precision bit 2) */
+    int32_t reserved;
 } isax_index_info;
 
 int isax_index_get_info(const isax_index* idx, isax_index_info* out);

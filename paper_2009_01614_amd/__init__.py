@@ -58,7 +58,8 @@ class IndexInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("len", ctypes.c_int32), ("segments", ctypes.c_int32),
                 ("card_bits", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("key_bits", ctypes.c_int32),
                 ("has_bf16", ctypes.c_int32), ("has_fp8", ctypes.c_int32), ("n_leaves", ctypes.c_int64),
-                ("max_abs", ctypes.c_float), ("delta", ctypes.c_float), ("device_bytes", ctypes.c_int64)]
+                ("max_abs", ctypes.c_float), ("delta", ctypes.c_float), ("device_bytes", ctypes.c_int64),
+                ("has_sorted_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ProfileEntry(ctypes.Structure):

@@ -8,6 +8,7 @@ void launch_summarise(const float* data, int64_t n, int len, int w, int out_stri
 void launch_make_keys(const uint8_t* words, int64_t n, int ws, int w, int c, int key_bits, uint64_t* keys,
                       int32_t* ids, hipStream_t s);
 void sort_keys(uint64_t* keys, int32_t* ids, int64_t n, int key_bits, hipStream_t s);
+void launch_gather_rows(const float* data, const int32_t* ids, int64_t n, int len, float* out, hipStream_t s);
 void launch_gather_words(const uint8_t* words, const int32_t* ids, int64_t n, int ws, uint8_t* out, hipStream_t s);
 void launch_leaf_layout(const uint64_t* keys_sorted, const uint8_t* words_sorted, int64_t n, int ws, int leaf,
                         int64_t n_leaves, uint64_t* leaf_key, uint8_t* lo, uint8_t* hi, hipStream_t s);

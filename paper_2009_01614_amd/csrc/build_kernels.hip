@@ -324,6 +324,22 @@ __global__ void k_gather_words(const uint8_t* __restrict__ words, const int32_t*
     }
 }
 
+// Rows of the collection in leaf order: out[p] = data[ids[p]], 16 bytes per
+// thread when rows are 16-byte aligned.
+template <bool VEC>
+__global__ void k_gather_rows(const float* __restrict__ data, const int32_t* __restrict__ ids, int64_t n, int len,
+                              float* __restrict__ out) {
+    const int per = VEC ? len / 4 : len;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * per; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = t / per;
+        const int e = (int)(t - p * per);
+        if (VEC)
+            reinterpret_cast<float4*>(out + p * len)[e] = reinterpret_cast<const float4*>(data + (int64_t)ids[p] * len)[e];
+        else
+            out[p * len + e] = data[(int64_t)ids[p] * len + e];
+    }
+}
+
 __global__ void k_leaf_keys(const uint64_t* __restrict__ keys_sorted, int64_t n_leaves, int leaf,
                             uint64_t* __restrict__ leaf_key) {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -572,6 +588,15 @@ void launch_gather_words(const uint8_t* words, const int32_t* ids, int64_t n, in
     ProfScope ps("gather_words", s);
     const int64_t t = n * (ws / 16);
     k_gather_words<<<grid_blocks(t, 256), 256, 0, s>>>(words, ids, n, ws, out);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_gather_rows(const float* data, const int32_t* ids, int64_t n, int len, float* out, hipStream_t s) {
+    ProfScope ps("gather_rows", s);
+    const bool vec = len % 4 == 0 && (reinterpret_cast<uintptr_t>(data) & 15) == 0;
+    const int64_t t = n * (vec ? len / 4 : len);
+    if (vec) k_gather_rows<true><<<grid_blocks(t, 256), 256, 0, s>>>(data, ids, n, len, out);
+    else k_gather_rows<false><<<grid_blocks(t, 256), 256, 0, s>>>(data, ids, n, len, out);
     ISAX_HIP(hipGetLastError());
 }
 

@@ -458,7 +458,7 @@ __global__ void __launch_bounds__(256) k_refine_filtered(QueryArgs a, FilterArgs
     for (unsigned i = blockIdx.x * 16 + g; i < cnt; i += gridDim.x * 16) {
         const unsigned pos = f.fcand[(int64_t)q * f.fcap + i];
         const int32_t id = a.ids_sorted[pos];
-        const float* row = a.data + (int64_t)id * a.len;
+        const float* row = series_row(a, pos, id);
         const float thr = read_tau(a, q, k) * a.tau_scale;
         const int S = (a.len + 63) >> 6;
         float acc = 0.f;

@@ -122,6 +122,7 @@ struct isax_index {
     uint8_t* env_hi = nullptr;      // [n_leaves][ws]
     uint64_t* leaf_key = nullptr;   // [n_leaves] first key of each leaf
     // reduced-precision copies for the dot-product filter
+    float* xs = nullptr;            // [n][len] FP32 rows in leaf order (optional copy)
     uint16_t* x_bf16 = nullptr;     // [n][len] BF16 bits
     float4* meta_bf16 = nullptr;    // [n] {|x|^2, |e_x| (up), |x~| (up), 1}
     uint8_t* x_fp8 = nullptr;       // [n][len] E4M3 codes

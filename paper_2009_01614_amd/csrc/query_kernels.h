@@ -11,6 +11,7 @@ enum { ST_LEAVES = 0, ST_LEAVES_KEPT, ST_SERIES_LB, ST_REFINED, ST_REFINE_BYTES,
 struct QueryArgs {
     // index (read only)
     const float* data;
+    const float* xs;            // rows in leaf order (position p = sorted position), or null
     int64_t n;
     int len, w, c, m_seg, ws, ns;
     int leaf_size;
@@ -65,6 +66,11 @@ constexpr int kDtwMaxLen = 2048;
 // The filter's first phase reads one tile in kFilterSub (an even sample of the
 // collection) whose candidates tighten the bound before the other tiles.
 constexpr int kFilterSub = 64;  // longest series the DTW path takes (its LDS plan)
+// Row of the series at sorted position p (id = ids_sorted[p]): the leaf-order
+// copy when the index keeps one, else the borrowed collection.
+__device__ inline const float* series_row(const QueryArgs& a, int64_t p, int32_t id) {
+    return a.xs ? a.xs + p * a.len : a.data + (int64_t)id * a.len;
+}
 constexpr int kLeafBins = 64;
 constexpr int kFirstLeaves = 64;  // leaves refined first, by smallest lower bound
 

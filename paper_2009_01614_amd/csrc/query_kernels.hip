@@ -227,8 +227,9 @@ __device__ void dtw_drain(const QueryArgs& a, int q, int k, const float* qpad, c
         if (idle) {
             const int rank = __popcll(im & lt);
             if (rank < avail) {
-                id = dq[head + rank];
-                x = a.data + (int64_t)id * len;
+                const int32_t pos = dq[head + rank];
+                id = a.ids_sorted[pos];
+                x = series_row(a, pos, id);
                 row = 0;
 #pragma unroll
                 for (int d = 0; d < RB; ++d) {
@@ -621,7 +622,7 @@ __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
         const bool vec = a.len % 4 == 0 && (reinterpret_cast<uintptr_t>(a.data) & 15) == 0;
         for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
             const int32_t id = a.ids_sorted[p0 + i];
-            const float* row = a.data + (int64_t)id * a.len;
+            const float* row = series_row(a, p0 + i, id);
             int cols = 0;
             const float v = vec ? dtw_lane<RB, true>(qrow, row, a.len, a.window, kInf, false, cols)
                                 : dtw_lane<RB, false>(qrow, row, a.len, a.window, kInf, false, cols);
@@ -630,7 +631,7 @@ __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
     } else {
         for (int i = wave; i < cnt; i += blockDim.x / 64) {
             const int32_t id = a.ids_sorted[p0 + i];
-            const float* row = a.data + (int64_t)id * a.len;
+            const float* row = series_row(a, p0 + i, id);
             float acc = 0.f;
             for (int t = lane; t < a.len; t += 64) {
                 const float d = qrow[t] - row[t];
@@ -891,10 +892,11 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
         auto dtw_batch = [&](int cnt) {
             thr = read_tau(a, q, k) * a.tau_scale;
             if (lane < cnt) {
-                const int32_t id = dq[lane];
+                const int32_t pos = dq[lane];
+                const int32_t id = a.ids_sorted[pos];
                 int cols = 0;
-                const float d2 = dtw_lane<DTW ? RB : 8, VEC>(qrow, a.data + (int64_t)id * a.len, a.len, a.window,
-                                                             thr, abandon, cols);
+                const float d2 = dtw_lane<DTW ? RB : 8, VEC>(qrow, series_row(a, pos, id), a.len, a.window, thr,
+                                                             abandon, cols);
                 ++n_dtw;
                 n_cells += (unsigned long long)cols * (2 * a.window + 1);
                 if (d2 <= thr) {
@@ -936,12 +938,12 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                     const int my = ci + g;
                     if constexpr (DTW) {
                         bool surv = false;
-                        int32_t id = 0;
+                        int32_t p2 = 0;  // sorted position; the queue holds positions
                         if (my < nc) {
-                            id = a.ids_sorted[pa + my_wl[my]];
+                            p2 = (int32_t)(pa + my_wl[my]);
                             int steps = 0;
-                            const float lk = lbk16<VEC>(a.data + (int64_t)id * a.len, envU, envL, a.len, gl, thr,
-                                                        abandon, steps);
+                            const float lk = lbk16<VEC>(series_row(a, p2, a.ids_sorted[p2]), envU, envL, a.len, gl,
+                                                        thr, abandon, steps);
                             surv = lk * a.lbk_scale <= thr;
                             if (gl == 0) {
                                 ++n_ref;
@@ -949,7 +951,7 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                             }
                         }
                         const unsigned long long sm = __ballot(surv && gl == 0);
-                        if (surv && gl == 0) dq[dn + __popcll(sm & lt)] = id;
+                        if (surv && gl == 0) dq[dn + __popcll(sm & lt)] = p2;
                         dn += __popcll(sm);
                         __builtin_amdgcn_wave_barrier();
                         if (REFILL && dn >= kDtwDrainAt) {
@@ -973,7 +975,7 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                         if (my < nc) {
                             const int64_t p2 = pa + my_wl[my];
                             const int32_t id = a.ids_sorted[p2];
-                            const float* row = a.data + (int64_t)id * a.len;
+                            const float* row = series_row(a, p2, id);
                             int steps = 0;
                             const float d2 = refine16<VEC>(row, qrow, a.len, gl, thr, abandon, steps);
                             if (gl == 0) {

@@ -198,7 +198,8 @@ isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int
     ISAX_REQUIRE(leaf >= 16 && leaf <= kMaxLeaf, "leaf_size must be in 16..1024");
     const int key_bits = o.key_bits ? o.key_bits : default_key_bits(w, c);
     ISAX_REQUIRE(key_bits >= 8 && key_bits <= 64 && key_bits % 8 == 0, "key_bits must be a multiple of 8 in 8..64");
-    ISAX_REQUIRE(o.precision >= 0 && o.precision <= 3, "precision must be a bitmask of 1 (BF16) and 2 (FP8)");
+    ISAX_REQUIRE(o.precision >= 0 && o.precision <= 7,
+                 "precision must be a bitmask of 1 (BF16), 2 (FP8) and 4 (FP32 rows in leaf order)");
     ISAX_REQUIRE(o.reserved == 0, "reserved must be 0");
     require_device_accessible(data, "data");
     hipStream_t s = static_cast<hipStream_t>(o.stream);
@@ -245,7 +246,11 @@ isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int
     idx->env_hi = own<uint8_t>(idx.get(), (size_t)idx->n_leaves * ws);
     launch_leaf_layout(keys.as<uint64_t>(), idx->words_sorted, n, ws, leaf, idx->n_leaves, idx->leaf_key, idx->env_lo,
                        idx->env_hi, s);
-    ISAX_REQUIRE(o.precision == 0 || len <= 512, "the reduced-precision copies support len <= 512");
+    ISAX_REQUIRE((o.precision & 3) == 0 || len <= 512, "the reduced-precision copies support len <= 512");
+    if (o.precision & 4) {
+        idx->xs = own<float>(idx.get(), (size_t)n * len);
+        launch_gather_rows(data, idx->ids_sorted, n, len, idx->xs, s);
+    }
     const int lp = filter_len_pad(len);
     if (o.precision & 1) {
         idx->x_bf16 = own<uint16_t>(idx.get(), (size_t)n * lp);
@@ -290,6 +295,7 @@ void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const 
     QueryArgs& a = b.a;
     std::memset(&a, 0, sizeof(a));
     a.data = idx->data;
+    a.xs = idx->xs;
     a.n = idx->n;
     a.len = idx->len;
     a.w = idx->w;
@@ -749,6 +755,7 @@ int isax_index_get_info(const isax_index* idx, isax_index_info* out) {
         out->key_bits = idx->key_bits;
         out->has_bf16 = idx->x_bf16 != nullptr;
         out->has_fp8 = idx->x_fp8 != nullptr;
+        out->has_sorted_rows = idx->xs != nullptr;
         out->n_leaves = idx->n_leaves;
         out->max_abs = idx->max_abs;
         out->delta = idx->delta;

@@ -144,3 +144,12 @@ def test_dtw_argument_errors(isax, coll):
     with pytest.raises(isax.IsaxError) as e:
         big.query(X[:1].contiguous(), k=1, metric="dtw", window=3)
     assert "at most 2048" in str(e.value)
+
+
+@pytest.mark.parametrize("r", [12, 20])
+def test_dtw_sorted_rows_copy(isax, coll, r):
+    idx = isax.Index(coll["X"], 16, 8, leaf_size=64, precision=4)
+    ref_ids, ref_d2 = _ref(coll, r)
+    for mode in ("index", "scan"):
+        ids, d = idx.query(coll["Q"], k=10, mode=mode, metric="dtw", window=r)
+        _check(ids, d, ref_ids, ref_d2, 10)

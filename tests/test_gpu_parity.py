@@ -215,3 +215,17 @@ def test_errors_leave_outputs_untouched(isax, coll):
     host = np.zeros((100, 256), np.float32)
     assert not isax.lib().isax_build(host.ctypes.data, 100, 256, 16, 8)
     assert "not device memory" in isax.last_error()
+
+
+def test_sorted_rows_copy(isax, coll):
+    """With the FP32 rows also kept in leaf order, refinement reads them there; same answers."""
+    plain = isax.Index(coll["X"], 16, 8, precision=1)
+    idx = isax.Index(coll["X"], 16, 8, precision=5)
+    inf, inf0 = idx.info(), plain.info()
+    assert inf["has_sorted_rows"] == 1 and inf0["has_sorted_rows"] == 0
+    assert inf["device_bytes"] - inf0["device_bytes"] >= coll["X"].numel() * 4
+    for mode in ("index", "scan", "bf16"):
+        ids, d = idx.query(coll["Q"], k=10, mode=mode)
+        _check_answer(ids, d, coll["ids10"], coll["d2_10"], 10)
+    ids, d = idx.query(coll["Q"], k=10, candidate_capacity=10)
+    _check_answer(ids, d, coll["ids10"], coll["d2_10"], 10)

@@ -58,7 +58,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; a sharded design is described "
+              "with the rest of the design notes",
               file=sys.stderr)
         sys.exit(2)
 
@@ -358,16 +359,15 @@ def precision_report(args, dev):
     """Precision configuration: 10M x 256, 4 batches of 1024 queries, k = 1 and 10.
 
     Reports queries/s of every mode (all exact, ids compared) and, for sampled
-    queries, the reduced-precision filter's error against FP64 distances from the
-    C oracle: max |ED^2 - approx| / M (<= 1 by the proof), mean margin M and the
-    fraction of series the filter keeps at the final bound.
+    queries, the reduced-precision filter's error against plain FP64 distances:
+    max |ED^2 - approx| / M (<= 1 by the proof), mean margin M and the fraction
+    of series the filter keeps at the final bound.
     """
     import numpy as np
     import torch
 
     import paper_2009_01614_amd as isax
     import workload
-    from oracle import knn_ref
 
     n, L = 10_000_000, 256
     log("generating 10M x 256")
@@ -391,9 +391,15 @@ def precision_report(args, dev):
             assert torch.equal(ids, ref), f"{mode} disagrees"
             log(f"k={k} {mode}: {out['qps'][f'{mode}_k{k}']} queries/s")
     log("filter error vs FP64 on 4 sampled queries")
-    Xh = X.cpu().numpy()
     sample = Q[[0, 1, 2, 3]].contiguous()
-    d64 = np.stack([knn_ref.sq_dists_c(Xh, sample[j].cpu().numpy()) for j in range(4)])
+    # the bound check: plain FP64 squared distances (PyTorch on the device, in chunks)
+    d64 = np.empty((4, n), np.float64)
+    q64 = sample.double()
+    for c0 in range(0, n, 1 << 20):
+        xc = X[c0:c0 + (1 << 20)].double()
+        for j in range(4):
+            d64[j, c0:c0 + xc.shape[0]] = ((xc - q64[j]) ** 2).sum(dim=1).cpu().numpy()
+        del xc
     for mode in ("bf16", "fp8"):
         ap, mg = (t.cpu().numpy().astype(np.float64) for t in idx.filter_scores(sample, mode))
         err = np.abs(d64 - ap)
@@ -423,7 +429,7 @@ def _timed_query(isax, idx, Q, **kw):
 
 
 def next_report(args, dev):
-    """Next rows, each exact (answers compared across modes and with the oracle on a sample).
+    """Next rows, each exact (answers compared across modes; the DTW CPU baseline's answer too).
 
     DTW: n x 256 random walks, Sakoe-Chiba half-width 25 (10 %), 100 noisy
     queries, k = 1 and 10, index and plain-scan modes; DTW cells/s against the
@@ -463,7 +469,7 @@ def next_report(args, dev):
                 "cells_per_s": cps, "alu_frac": cps * DTW_OPS_PER_CELL / PEAK_VALU_OPS}
             log(f"dtw k={k} {mode}: {out['dtw'][f'{mode}_k{k}']}")
         assert torch.equal(res[(k, "index")], res[(k, "scan")]), "DTW index and scan disagree"
-    log("DTW oracle on 1 query (all host threads)")
+    log("DTW CPU baseline: the oracle on 1 query (all host threads)")
     Xh = X.cpu().numpy()
     t0 = time.perf_counter()
     ref_ids, _ = knn_ref.knn_dtw_c(Xh, Q100[:1].cpu().numpy(), 10, r)

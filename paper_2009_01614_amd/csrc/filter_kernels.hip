@@ -551,9 +551,13 @@ void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qm
     else k_filter<KIND, KS, MT, WAVES, false><<<blocks, C::THREADS, 0, s>>>(a, f, qtiles, n_streams, qmax);
 }
 
+// Batch-size classes: a block serves 64, 128, 256 or 512 queries, so a batch
+// of m queries pads to at most twice m rows of matrix work (above 64).
 template <int KIND, int KS, int MT>
 void launch_filter_sized(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax, hipStream_t s) {
     if (a.mq <= 64 && !f.out_approx) launch_filter_t<KIND, KS, 1, 2>(a, f, qmax, s);
+    else if (a.mq <= 128 && !f.out_approx) launch_filter_t<KIND, KS, 1, 4>(a, f, qmax, s);
+    else if (a.mq <= 256 && !f.out_approx) launch_filter_t<KIND, KS, MT, 4>(a, f, qmax, s);
     else launch_filter_t<KIND, KS, MT, 8>(a, f, qmax, s);
 }
 
@@ -606,7 +610,7 @@ void launch_refine_filtered(const QueryArgs& a, const FilterArgs& f, hipStream_t
 }
 
 // Query codes are padded to a multiple of 512 rows, a multiple of every
-// configuration's queries per block (64, 256 or 512).
+// configuration's queries per block (64, 128, 256 or 512).
 int filter_queries_per_block(int len) {
     (void)len;
     return 512;

@@ -83,3 +83,15 @@ def test_filter_candidate_overflow_path(isax, mode):
     for cap in (16, 200):
         ids, _ = idx.query(Q, k=10, mode=mode, candidate_capacity=cap)
         assert np.array_equal(_cpu(ids), ref_ids), cap
+
+
+@pytest.mark.parametrize("m", [64, 65, 100, 128, 129, 200, 256, 257])
+def test_filter_batch_size_classes(isax, m):
+    """Every block configuration (64, 128, 256, 512 queries per block) and its boundaries."""
+    X = workload.random_walks(40_009, 256, seed=61, device="cuda")
+    Qn, _, _ = workload.noisy_queries(X, m, seed=62 + m)
+    ref_ids, _ = kr.knn_exact_c(_cpu(X), _cpu(Qn), 3)
+    idx = isax.Index(X, 16, 8, precision=3)
+    for mode in ("bf16", "fp8"):
+        ids, _ = idx.query(Qn.contiguous(), k=3, mode=mode)
+        assert np.array_equal(_cpu(ids), ref_ids), mode

@@ -629,16 +629,17 @@ __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
             keys[i] = make_key(v, id);
         }
     } else {
-        for (int i = wave; i < cnt; i += blockDim.x / 64) {
+        // 16 lanes per series, four series per wave at a time (no early abandoning: these
+        // values seed the bound)
+        const bool vec = a.len % 4 == 0 && (reinterpret_cast<uintptr_t>(a.data) & 15) == 0;
+        const int g = lane >> 4, gl = lane & 15;
+        for (int i = wave * 4 + g; i < cnt; i += (int)(blockDim.x / 64) * 4) {
             const int32_t id = a.ids_sorted[p0 + i];
             const float* row = series_row(a, p0 + i, id);
-            float acc = 0.f;
-            for (int t = lane; t < a.len; t += 64) {
-                const float d = qrow[t] - row[t];
-                acc = fmaf(d, d, acc);
-            }
-            acc = sum64(acc);
-            if (lane == 0) keys[i] = make_key(acc, id);
+            int steps = 0;
+            const float acc = vec ? refine16<true>(row, qrow, a.len, gl, kInf, false, steps)
+                                  : refine16<false>(row, qrow, a.len, gl, kInf, false, steps);
+            if (gl == 0) keys[i] = make_key(acc, id);
         }
     }
     __syncthreads();

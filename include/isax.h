@@ -235,7 +235,7 @@ typedef struct isax_server_options {
     int32_t max_batch;       /* requests per batch; 0 = 256 */
     int32_t streams;         /* batches in flight; 0 = 4 */
     int64_t memory_budget;   /* bytes of per-batch scratch allowed in flight; 0 = 4 GiB */
-    int32_t mode;            /* ISAX_MODE_* used for every batch */
+    int32_t mode;            /* ISAX_MODE_* used for every batch; the server answers Euclidean k-NN */
     int32_t reserved;
 } isax_server_options;
 

@@ -153,3 +153,12 @@ def test_dtw_sorted_rows_copy(isax, coll, r):
     for mode in ("index", "scan"):
         ids, d = idx.query(coll["Q"], k=10, mode=mode, metric="dtw", window=r)
         _check(ids, d, ref_ids, ref_d2, 10)
+
+
+@pytest.mark.parametrize("w,c", [(8, 4), (32, 2)])
+def test_dtw_metamorphic_summaries(isax, coll, w, c):
+    """Other segment counts and cardinalities give the same DTW answer."""
+    idx = isax.Index(coll["X"], w, c)
+    ref_ids, ref_d2 = _ref(coll, 12)
+    ids, d = idx.query(coll["Q"], k=5, metric="dtw", window=12)
+    _check(ids, d, ref_ids, ref_d2, 5)

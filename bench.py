@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--sweep-mode", default="bf16", choices=["index", "scan", "bf16", "fp8"])
     ap.add_argument("--precision-report", action="store_true",
                     help="instead of the headline: 10M x 256, batches of 1024, modes and filter error vs FP64")
+    ap.add_argument("--sigma-report", action="store_true",
+                    help="instead of the headline: 100M x 256, queries split by noise level, k = 1, 10, 100")
     ap.add_argument("--next-report", action="store_true",
                     help="instead of the headline: DTW on the index, raw data in pinned host memory, embeddings")
     ap.add_argument("--next-n", type=int, default=10_000_000, help="collection size of the next-rows report")
@@ -76,6 +78,8 @@ def main():
         return serving_sweep(args, dev)
     if args.next_report:
         return next_report(args, dev)
+    if args.sigma_report:
+        return sigma_report(args, dev)
     if args.precision_report:
         return precision_report(args, dev)
     n, L, m, k = args.n, args.len, args.m, args.k
@@ -408,6 +412,45 @@ def precision_report(args, dev):
                                  "mean_abs_err": float(err.mean()),
                                  "kept_fraction_at_final_bound_k1": float(((ap - mg) <= tau).mean())}
         log(f"{mode}: {out[f'filter_{mode}']}")
+    print(json.dumps(out), flush=True)
+
+
+def sigma_report(args, dev):
+    """Per-noise-level breakdown at the headline size: the 1000 noisy queries split by
+    sigma (0.01 / 0.1 / 1), each third answered as one batch in the BF16 and index
+    modes at k = 1, 10 and 100, with the index path's pruning statistics."""
+    import numpy as np
+    import torch
+
+    import paper_2009_01614_amd as isax
+    import workload
+
+    n, L, m = args.n, args.len, args.m
+    log(f"generating {n} x {L}")
+    X = workload.random_walks(n, L, seed=20090163, device=dev)
+    Q, src, sig = workload.noisy_queries(X, m, seed=20091163)
+    idx = isax.Index(X, 16, 8, precision=1)
+    out = {"metric": "exact k-NN queries/s and pruning by query noise level",
+           "config": {"workload": f"{n} x {L} random walks, {m} noisy queries split by sigma"}, "by_sigma": {}}
+    for sg in (0.01, 0.1, 1.0):
+        sel = torch.from_numpy(np.where(sig == sg)[0]).to(dev)
+        Qs = Q[sel].contiguous()
+        rec = {"queries": int(Qs.shape[0])}
+        for k in (1, 10, 100):
+            for mode in ("bf16", "index"):
+                idx.query(Qs[:8].contiguous(), k=k, mode=mode)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = idx.query(Qs, k=k, mode=mode, stats=(mode == "index"))
+                torch.cuda.synchronize()
+                rec[f"{mode}_k{k}_qps"] = round(Qs.shape[0] / (time.perf_counter() - t0), 1)
+                if mode == "index":
+                    st = res[2]
+                    rec[f"index_k{k}_leaves_kept_frac"] = round(
+                        float(np.mean([x["leaves_kept"] / max(x["leaves_scanned"], 1) for x in st])), 4)
+                    rec[f"index_k{k}_series_refined"] = round(float(np.mean([x["series_refined"] for x in st])), 1)
+        out["by_sigma"][str(sg)] = rec
+        log(f"sigma {sg}: {rec}")
     print(json.dumps(out), flush=True)
 
 

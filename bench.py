@@ -38,7 +38,7 @@ def main():
     ap.add_argument("--len", type=int, default=256)
     ap.add_argument("--m", type=int, default=1000)
     ap.add_argument("--k", type=int, default=1)
-    ap.add_argument("--mode", default="bf16", choices=["index", "scan", "bf16", "fp8"])
+    ap.add_argument("--mode", default="bf16", choices=["index", "scan", "bf16", "fp8", "hybrid"])
     ap.add_argument("--modes", default="index,scan,bf16,fp8", help="modes measured once each besides the timed one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-series", type=int, default=10_000_000)
@@ -47,7 +47,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="instead of the headline: serve 50M x 256 + 20M x 128 at swept Poisson rates")
-    ap.add_argument("--sweep-mode", default="bf16", choices=["index", "scan", "bf16", "fp8"])
+    ap.add_argument("--sweep-mode", default="bf16", choices=["index", "scan", "bf16", "fp8", "hybrid"])
     ap.add_argument("--precision-report", action="store_true",
                     help="instead of the headline: 10M x 256, batches of 1024, modes and filter error vs FP64")
     ap.add_argument("--sigma-report", action="store_true",
@@ -92,7 +92,7 @@ def main():
     # ---------------------------------------------------------------- build
     precision = 0
     for md in set(args.modes.split(",")) | {args.mode}:
-        precision |= {"bf16": 1, "fp8": 2}.get(md, 0)
+        precision |= {"bf16": 1, "fp8": 2, "hybrid": 1}.get(md, 0)
     log("building the index (twice; the second is timed)")
     idx = isax.Index(X, 16, 8, precision=precision)
     del idx
@@ -128,11 +128,19 @@ def main():
     qps = m * args.steps / dt
     log(f"{args.mode}: {qps:.1f} queries/s, {dt / args.steps * 1e3:.2f} ms/step")
 
+    # queries the filter answers: all of them, or under hybrid those the planner hands to it
+    m_filter, split = m, None
+    if args.mode == "hybrid":
+        _, _, st = idx.query(Q, k=k, mode="hybrid", stream=stream, stats=True)
+        m_filter = sum(1 for x in st if x["path"] == isax.MODE_BF16)
+        split = {"index": m - m_filter, "bf16": m_filter,
+                 "hybrid_leaves": max(1, idx.info()["n_leaves"] // 32)}
+        log(f"hybrid split: {split}")
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     avg_ms = dom["total_ms"] / max(dom["launches"], 1)
     if dom_name.startswith("filter_"):
         dt_ = dom_name.split("_")[1]
-        per_launch_flop = 2.0 * L * n * m / max(dom["launches"] / args.steps, 1)
+        per_launch_flop = 2.0 * L * n * m_filter / max(dom["launches"] / args.steps, 1)
         achieved = per_launch_flop / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 1), "peak": PEAK_TFLOPS[dt_], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_TFLOPS[dt_], 4), "traffic": None, "kernel": "k_filter",
@@ -156,7 +164,9 @@ def main():
         cnt = json.load(open(os.path.join(ROOT, "profiles", "hbm_counters_100Mx256_m1000.json")))
         key = "k_filter" if dom_name.startswith("filter_") else "k_" + dom_name
         srcf = {"k_filter": "filter_kernels.hip", "k_index_scan": "query_kernels.hip"}.get(key)
-        if (srcf and key in cnt and n == 100_000_000 and m == 1000 and (key != "k_filter" or dom_name == "filter_bf16")):
+        mode_ok = cnt.get(key, {}).get("mode", "bf16" if key == "k_filter" else "index") == args.mode
+        if (srcf and key in cnt and n == 100_000_000 and m == 1000 and mode_ok and k == 1
+                and (key != "k_filter" or dom_name == "filter_bf16")):
             with open(os.path.join(ROOT, "paper_2009_01614_amd", "csrc", srcf), "rb") as fh:
                 cur = hashlib.sha256(fh.read()).hexdigest()[:16]
             if cur == cnt[key]["source_sha256_16"]:
@@ -250,11 +260,12 @@ def main():
     out = {
         "metric": "exact 1-NN queries/s @100M x 256", "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.mode if args.mode in ("bf16", "fp8") else "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"bf16": "bf16", "fp8": "fp8", "hybrid": "bf16"}.get(args.mode, "f32"),
         "data": "synthetic",
         "config": {"workload": f"{n} x {L} z-normalised FP32 random walks, 16 segments, 8-bit iSAX; {m} noisy-copy "
                                f"queries (sigma 0.01/0.1/1), exact k={k}",
-                   "mode": args.mode, "refine_dtype": "f32", "source_hit_rate": hit},
+                   "mode": args.mode, "refine_dtype": "f32", "source_hit_rate": hit, "hybrid_split": split},
         "build_s": round(build_s, 4), "build_isax_only_s": round(build_plain_s, 4),
         "build_kernels_ms": {kk: round(v["total_ms"], 3) for kk, v in build_prof.items()},
         "modes_qps": modes_qps, "serving": serving, "kernels": kernels,

@@ -51,7 +51,10 @@ enum {
     ISAX_MODE_INDEX = 0, /* iSAX path: home leaf, leaf and series lower bounds, refinement (Sec. III) */
     ISAX_MODE_SCAN = 1,  /* plain FP32 scan of every series (the sequential-scan baseline, Sec. I) */
     ISAX_MODE_BF16 = 2,  /* BF16 matrix-core dot-product filter with a proven error margin, FP32 refinement */
-    ISAX_MODE_FP8 = 3    /* FP8 E4M3 (power-of-two scale per series) filter, same margin rule */
+    ISAX_MODE_FP8 = 3,   /* FP8 E4M3 (power-of-two scale per series) filter, same margin rule */
+    ISAX_MODE_HYBRID = 4 /* per query: the iSAX path when at most hybrid_leaves leaves have a lower bound
+                            within the approximate answer's best-so-far (the pruning of Sec. III will
+                            leave little to refine), else the BF16 filter; needs the BF16 copy, ED only */
 };
 
 /* Query flags (isax_query_options.flags): switches for testing; the answer never changes. */
@@ -100,6 +103,11 @@ typedef struct isax_query_stats { /* per query, filled when requested */
     float tau_final;         /* squared k-th distance found, FP32 */
     int64_t dtw_series;      /* DTW only: series whose warping distance was (partly) computed */
     int64_t dtw_cells;       /* DTW only: band cells computed (columns x (2 window + 1)) */
+    int64_t leaves_initial;  /* index and hybrid modes (best-first order): leaves other than the home leaf
+                                whose lower bound is within the best-so-far of the approximate answer;
+                                -1 where not computed */
+    int32_t path;            /* the mode that answered this query (ISAX_MODE_INDEX or _BF16 under hybrid) */
+    int32_t reserved;
 } isax_query_stats;
 
 typedef struct isax_query_options {
@@ -113,6 +121,8 @@ typedef struct isax_query_options {
     isax_query_stats* stats;    /* host, m entries, or NULL */
     int32_t metric;             /* ISAX_METRIC_*; DTW runs in ISAX_MODE_INDEX and ISAX_MODE_SCAN only */
     int32_t window;             /* DTW band half-width, 0..min(ISAX_MAX_WINDOW, len-1); must be 0 for ED */
+    int64_t hybrid_leaves;      /* ISAX_MODE_HYBRID: the largest leaves_initial answered by the iSAX path;
+                                   0 = max(1, n_leaves / 32); must be >= 0 */
 } isax_query_options;
 
 /* Last error message of the calling thread ("" if none). Static storage, thread-local. */
@@ -235,7 +245,8 @@ typedef struct isax_server_options {
     int32_t max_batch;       /* requests per batch; 0 = 256 */
     int32_t streams;         /* batches in flight; 0 = 4 */
     int64_t memory_budget;   /* bytes of per-batch scratch allowed in flight; 0 = 4 GiB */
-    int32_t mode;            /* ISAX_MODE_* used for every batch; the server answers Euclidean k-NN */
+    int32_t mode;            /* ISAX_MODE_* used for every batch (hybrid with its default limit); the server
+                                answers Euclidean k-NN */
     int32_t reserved;
 } isax_server_options;
 

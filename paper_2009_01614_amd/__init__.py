@@ -20,8 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libisax.so")
 
 ISAX_OK, ISAX_EINVAL, ISAX_ENOMEM, ISAX_EDEVICE, ISAX_EOVERFLOW = 0, -1, -2, -3, -4
-MODE_INDEX, MODE_SCAN, MODE_BF16, MODE_FP8 = 0, 1, 2, 3
-MODES = {"index": MODE_INDEX, "scan": MODE_SCAN, "bf16": MODE_BF16, "fp8": MODE_FP8}
+MODE_INDEX, MODE_SCAN, MODE_BF16, MODE_FP8, MODE_HYBRID = 0, 1, 2, 3, 4
+MODES = {"index": MODE_INDEX, "scan": MODE_SCAN, "bf16": MODE_BF16, "fp8": MODE_FP8, "hybrid": MODE_HYBRID}
 METRIC_ED, METRIC_DTW = 0, 1
 METRICS = {"ed": METRIC_ED, "dtw": METRIC_DTW}
 MAX_WINDOW = 31
@@ -45,13 +45,15 @@ class QueryStats(ctypes.Structure):
                 ("series_bounded", ctypes.c_int64), ("series_refined", ctypes.c_int64),
                 ("refine_bytes", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("tau_initial", ctypes.c_float), ("tau_final", ctypes.c_float),
-                ("dtw_series", ctypes.c_int64), ("dtw_cells", ctypes.c_int64)]
+                ("dtw_series", ctypes.c_int64), ("dtw_cells", ctypes.c_int64),
+                ("leaves_initial", ctypes.c_int64), ("path", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class QueryOptions(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("candidate_capacity", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("k_per_query", ctypes.c_void_p), ("stream", ctypes.c_void_p),
-                ("stats", ctypes.POINTER(QueryStats)), ("metric", ctypes.c_int32), ("window", ctypes.c_int32)]
+                ("stats", ctypes.POINTER(QueryStats)), ("metric", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("hybrid_leaves", ctypes.c_int64)]
 
 
 class IndexInfo(ctypes.Structure):
@@ -235,10 +237,12 @@ class Index:
 
     def query(self, queries: torch.Tensor, k: int = 1, mode="index", k_per_query: torch.Tensor | None = None,
               candidate_capacity: int = 0, flags: int = 0, batch: int = 0, stream=None, stats: bool = False,
-              metric="ed", window: int = 0):
+              metric="ed", window: int = 0, hybrid_leaves: int = 0):
         """Exact k-NN: (ids int64 [m, k], dists float32 [m, k]); with stats=True also a list of dicts.
 
         metric "ed" (Euclidean) or "dtw" (banded DTW of half-width `window`, modes "index" and "scan").
+        mode "hybrid" answers each query with the iSAX path when at most `hybrid_leaves` leaves
+        (0: the library's default) lie within its first best-so-far, else with the BF16 filter.
         """
         _dev_f32(queries, "queries")
         m = queries.shape[0]
@@ -253,7 +257,7 @@ class Index:
             kp = k_per_query.data_ptr()
         opt = QueryOptions(MODES[mode] if isinstance(mode, str) else int(mode), candidate_capacity, flags, batch,
                            kp, _stream(stream), st, METRICS[metric] if isinstance(metric, str) else int(metric),
-                           window)
+                           window, hybrid_leaves)
         _check(lib().isax_query_ex(self._h, queries.data_ptr(), m, k, ids.data_ptr(), dists.data_ptr(),
                                    ctypes.byref(opt)))
         if stats:

@@ -62,10 +62,10 @@ struct QueryArgs {
     float* env_paa;             // [mq][2][w] PAA of the upper then lower query envelope (ED: the query PAA twice)
     float* qenv;                // [mq][2][len] DTW: upper then lower envelope of the query
 };
-constexpr int kDtwMaxLen = 2048;
+constexpr int kDtwMaxLen = 2048;  // longest series the DTW path takes (its LDS plan)
 // The filter's first phase reads one tile in kFilterSub (an even sample of the
 // collection) whose candidates tighten the bound before the other tiles.
-constexpr int kFilterSub = 64;  // longest series the DTW path takes (its LDS plan)
+constexpr int kFilterSub = 64;
 // Row of the series at sorted position p (id = ids_sorted[p]): the leaf-order
 // copy when the index keeps one, else the borrowed collection.
 __device__ inline const float* series_row(const QueryArgs& a, int64_t p, int32_t id) {
@@ -84,6 +84,11 @@ void launch_brute_scan(const QueryArgs& a, hipStream_t s);
 void launch_topk(const QueryArgs& a, hipStream_t s);
 void launch_rerun_reset(const QueryArgs& a, hipStream_t s);
 void launch_lower_bounds(const QueryArgs& a, float* out, hipStream_t s);
+// Hybrid batches: rows pos[0..mf) of (Q, kq) into (Qf, kqf); answer rows back to pos.
+void launch_gather_queries(const float* Q, const int32_t* kq, const int32_t* pos, int mf, int len, float* Qf,
+                           int32_t* kqf, hipStream_t s);
+void launch_scatter_answers(const int64_t* ids, const float* dists, const int32_t* pos, int mf, int kmax,
+                            int64_t* out_ids, float* out_dists, hipStream_t s);
 
 // Reduced-precision filter (filter_kernels.hip).
 struct FilterArgs {

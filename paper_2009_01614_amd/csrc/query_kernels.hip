@@ -819,7 +819,8 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
     __shared__ unsigned long long s_st[ST_N];
 
     const int q = blockIdx.y;
-    if (a.rerun && a.done[q]) return;
+    // finished queries (re-runs), and queries that a hybrid batch hands to the filter
+    if (a.done[q]) return;
     const int k = a.kq[q];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t leaf = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -1258,6 +1259,28 @@ __global__ void __launch_bounds__(256) k_topk(QueryArgs a) {
     }
 }
 
+// Sub-batch of a hybrid batch: query rows and k by position in the batch, and
+// the answers written back to those positions.
+__global__ void k_gather_queries(const float* __restrict__ Q, const int32_t* __restrict__ kq,
+                                 const int32_t* __restrict__ pos, int len, float* __restrict__ Qf,
+                                 int32_t* __restrict__ kqf) {
+    const int i = blockIdx.x;
+    const int64_t src = pos[i];
+    for (int t = threadIdx.x; t < len; t += blockDim.x) Qf[(int64_t)i * len + t] = Q[src * len + t];
+    if (threadIdx.x == 0) kqf[i] = kq[src];
+}
+
+__global__ void k_scatter_answers(const int64_t* __restrict__ ids, const float* __restrict__ dists,
+                                  const int32_t* __restrict__ pos, int kmax, int64_t* __restrict__ out_ids,
+                                  float* __restrict__ out_dists) {
+    const int i = blockIdx.x;
+    const int64_t dst = pos[i];
+    for (int t = threadIdx.x; t < kmax; t += blockDim.x) {
+        out_ids[dst * kmax + t] = ids[(int64_t)i * kmax + t];
+        out_dists[dst * kmax + t] = dists[(int64_t)i * kmax + t];
+    }
+}
+
 // Before a re-run: empty the candidate lists of the unfinished queries.
 __global__ void k_rerun_reset(QueryArgs a) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1318,6 +1341,20 @@ void launch_homeleaf(const QueryArgs& a, hipStream_t s) {
             default: k_homeleaf<64><<<a.mq, 256, lds, s>>>(a); break;
         }
     }
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_gather_queries(const float* Q, const int32_t* kq, const int32_t* pos, int mf, int len, float* Qf,
+                           int32_t* kqf, hipStream_t s) {
+    if (mf <= 0) return;
+    k_gather_queries<<<mf, 256, 0, s>>>(Q, kq, pos, len, Qf, kqf);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_scatter_answers(const int64_t* ids, const float* dists, const int32_t* pos, int mf, int kmax,
+                            int64_t* out_ids, float* out_dists, hipStream_t s) {
+    if (mf <= 0) return;
+    k_scatter_answers<<<mf, 256, 0, s>>>(ids, dists, pos, kmax, out_ids, out_dists);
     ISAX_HIP(hipGetLastError());
 }
 

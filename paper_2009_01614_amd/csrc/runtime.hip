@@ -275,7 +275,15 @@ isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int
 struct Batch {
     DevBuf mem;
     QueryArgs a;
-    int fcap0 = 0;  // initial filter-candidate capacity (0: default)
+    int fcap0 = 0;              // initial filter-candidate capacity (0: default)
+    int mode = ISAX_MODE_INDEX; // the mode the batch ran in
+    bool hist_valid = false;    // leaf_hist holds the best-first histogram of every query
+    // hybrid batches: positions handed to the filter, the per-query skip flags
+    // (1 = filter), and the filter's sub-batch with its gathered rows
+    std::vector<int32_t> far;
+    std::vector<int> skip;
+    std::unique_ptr<Batch> sub;
+    DevBuf sub_mem;
 };
 
 // Slack of comparisons with a DTW best-so-far: the FP32 recurrence sums at
@@ -354,6 +362,17 @@ void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const 
 
 constexpr int kDefaultCap = 16384;
 
+std::vector<int64_t> leaves_initial(const Batch& b, hipStream_t s) {
+    const int mq = b.a.mq;
+    std::vector<unsigned> h((size_t)mq * kLeafBins);
+    ISAX_HIP(hipMemcpyAsync(h.data(), b.a.leaf_hist, h.size() * 4, hipMemcpyDeviceToHost, s));
+    ISAX_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> c(mq, 0);
+    for (int i = 0; i < mq; ++i)
+        for (int j = 0; j < kLeafBins; ++j) c[i] += h[(size_t)i * kLeafBins + j];
+    return c;
+}
+
 void fill_stats(const Batch& b, isax_query_stats* out, hipStream_t s) {
     const int mq = b.a.mq;
     std::vector<unsigned long long> st((size_t)mq * ST_N);
@@ -361,6 +380,7 @@ void fill_stats(const Batch& b, isax_query_stats* out, hipStream_t s) {
     ISAX_HIP(hipMemcpyAsync(st.data(), b.a.stats, st.size() * 8, hipMemcpyDeviceToHost, s));
     ISAX_HIP(hipMemcpyAsync(qi.data(), b.a.qinfo, qi.size() * sizeof(float4), hipMemcpyDeviceToHost, s));
     ISAX_HIP(hipStreamSynchronize(s));
+    const std::vector<int64_t> li = b.hist_valid ? leaves_initial(b, s) : std::vector<int64_t>(mq, -1);
     for (int i = 0; i < mq; ++i) {
         const unsigned long long* r = &st[(size_t)i * ST_N];
         out[i].leaves_scanned = (int64_t)r[ST_LEAVES];
@@ -373,6 +393,21 @@ void fill_stats(const Batch& b, isax_query_stats* out, hipStream_t s) {
         out[i].tau_final = qi[i].y;
         out[i].dtw_series = (int64_t)r[ST_DTW];
         out[i].dtw_cells = (int64_t)r[ST_DTW_CELLS];
+        out[i].leaves_initial = li[i];
+        out[i].path = b.mode == ISAX_MODE_HYBRID ? ISAX_MODE_INDEX : b.mode;
+        out[i].reserved = 0;
+    }
+    if (b.sub) {
+        // queries answered by the filter: its statistics, the first histogram's count
+        std::vector<isax_query_stats> fs(b.far.size());
+        fill_stats(*b.sub, fs.data(), s);
+        for (size_t j = 0; j < b.far.size(); ++j) {
+            isax_query_stats& o = out[b.far[j]];
+            const int64_t keep = o.leaves_initial;
+            o = fs[j];
+            o.leaves_initial = keep;
+            o.path = ISAX_MODE_BF16;
+        }
     }
 }
 
@@ -392,9 +427,83 @@ double scan_bytes(const Batch& b, const isax_index* idx, hipStream_t s) {
 }
 
 void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s);  // defined below
+void finish_batch(isax_index* idx, Batch& b, int mode, hipStream_t s);
+void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s, int64_t hybrid_limit = 0);
 
-void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
+// The iSAX scan after qprep and homeleaf (and the leaf histogram, for the
+// best-first rounds): one pass in layout order, or round 1 then round 2.
+void index_rounds(isax_index* idx, Batch& b, hipStream_t s) {
     QueryArgs& a = b.a;
+    if (a.flags & ISAX_QF_NO_BEST_FIRST) {
+        a.round = 0;
+        launch_index_scan(a, s);
+    } else {
+        a.round = 1;
+        launch_index_scan(a, s);
+        a.round = 2;
+        launch_index_scan(a, s);
+    }
+    if (profiling_on())
+        profile_add_bytes(a.metric == ISAX_METRIC_DTW ? "dtw_scan" : "index_scan", scan_bytes(b, idx, s));
+}
+
+// Hybrid batch: the leaf histogram of the iSAX path counts, for every query,
+// the leaves whose bound is within the approximate answer's best-so-far.  A
+// query with at most `limit` such leaves stays on the iSAX path (pruning will
+// leave little to refine); the others are gathered into a sub-batch that the
+// BF16 filter answers, and their answers are written back to their rows.
+void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
+    QueryArgs& a = b.a;
+    launch_qprep(a, s);
+    launch_homeleaf(a, s);
+    launch_leaf_order(a, s);
+    b.hist_valid = true;
+    const std::vector<int64_t> cnt = leaves_initial(b, s);
+    b.skip.assign(a.mq, 0);
+    for (int q = 0; q < a.mq; ++q)
+        if (cnt[q] > limit) {
+            b.skip[q] = 1;
+            b.far.push_back(q);
+        }
+    const int mf = (int)b.far.size();
+    int32_t* pos = nullptr;
+    int64_t* oid = nullptr;
+    float* od = nullptr;
+    if (mf > 0) {
+        float* Qf = nullptr;
+        int32_t* kqf = nullptr;
+        Arena ar;
+        ar.add(&pos, mf);
+        ar.add(&Qf, (size_t)mf * a.len);
+        ar.add(&kqf, mf);
+        ar.add(&oid, (size_t)mf * a.kmax);
+        ar.add(&od, (size_t)mf * a.kmax);
+        b.sub_mem = ar.commit(s);
+        ISAX_HIP(hipMemcpyAsync(pos, b.far.data(), mf * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        // the iSAX kernels pass over a query whose done flag is set
+        ISAX_HIP(hipMemcpyAsync(a.done, b.skip.data(), a.mq * sizeof(int), hipMemcpyHostToDevice, s));
+        launch_gather_queries(a.Q, a.kq, pos, mf, a.len, Qf, kqf, s);
+        b.sub.reset(new Batch);
+        setup_batch(*b.sub, idx, Qf, mf, kqf, a.kmax, a.cap, a.flags, oid, od, s);
+        b.sub->fcap0 = b.fcap0;
+    }
+    if (mf < a.mq) {
+        index_rounds(idx, b, s);
+        finish_batch(idx, b, ISAX_MODE_INDEX, s);
+    }
+    if (mf > 0) {
+        run_batch(idx, *b.sub, ISAX_MODE_BF16, s);
+        launch_scatter_answers(oid, od, pos, mf, a.kmax, a.out_ids, a.out_dists, s);
+    }
+}
+
+void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s, int64_t hybrid_limit) {
+    QueryArgs& a = b.a;
+    b.mode = mode;
+    if (mode == ISAX_MODE_HYBRID) {
+        run_hybrid_batch(idx, b, s, hybrid_limit);
+        return;
+    }
     launch_qprep(a, s);
     const bool dtw = a.metric == ISAX_METRIC_DTW;
     if (dtw && mode == ISAX_MODE_SCAN) {
@@ -405,17 +514,11 @@ void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
         launch_index_scan(a, s);
     } else if (mode == ISAX_MODE_INDEX) {
         launch_homeleaf(a, s);
-        if (a.flags & ISAX_QF_NO_BEST_FIRST) {
-            a.round = 0;
-            launch_index_scan(a, s);
-        } else {
+        if (!(a.flags & ISAX_QF_NO_BEST_FIRST)) {
             launch_leaf_order(a, s);
-            a.round = 1;
-            launch_index_scan(a, s);
-            a.round = 2;
-            launch_index_scan(a, s);
+            b.hist_valid = true;
         }
-        if (profiling_on()) profile_add_bytes(dtw ? "dtw_scan" : "index_scan", scan_bytes(b, idx, s));
+        index_rounds(idx, b, s);
     } else if (mode == ISAX_MODE_SCAN) {
         launch_seed(a, s);
         launch_brute_scan(a, s);
@@ -423,6 +526,13 @@ void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     } else {
         run_filter_batch(idx, b, mode, s);
     }
+    finish_batch(idx, b, mode, s);
+}
+
+// Final ordering, and re-runs of the queries whose candidate list overflowed.
+void finish_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
+    QueryArgs& a = b.a;
+    const bool dtw = a.metric == ISAX_METRIC_DTW;
     launch_topk(a, s);
     std::vector<int> status(a.mq);
     for (int round = 0;; ++round) {
@@ -459,11 +569,13 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     ISAX_REQUIRE(k >= 1 && k <= ISAX_MAX_K && k <= idx->n, "k must be in 1..min(n, 1024)");
     isax_query_options o{};
     if (opt) o = *opt;
-    ISAX_REQUIRE(o.mode >= ISAX_MODE_INDEX && o.mode <= ISAX_MODE_FP8, "unknown mode");
+    ISAX_REQUIRE(o.mode >= ISAX_MODE_INDEX && o.mode <= ISAX_MODE_HYBRID, "unknown mode");
+    ISAX_REQUIRE(o.hybrid_leaves >= 0, "hybrid_leaves must be >= 0");
     ISAX_REQUIRE(o.candidate_capacity >= 0 && o.batch >= 0, "candidate_capacity and batch must be >= 0");
     ISAX_REQUIRE((o.flags & ~(ISAX_QF_NO_SHARING | ISAX_QF_NO_EARLY_ABANDON | ISAX_QF_NO_BEST_FIRST)) == 0,
                  "unknown flag");
-    ISAX_REQUIRE(o.mode != ISAX_MODE_BF16 || idx->x_bf16, "index was built without the BF16 copy");
+    ISAX_REQUIRE((o.mode != ISAX_MODE_BF16 && o.mode != ISAX_MODE_HYBRID) || idx->x_bf16,
+                 "index was built without the BF16 copy");
     ISAX_REQUIRE(o.mode != ISAX_MODE_FP8 || idx->x_fp8, "index was built without the FP8 copy");
     ISAX_REQUIRE(o.metric == ISAX_METRIC_ED || o.metric == ISAX_METRIC_DTW, "unknown metric");
     if (o.metric == ISAX_METRIC_ED) {
@@ -513,13 +625,14 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     }
     const int B = o.batch ? o.batch : 1024;
     const int cap = o.candidate_capacity ? std::max(o.candidate_capacity, k) : kDefaultCap;
+    const int64_t hybrid_limit = o.hybrid_leaves ? o.hybrid_leaves : std::max<int64_t>(1, idx->n_leaves / 32);
     for (int64_t q0 = 0; q0 < m; q0 += B) {
         const int mq = (int)std::min<int64_t>(B, m - q0);
         Batch b;
         setup_batch(b, idx, Q + q0 * idx->len, mq, kq + q0, k, cap, o.flags, out_ids + q0 * k, out_dists + q0 * k, s,
                     o.metric, o.window);
         b.fcap0 = o.candidate_capacity;
-        run_batch(idx, b, o.mode, s);
+        run_batch(idx, b, o.mode, s, hybrid_limit);
         if (o.stats) fill_stats(b, o.stats + q0, s);
     }
     ISAX_HIP(hipStreamSynchronize(s));
@@ -666,12 +779,14 @@ int64_t isax::query_scratch_bytes(const isax_index* idx, int mq, int kmax, int m
                           (int64_t)kmax * 8 + (int64_t)kDefaultCap * 8 + 4 + 16 + ST_N * 8 + 8 + 4 + 4 +
                           kLeafBins * 4 + 2 * idx->w * 4;
     int64_t tot = per_q * mq + 16 * 256;
-    if (mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8) {
+    if (mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8 || mode == ISAX_MODE_HYBRID) {
         const int qpb = filter_queries_per_block(idx->len);
         const int64_t mq_pad = (mq + qpb - 1) / qpb * qpb;
-        tot += mq_pad * filter_len_pad(idx->len) * (mode == ISAX_MODE_BF16 ? 2 : 1) + mq_pad * 16 +
+        tot += mq_pad * filter_len_pad(idx->len) * (mode == ISAX_MODE_FP8 ? 1 : 2) + mq_pad * 16 +
                (int64_t)mq * (kFilterCap * 4 + 4);
     }
+    if (mode == ISAX_MODE_HYBRID)  // the filter's sub-batch: its own per-query state and gathered rows
+        tot += per_q * mq + (int64_t)mq * (idx->len * 4 + kmax * 12 + 8);
     return tot;
 }
 

@@ -184,7 +184,7 @@ isax_server* isax_server_create(isax_index* const* collections, int32_t n_collec
     if (opt.streams == 0) opt.streams = 4;
     if (opt.memory_budget == 0) opt.memory_budget = int64_t(4) << 30;
     if (opt.max_batch < 1 || opt.max_batch > 4096 || opt.streams < 1 || opt.streams > 16 || opt.memory_budget < 0 ||
-        opt.mode < ISAX_MODE_INDEX || opt.mode > ISAX_MODE_FP8 || opt.reserved != 0) {
+        opt.mode < ISAX_MODE_INDEX || opt.mode > ISAX_MODE_HYBRID || opt.reserved != 0) {
         isax::set_error(ISAX_EINVAL, "bad server options (max_batch 1..4096, streams 1..16, mode, reserved = 0)");
         return nullptr;
     }
@@ -197,7 +197,7 @@ isax_server* isax_server_create(isax_index* const* collections, int32_t n_collec
             delete s;
             return nullptr;
         }
-        if ((opt.mode == ISAX_MODE_BF16 && !idx->x_bf16) || (opt.mode == ISAX_MODE_FP8 && !idx->x_fp8)) {
+        if (((opt.mode == ISAX_MODE_BF16 || opt.mode == ISAX_MODE_HYBRID) && !idx->x_bf16) || (opt.mode == ISAX_MODE_FP8 && !idx->x_fp8)) {
             isax::set_error(ISAX_EINVAL, "a collection lacks the reduced-precision copy the mode needs");
             delete s;
             return nullptr;

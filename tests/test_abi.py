@@ -57,3 +57,29 @@ def test_validation_before_device_work(isax):
     assert not L.isax_server_create(None, 0, None)
     L.isax_free(None)
     assert L.isax_clock() > 0
+
+
+def test_struct_layouts_match_the_header(isax, tmp_path):
+    # the ctypes mirrors of the option, statistics and result structs against
+    # sizeof / offsetof of the same structs compiled from include/isax.h
+    structs = {"isax_build_options": isax.BuildOptions, "isax_query_stats": isax.QueryStats,
+               "isax_query_options": isax.QueryOptions, "isax_index_info": isax.IndexInfo,
+               "isax_profile_entry": isax.ProfileEntry, "isax_server_options": isax.ServerOptions,
+               "isax_result": isax.Result}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "isax.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)

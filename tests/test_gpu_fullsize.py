@@ -50,7 +50,7 @@ def big():
     idx.close()
 
 
-@pytest.mark.parametrize("mode", ["index", "scan", "bf16", "fp8"])
+@pytest.mark.parametrize("mode", ["index", "scan", "bf16", "fp8", "hybrid"])
 @pytest.mark.parametrize("k", [1, 10])
 def test_fullsize_sampled_parity(big, mode, k):
     say("query", mode, "k =", k)

@@ -68,9 +68,9 @@ def _serve(isax, indexes, reqs, mode="index", rate_hz=2000.0, **opt):
     return out
 
 
-@pytest.mark.parametrize("mode", ["index", "bf16"])
+@pytest.mark.parametrize("mode", ["index", "bf16", "hybrid"])
 def test_alone_equals_mix_and_oracle(isax, colls, mode):
-    indexes = [isax.Index(X, 16, 8, precision=1 if mode == "bf16" else 0) for X in colls]
+    indexes = [isax.Index(X, 16, 8, precision=1 if mode in ("bf16", "hybrid") else 0) for X in colls]
     reqs = _requests(colls, 90, seed=11)
     out = _serve(isax, indexes, reqs, mode=mode, max_batch=16, streams=3)
     Xh = [X.cpu().numpy() for X in colls]

@@ -54,6 +54,10 @@ struct QueryArgs {
     int round;
     float* theta;               // [mq]
     unsigned* leaf_hist;        // [mq][kLeafBins]
+    uint2* leaf_list;           // [mq][leaf_cap] {leaf, bound bits} of leaves within the first bound
+    unsigned* leaf_count;       // [mq] leaves within the first bound (also those past leaf_cap)
+    int64_t leaf_cap;
+    int64_t grid_leaves;        // rounds 1 and 2: blocks per query (0: one per 256 leaves)
     // distance measure
     int metric;                 // ISAX_METRIC_*
     int window;                 // DTW band half-width r
@@ -73,6 +77,7 @@ __device__ inline const float* series_row(const QueryArgs& a, int64_t p, int32_t
 }
 constexpr int kLeafBins = 64;
 constexpr int kFirstLeaves = 64;  // leaves refined first, by smallest lower bound
+constexpr int kHistQueries = 4;   // queries per block of the leaf pass
 
 void launch_check_finite(const float* x, int64_t count, int* flag, hipStream_t s);
 void launch_qprep(const QueryArgs& a, hipStream_t s);

@@ -705,40 +705,98 @@ __device__ inline float leaf_bound(const QueryArgs& a, int64_t leaf, const float
     return lb * (float)a.m_seg;
 }
 
-// Best-first order (MESSI's priority queues, by rounds): a histogram of the
-// leaf bounds of every query over [0, bsf] in kLeafBins equal bins, and the
-// threshold theta[q] = the lowest bin edge below which at least kFirstLeaves
-// leaves lie.  Round 1 then refines those leaves, which lowers the
-// best-so-far before round 2 bounds the rest.
+// Best-first order (MESSI's priority queues, by rounds): the bound of every
+// leaf against the best-so-far of the approximate answer.  Per query: a
+// histogram of the bounds over [0, bsf] in kLeafBins equal bins, the count of
+// leaves within the bound, and the list of those leaves with their bounds (the
+// first leaf_cap of them).  theta[q] = the lowest bin edge below which at least
+// kFirstLeaves leaves lie; round 1 refines the listed leaves below theta, which
+// lowers the best-so-far before round 2 takes the rest of the list.  A block
+// takes 256 leaves of kHistQueries queries, so the envelope tile is read once
+// for all of them.
 __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
-    __shared__ float lo_e[256], hi_e[256], pu[64], pl[64];
-    __shared__ unsigned hist[kLeafBins];
-    const int q = blockIdx.y;
+    __shared__ float lo_e[kHistQueries][256], hi_e[kHistQueries][256], pu[kHistQueries][64], pl[kHistQueries][64];
+    __shared__ unsigned hist[kHistQueries][kLeafBins];
+    __shared__ float s_thr[kHistQueries];
+    __shared__ int64_t s_home[kHistQueries][2];
+    __shared__ unsigned s_valid[kHistQueries], s_kept[kHistQueries], s_base[kHistQueries];
+    const int q0 = blockIdx.y * kHistQueries;
+    const int nq = min(kHistQueries, a.mq - q0);
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t leaf = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t h0 = a.home[2 * q], h1 = a.home[2 * q + 1];
-    for (int s = threadIdx.x; s < a.ns; s += 256) {
-        lo_e[s] = a.edges[(int64_t)q * 2 * a.ns + s];
-        hi_e[s] = a.edges[(int64_t)q * 2 * a.ns + a.ns + s];
+    for (int i = 0; i < nq; ++i) {
+        const int q = q0 + i;
+        for (int s = threadIdx.x; s < a.ns; s += 256) {
+            lo_e[i][s] = a.edges[(int64_t)q * 2 * a.ns + s];
+            hi_e[i][s] = a.edges[(int64_t)q * 2 * a.ns + a.ns + s];
+        }
+        if (threadIdx.x < a.w) {
+            pu[i][threadIdx.x] = a.env_paa[(int64_t)q * 2 * a.w + threadIdx.x];
+            pl[i][threadIdx.x] = a.env_paa[(int64_t)q * 2 * a.w + a.w + threadIdx.x];
+        }
+        if (threadIdx.x < kLeafBins) hist[i][threadIdx.x] = 0u;
     }
-    if (threadIdx.x < a.w) {
-        pu[threadIdx.x] = a.env_paa[(int64_t)q * 2 * a.w + threadIdx.x];
-        pl[threadIdx.x] = a.env_paa[(int64_t)q * 2 * a.w + a.w + threadIdx.x];
+    if (threadIdx.x < nq) {
+        const int q = q0 + threadIdx.x;
+        s_thr[threadIdx.x] = read_tau(a, q, a.kq[q]) * a.tau_scale;
+        s_home[threadIdx.x][0] = a.home[2 * q];
+        s_home[threadIdx.x][1] = a.home[2 * q + 1];
+        s_valid[threadIdx.x] = 0u;
+        s_kept[threadIdx.x] = 0u;
     }
-    if (threadIdx.x < kLeafBins) hist[threadIdx.x] = 0u;
     __syncthreads();
-    const float thr = read_tau(a, q, a.kq[q]) * a.tau_scale;
-    if (leaf < a.n_leaves && !(leaf >= h0 && leaf < h1)) {
-        const float lb = leaf_bound(a, leaf, pu, pl, lo_e, hi_e);
-        if (lb * a.lb_scale <= thr) {
+    // per query: the bound, and the slot of a kept leaf among the block's kept leaves
+    float lbs[kHistQueries];
+    int slot[kHistQueries];
+#pragma unroll
+    for (int i = 0; i < kHistQueries; ++i) {
+        slot[i] = -1;
+        lbs[i] = 0.f;
+        if (i >= nq) continue;
+        const float thr = s_thr[i];
+        const bool valid = leaf < a.n_leaves && !(leaf >= s_home[i][0] && leaf < s_home[i][1]);
+        bool keep = false;
+        float lb = 0.f;
+        if (valid) {
+            lb = leaf_bound(a, leaf, pu[i], pl[i], lo_e[i], hi_e[i]);
+            keep = lb * a.lb_scale <= thr;
+        }
+        if (keep) {
             // thr may be 0 (an exact duplicate) or +inf: keep the bin index in range
             const float f = thr > 0.f ? lb / thr * (float)kLeafBins : 0.f;
             const int bin = f < (float)(kLeafBins - 1) ? (int)f : kLeafBins - 1;
-            atomicAdd(&hist[bin], 1u);
+            atomicAdd(&hist[i][bin], 1u);
         }
+        const unsigned long long km = __ballot(keep), vm = __ballot(valid);
+        if (km) {
+            int base = 0;
+            if (lane == 0) base = (int)atomicAdd(&s_kept[i], (unsigned)__popcll(km));
+            base = __shfl(base, 0, 64);
+            if (keep) slot[i] = base + __popcll(km & lt);
+        }
+        lbs[i] = lb;
+        if (lane == 0 && vm) atomicAdd(&s_valid[i], (unsigned)__popcll(vm));
     }
     __syncthreads();
-    if (threadIdx.x < kLeafBins && hist[threadIdx.x])
-        atomicAdd(a.leaf_hist + (int64_t)q * kLeafBins + threadIdx.x, hist[threadIdx.x]);
+    // one atomic per query and block for the list position, then the entries
+    if (threadIdx.x < nq && s_kept[threadIdx.x])
+        s_base[threadIdx.x] = atomicAdd(a.leaf_count + q0 + threadIdx.x, s_kept[threadIdx.x]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kHistQueries; ++i) {
+        if (slot[i] < 0) continue;
+        const int64_t p = (int64_t)s_base[i] + slot[i];
+        if (p < a.leaf_cap)
+            a.leaf_list[(int64_t)(q0 + i) * a.leaf_cap + p] = make_uint2((unsigned)leaf, __float_as_uint(lbs[i]));
+    }
+    for (int i = 0; i < nq; ++i) {
+        const int q = q0 + i;
+        if (threadIdx.x < kLeafBins && hist[i][threadIdx.x])
+            atomicAdd(a.leaf_hist + (int64_t)q * kLeafBins + threadIdx.x, hist[i][threadIdx.x]);
+    }
+    if (threadIdx.x < nq && s_valid[threadIdx.x])
+        atomicAdd(a.stats + (int64_t)(q0 + threadIdx.x) * ST_N + ST_LEAVES, (unsigned long long)s_valid[threadIdx.x]);
 }
 
 __global__ void k_leaf_theta(QueryArgs a) {
@@ -823,7 +881,7 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
     if (a.done[q]) return;
     const int k = a.kq[q];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t leaf = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t leaf_id = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t h0 = a.home[2 * q], h1 = a.home[2 * q + 1];
 
     for (int s = threadIdx.x; s < a.ns; s += 256) {
@@ -839,13 +897,26 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
     __syncthreads();
 
     float thr = read_tau(a, q, k) * a.tau_scale;
-    const bool valid_leaf = leaf < a.n_leaves && !(leaf >= h0 && leaf < h1);
-    bool keep = false;
-    if (valid_leaf) {
+    // rounds 1 and 2 take the query's leaf list when it holds every leaf within
+    // the first bound (block x = a tile of list entries), else all leaves again
+    const unsigned n_list = a.round != 0 ? a.leaf_count[q] : 0u;
+    const bool from_list = a.round != 0 && n_list <= (uint64_t)a.leaf_cap;
+    bool valid_leaf = false, keep = false;
+    int64_t leaf = leaf_id;
+    if (from_list) {
+        if (leaf_id < (int64_t)n_list) {
+            const uint2 e = a.leaf_list[(int64_t)q * a.leaf_cap + leaf_id];
+            leaf = e.x;
+            const float lb = __uint_as_float(e.y);
+            valid_leaf = true;
+            keep = lb * a.lb_scale <= thr && (a.round == 1 ? lb < a.theta[q] : !(lb < a.theta[q]));
+        }
+    } else if (leaf_id < a.n_leaves && !(leaf_id >= h0 && leaf_id < h1)) {
+        valid_leaf = true;
         if (DTW && a.all_leaves) {
             keep = true;
         } else {
-            const float lb = leaf_bound(a, leaf, pu, pl, lo_e, hi_e);
+            const float lb = leaf_bound(a, leaf_id, pu, pl, lo_e, hi_e);
             keep = lb * a.lb_scale <= thr;
             if (a.round == 1) keep = keep && lb < a.theta[q];
             if (a.round == 2) keep = keep && !(lb < a.theta[q]);
@@ -859,7 +930,8 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
         base = __shfl(base, 0, 64);
         if (keep) list[base + __popcll(km & lt)] = (int)leaf;
         if (lane == 0) {
-            if (a.round != 1) atomicAdd(&s_st[ST_LEAVES], (unsigned long long)__popcll(vm));
+            // the leaf pass before the rounds counted every leaf bound
+            if (a.round == 0) atomicAdd(&s_st[ST_LEAVES], (unsigned long long)__popcll(vm));
             atomicAdd(&s_st[ST_LEAVES_KEPT], (unsigned long long)__popcll(km));
         }
     }
@@ -1361,7 +1433,8 @@ void launch_scatter_answers(const int64_t* ids, const float* dists, const int32_
 void launch_leaf_order(const QueryArgs& a, hipStream_t s) {
     ProfScope ps("leaf_order", s);
     ISAX_HIP(hipMemsetAsync(a.leaf_hist, 0, (size_t)a.mq * kLeafBins * sizeof(unsigned), s));
-    const dim3 grid((unsigned)((a.n_leaves + 255) / 256), (unsigned)a.mq);
+    ISAX_HIP(hipMemsetAsync(a.leaf_count, 0, (size_t)a.mq * sizeof(unsigned), s));
+    const dim3 grid((unsigned)((a.n_leaves + 255) / 256), (unsigned)((a.mq + kHistQueries - 1) / kHistQueries));
     k_leaf_hist<<<grid, 256, 0, s>>>(a);
     k_leaf_theta<<<(a.mq + 255) / 256, 256, 0, s>>>(a);
     ISAX_HIP(hipGetLastError());
@@ -1388,7 +1461,8 @@ void launch_index_scan_t(const QueryArgs& a, const dim3& grid, hipStream_t s) {
 void launch_index_scan(const QueryArgs& a, hipStream_t s) {
     ProfScope ps(a.metric == ISAX_METRIC_DTW ? "dtw_scan" : "index_scan", s);
     const bool dtw = a.metric == ISAX_METRIC_DTW;
-    const dim3 grid((unsigned)((a.n_leaves + 255) / 256), (unsigned)a.mq);
+    const int64_t gx = a.round != 0 && a.grid_leaves > 0 ? a.grid_leaves : (a.n_leaves + 255) / 256;
+    const dim3 grid((unsigned)gx, (unsigned)a.mq);
     const bool vec = a.len % 4 == 0 && (reinterpret_cast<uintptr_t>(a.data) & 15) == 0;
     const bool tl = a.w * a.ns * 4 <= kTableLdsMax && scan_smem(a.ns, a.w, a.len, dtw, true).total <= 64 * 1024;
     ISAX_REQUIRE(scan_smem(a.ns, a.w, a.len, dtw, tl).total <= 64 * 1024, "series too long for the scan's LDS plan");

@@ -277,7 +277,8 @@ struct Batch {
     QueryArgs a;
     int fcap0 = 0;              // initial filter-candidate capacity (0: default)
     int mode = ISAX_MODE_INDEX; // the mode the batch ran in
-    bool hist_valid = false;    // leaf_hist holds the best-first histogram of every query
+    bool hist_valid = false;    // leaf_count / leaf_list hold the leaf pass of every query
+    DevBuf list_mem;            // leaf lists of the best-first rounds
     // hybrid batches: positions handed to the filter, the per-query skip flags
     // (1 = filter), and the filter's sub-batch with its gathered rows
     std::vector<int32_t> far;
@@ -355,6 +356,7 @@ void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const 
     ar.add(&a.status, mq);
     ar.add(&a.theta, mq);
     ar.add(&a.leaf_hist, (size_t)mq * kLeafBins);
+    ar.add(&a.leaf_count, mq);
     ar.add(&a.env_paa, (size_t)mq * 2 * idx->w);
     if (metric == ISAX_METRIC_DTW) ar.add(&a.qenv, (size_t)mq * 2 * idx->len);
     b.mem = ar.commit(s);
@@ -364,13 +366,27 @@ constexpr int kDefaultCap = 16384;
 
 std::vector<int64_t> leaves_initial(const Batch& b, hipStream_t s) {
     const int mq = b.a.mq;
-    std::vector<unsigned> h((size_t)mq * kLeafBins);
-    ISAX_HIP(hipMemcpyAsync(h.data(), b.a.leaf_hist, h.size() * 4, hipMemcpyDeviceToHost, s));
+    std::vector<unsigned> h(mq);
+    ISAX_HIP(hipMemcpyAsync(h.data(), b.a.leaf_count, mq * sizeof(unsigned), hipMemcpyDeviceToHost, s));
     ISAX_HIP(hipStreamSynchronize(s));
-    std::vector<int64_t> c(mq, 0);
-    for (int i = 0; i < mq; ++i)
-        for (int j = 0; j < kLeafBins; ++j) c[i] += h[(size_t)i * kLeafBins + j];
-    return c;
+    return std::vector<int64_t>(h.begin(), h.end());
+}
+
+// Leaf lists kept per query by the leaf pass: every leaf within the first
+// bound when there are at most this many, else the rounds bound all leaves.
+constexpr int64_t kLeafListMax = 32768;
+
+// The leaf pass of the best-first rounds (histogram, theta, leaf lists).
+void leaf_pass(Batch& b, int64_t cap, hipStream_t s) {
+    QueryArgs& a = b.a;
+    a.leaf_cap = std::max<int64_t>(1, std::min<int64_t>(cap, std::min<int64_t>(a.n_leaves, kLeafListMax)));
+    b.list_mem = DevBuf((size_t)a.mq * a.leaf_cap * sizeof(uint2), s);
+    a.leaf_list = b.list_mem.as<uint2>();
+    launch_leaf_order(a, s);
+    b.hist_valid = true;
+    // envelopes once per block of queries, list entries written
+    if (profiling_on())
+        profile_add_bytes("leaf_order", 2.0 * a.ws * a.n_leaves * ((a.mq + kHistQueries - 1) / kHistQueries));
 }
 
 void fill_stats(const Batch& b, isax_query_stats* out, hipStream_t s) {
@@ -411,17 +427,23 @@ void fill_stats(const Batch& b, isax_query_stats* out, hipStream_t s) {
     }
 }
 
-// Algorithmic bytes of the iSAX scan for one batch: 2 * word stride per leaf
-// bounded (envelope), word stride per series bounded, refinement bytes read.
-double scan_bytes(const Batch& b, const isax_index* idx, hipStream_t s) {
+// Algorithmic bytes of the iSAX scan for one batch: per leaf, its envelope
+// (2 * word stride) for every pass that bounds it, or its list entry (8 bytes)
+// for each of the two rounds; word stride per series bounded; refinement
+// bytes read.  `cnt` holds the leaf pass's counts (empty: one pass, no lists).
+double scan_bytes(const Batch& b, const isax_index* idx, hipStream_t s, const std::vector<int64_t>& cnt,
+                  const std::vector<int>& skip) {
     const int mq = b.a.mq;
     std::vector<unsigned long long> st((size_t)mq * ST_N);
     ISAX_HIP(hipMemcpyAsync(st.data(), b.a.stats, st.size() * 8, hipMemcpyDeviceToHost, s));
     ISAX_HIP(hipStreamSynchronize(s));
     double tot = 0;
     for (int i = 0; i < mq; ++i) {
+        if (!skip.empty() && skip[i]) continue;
         const unsigned long long* r = &st[(size_t)i * ST_N];
-        tot += 2.0 * idx->ws * r[ST_LEAVES] + (double)idx->ws * r[ST_SERIES_LB] + (double)r[ST_REFINE_BYTES];
+        double leaf_bytes = 2.0 * idx->ws * r[ST_LEAVES];
+        if (!cnt.empty()) leaf_bytes = cnt[i] <= b.a.leaf_cap ? 16.0 * cnt[i] : 2.0 * leaf_bytes;
+        tot += leaf_bytes + (double)idx->ws * r[ST_SERIES_LB] + (double)r[ST_REFINE_BYTES];
     }
     return tot;
 }
@@ -430,21 +452,33 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s);  // d
 void finish_batch(isax_index* idx, Batch& b, int mode, hipStream_t s);
 void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s, int64_t hybrid_limit = 0);
 
-// The iSAX scan after qprep and homeleaf (and the leaf histogram, for the
-// best-first rounds): one pass in layout order, or round 1 then round 2.
-void index_rounds(isax_index* idx, Batch& b, hipStream_t s) {
+// The iSAX scan after qprep and homeleaf (and the leaf pass, for the
+// best-first rounds): one pass in layout order, or round 1 then round 2 over
+// the leaf lists.  `cnt` holds the leaf pass's counts; queries with skip set
+// are not scanned.
+void index_rounds(isax_index* idx, Batch& b, hipStream_t s, const std::vector<int64_t>& cnt,
+                  const std::vector<int>& skip) {
     QueryArgs& a = b.a;
     if (a.flags & ISAX_QF_NO_BEST_FIRST) {
         a.round = 0;
         launch_index_scan(a, s);
     } else {
-        a.round = 1;
-        launch_index_scan(a, s);
-        a.round = 2;
-        launch_index_scan(a, s);
+        // blocks per query: enough for the longest list, or every leaf for a
+        // query whose list did not fit
+        const int64_t full = (a.n_leaves + 255) / 256;
+        int64_t g = 0;
+        for (int q = 0; q < a.mq; ++q)
+            if (skip.empty() || !skip[q]) g = std::max(g, cnt[q] <= a.leaf_cap ? (cnt[q] + 255) / 256 : full);
+        a.grid_leaves = g;
+        if (g > 0) {
+            a.round = 1;
+            launch_index_scan(a, s);
+            a.round = 2;
+            launch_index_scan(a, s);
+        }
     }
     if (profiling_on())
-        profile_add_bytes(a.metric == ISAX_METRIC_DTW ? "dtw_scan" : "index_scan", scan_bytes(b, idx, s));
+        profile_add_bytes(a.metric == ISAX_METRIC_DTW ? "dtw_scan" : "index_scan", scan_bytes(b, idx, s, cnt, skip));
 }
 
 // Hybrid batch: the leaf histogram of the iSAX path counts, for every query,
@@ -456,8 +490,7 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     QueryArgs& a = b.a;
     launch_qprep(a, s);
     launch_homeleaf(a, s);
-    launch_leaf_order(a, s);
-    b.hist_valid = true;
+    leaf_pass(b, limit, s);
     const std::vector<int64_t> cnt = leaves_initial(b, s);
     b.skip.assign(a.mq, 0);
     for (int q = 0; q < a.mq; ++q)
@@ -488,7 +521,7 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
         b.sub->fcap0 = b.fcap0;
     }
     if (mf < a.mq) {
-        index_rounds(idx, b, s);
+        index_rounds(idx, b, s, cnt, b.skip);
         finish_batch(idx, b, ISAX_MODE_INDEX, s);
     }
     if (mf > 0) {
@@ -514,11 +547,12 @@ void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s, int64_t hybri
         launch_index_scan(a, s);
     } else if (mode == ISAX_MODE_INDEX) {
         launch_homeleaf(a, s);
+        std::vector<int64_t> cnt;
         if (!(a.flags & ISAX_QF_NO_BEST_FIRST)) {
-            launch_leaf_order(a, s);
-            b.hist_valid = true;
+            leaf_pass(b, kLeafListMax, s);
+            cnt = leaves_initial(b, s);
         }
-        index_rounds(idx, b, s);
+        index_rounds(idx, b, s, cnt, {});
     } else if (mode == ISAX_MODE_SCAN) {
         launch_seed(a, s);
         launch_brute_scan(a, s);
@@ -777,7 +811,7 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
 int64_t isax::query_scratch_bytes(const isax_index* idx, int mq, int kmax, int mode) {
     const int64_t per_q = idx->w * 4 + idx->ws + 8 + 16 + 2 * idx->ns * 4 + (int64_t)idx->w * idx->ns * 4 + 4 +
                           (int64_t)kmax * 8 + (int64_t)kDefaultCap * 8 + 4 + 16 + ST_N * 8 + 8 + 4 + 4 +
-                          kLeafBins * 4 + 2 * idx->w * 4;
+                          kLeafBins * 4 + 2 * idx->w * 4 + 4;
     int64_t tot = per_q * mq + 16 * 256;
     if (mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8 || mode == ISAX_MODE_HYBRID) {
         const int qpb = filter_queries_per_block(idx->len);
@@ -787,6 +821,8 @@ int64_t isax::query_scratch_bytes(const isax_index* idx, int mq, int kmax, int m
     }
     if (mode == ISAX_MODE_HYBRID)  // the filter's sub-batch: its own per-query state and gathered rows
         tot += per_q * mq + (int64_t)mq * (idx->len * 4 + kmax * 12 + 8);
+    if (mode == ISAX_MODE_INDEX || mode == ISAX_MODE_HYBRID)  // leaf lists of the best-first rounds
+        tot += (int64_t)mq * std::min<int64_t>(idx->n_leaves, kLeafListMax) * 8;
     return tot;
 }
 

@@ -1,9 +1,11 @@
 """Benchmark: exact 1-NN queries/s over 100M x 256 random walks on one MI355X.
 
 One step = one batch of queries answered exactly through the library's C ABI
-(default mode: BF16 matrix-core candidate filter with the proven margin, home
-leaf of the iSAX index for the initial best-so-far, FP32 refinement, top-k with
-the compensated tie guard).  Inputs are resident in HBM before timing.  Also
+(default mode: hybrid.  The home leaf of the iSAX index gives each query its
+initial best-so-far and one leaf pass counts the leaves within it.  Queries
+with few such leaves take the iSAX rounds: leaf lists, series bounds, FP32
+refinement.  The others take the BF16 matrix-core candidate filter with the
+proven margin, then FP32 refinement.  Top-k uses the compensated tie guard.)  Inputs are resident in HBM before timing.  Also
 reported: index build seconds, queries/s of every mode, p50/p99 latency of the
 serving loop, the roofline of the dominant kernel (HIP events inside the
 library, on the stream it runs on), and the CPU oracle timed on a bounded
@@ -38,7 +40,7 @@ def main():
     ap.add_argument("--len", type=int, default=256)
     ap.add_argument("--m", type=int, default=1000)
     ap.add_argument("--k", type=int, default=1)
-    ap.add_argument("--mode", default="bf16", choices=["index", "scan", "bf16", "fp8", "hybrid"])
+    ap.add_argument("--mode", default="hybrid", choices=["index", "scan", "bf16", "fp8", "hybrid"])
     ap.add_argument("--modes", default="index,scan,bf16,fp8", help="modes measured once each besides the timed one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-series", type=int, default=10_000_000)
@@ -47,7 +49,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="instead of the headline: serve 50M x 256 + 20M x 128 at swept Poisson rates")
-    ap.add_argument("--sweep-mode", default="bf16", choices=["index", "scan", "bf16", "fp8", "hybrid"])
+    ap.add_argument("--sweep-mode", default="hybrid", choices=["index", "scan", "bf16", "fp8", "hybrid"])
     ap.add_argument("--precision-report", action="store_true",
                     help="instead of the headline: 10M x 256, batches of 1024, modes and filter error vs FP64")
     ap.add_argument("--sigma-report", action="store_true",
@@ -162,11 +164,11 @@ def main():
     try:
         import hashlib
         cnt = json.load(open(os.path.join(ROOT, "profiles", "hbm_counters_100Mx256_m1000.json")))
-        key = "k_filter" if dom_name.startswith("filter_") else "k_" + dom_name
-        srcf = {"k_filter": "filter_kernels.hip", "k_index_scan": "query_kernels.hip"}.get(key)
-        mode_ok = cnt.get(key, {}).get("mode", "bf16" if key == "k_filter" else "index") == args.mode
-        if (srcf and key in cnt and n == 100_000_000 and m == 1000 and mode_ok and k == 1
-                and (key != "k_filter" or dom_name == "filter_bf16")):
+        kname = "k_filter" if dom_name.startswith("filter_") else "k_" + dom_name
+        srcf = {"k_filter": "filter_kernels.hip", "k_index_scan": "query_kernels.hip"}.get(kname)
+        key = f"{kname}@{args.mode}"  # counters of this kernel in this query mode
+        if (srcf and key in cnt and n == 100_000_000 and m == 1000 and k == 1
+                and (kname != "k_filter" or dom_name == "filter_bf16")):
             with open(os.path.join(ROOT, "paper_2009_01614_amd", "csrc", srcf), "rb") as fh:
                 cur = hashlib.sha256(fh.read()).hexdigest()[:16]
             if cur == cnt[key]["source_sha256_16"]:
@@ -428,8 +430,9 @@ def precision_report(args, dev):
 
 def sigma_report(args, dev):
     """Per-noise-level breakdown at the headline size: the 1000 noisy queries split by
-    sigma (0.01 / 0.1 / 1), each third answered as one batch in the BF16 and index
-    modes at k = 1, 10 and 100, with the index path's pruning statistics."""
+    sigma (0.01 / 0.1 / 1), each third answered as one batch in the BF16, index and
+    hybrid modes at k = 1, 10 and 100, with the index path's pruning statistics and
+    the share of queries the hybrid mode keeps on the index path."""
     import numpy as np
     import torch
 
@@ -448,13 +451,18 @@ def sigma_report(args, dev):
         Qs = Q[sel].contiguous()
         rec = {"queries": int(Qs.shape[0])}
         for k in (1, 10, 100):
-            for mode in ("bf16", "index"):
+            for mode in ("bf16", "index", "hybrid"):
                 idx.query(Qs[:8].contiguous(), k=k, mode=mode)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                res = idx.query(Qs, k=k, mode=mode, stats=(mode == "index"))
+                res = idx.query(Qs, k=k, mode=mode)
                 torch.cuda.synchronize()
                 rec[f"{mode}_k{k}_qps"] = round(Qs.shape[0] / (time.perf_counter() - t0), 1)
+                if mode != "bf16":
+                    res = idx.query(Qs, k=k, mode=mode, stats=True)  # untimed
+                if mode == "hybrid":
+                    rec[f"hybrid_k{k}_index_share"] = round(
+                        float(np.mean([x["path"] == isax.MODE_INDEX for x in res[2]])), 3)
                 if mode == "index":
                     st = res[2]
                     rec[f"index_k{k}_leaves_kept_frac"] = round(

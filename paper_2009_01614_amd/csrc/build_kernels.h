@@ -10,8 +10,10 @@ void launch_make_keys(const uint8_t* words, int64_t n, int ws, int w, int c, int
 void sort_keys(uint64_t* keys, int32_t* ids, int64_t n, int key_bits, hipStream_t s);
 void launch_gather_rows(const float* data, const int32_t* ids, int64_t n, int len, float* out, hipStream_t s);
 void launch_gather_words(const uint8_t* words, const int32_t* ids, int64_t n, int ws, uint8_t* out, hipStream_t s);
+// Leaf keys and envelopes, and the envelopes of nodes of kNodeLeaves leaves.
 void launch_leaf_layout(const uint64_t* keys_sorted, const uint8_t* words_sorted, int64_t n, int ws, int leaf,
-                        int64_t n_leaves, uint64_t* leaf_key, uint8_t* lo, uint8_t* hi, hipStream_t s);
+                        int64_t n_leaves, uint64_t* leaf_key, uint8_t* lo, uint8_t* hi, uint8_t* node_lo,
+                        uint8_t* node_hi, hipStream_t s);
 // kind 0: BF16 copy into xb; kind 1: FP8 E4M3 copy into xf; row p (len_pad wide, zero-padded)
 // holds series ids[p].
 // meta[p] = {|x|^2, |e_x|, |x~|, scale}.

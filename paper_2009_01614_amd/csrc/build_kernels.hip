@@ -346,6 +346,27 @@ __global__ void k_leaf_keys(const uint64_t* __restrict__ keys_sorted, int64_t n_
     if (l < n_leaves) leaf_key[l] = keys_sorted[l * leaf];
 }
 
+// Envelopes of nodes of kNodeLeaves consecutive leaves: per word byte the
+// minimum of the leaves' lower and the maximum of their upper symbols, one
+// thread per (node, byte).
+__global__ void k_node_envelopes(const uint8_t* __restrict__ lo, const uint8_t* __restrict__ hi, int64_t n_leaves,
+                                 int ws, int64_t n_nodes, uint8_t* __restrict__ node_lo,
+                                 uint8_t* __restrict__ node_hi) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_nodes * ws;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t node = t / ws;
+        const int j = (int)(t - node * ws);
+        const int64_t l0 = node * kNodeLeaves, l1 = min(n_leaves, l0 + kNodeLeaves);
+        int mn = 255, mx = 0;
+        for (int64_t l = l0; l < l1; ++l) {
+            mn = min(mn, (int)lo[l * ws + j]);
+            mx = max(mx, (int)hi[l * ws + j]);
+        }
+        node_lo[t] = (uint8_t)mn;
+        node_hi[t] = (uint8_t)mx;
+    }
+}
+
 // One wave per leaf: per-segment min and max symbol of the leaf's words.
 __global__ void __launch_bounds__(256) k_envelopes(const uint8_t* __restrict__ ws_words, int64_t n, int ws, int leaf,
                                                    int64_t n_leaves, uint8_t* __restrict__ lo,
@@ -601,10 +622,13 @@ void launch_gather_rows(const float* data, const int32_t* ids, int64_t n, int le
 }
 
 void launch_leaf_layout(const uint64_t* keys_sorted, const uint8_t* words_sorted, int64_t n, int ws, int leaf,
-                        int64_t n_leaves, uint64_t* leaf_key, uint8_t* lo, uint8_t* hi, hipStream_t s) {
+                        int64_t n_leaves, uint64_t* leaf_key, uint8_t* lo, uint8_t* hi, uint8_t* node_lo,
+                        uint8_t* node_hi, hipStream_t s) {
     ProfScope ps("envelopes", s);
     k_leaf_keys<<<(int)((n_leaves + 255) / 256), 256, 0, s>>>(keys_sorted, n_leaves, leaf, leaf_key);
     k_envelopes<<<grid_blocks(n_leaves, 4), 256, 0, s>>>(words_sorted, n, ws, leaf, n_leaves, lo, hi);
+    const int64_t n_nodes = (n_leaves + kNodeLeaves - 1) / kNodeLeaves;
+    k_node_envelopes<<<grid_blocks(n_nodes * ws, 256), 256, 0, s>>>(lo, hi, n_leaves, ws, n_nodes, node_lo, node_hi);
     ISAX_HIP(hipGetLastError());
 }
 

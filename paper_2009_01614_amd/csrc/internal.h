@@ -39,6 +39,7 @@ void clear_error();
 constexpr int kWaveSize = 64;
 constexpr int kMaxCandLds = 4096;   // candidates one top-k block sorts in LDS
 constexpr int kMaxLeaf = 1024;
+constexpr int kNodeLeaves = 64;     // leaves per node of the two-level envelope (one wave of the leaf pass)
 
 inline int word_stride(int w) { return (w + 15) / 16 * 16; }
 
@@ -121,6 +122,9 @@ struct isax_index {
     uint8_t* env_lo = nullptr;      // [n_leaves][ws]
     uint8_t* env_hi = nullptr;      // [n_leaves][ws]
     uint64_t* leaf_key = nullptr;   // [n_leaves] first key of each leaf
+    uint8_t* node_lo = nullptr;     // [n_nodes][ws] envelope of leaves [i * kNodeLeaves, (i + 1) * kNodeLeaves)
+    uint8_t* node_hi = nullptr;     // [n_nodes][ws]
+    int64_t n_nodes = 0;
     // reduced-precision copies for the dot-product filter
     float* xs = nullptr;            // [n][len] FP32 rows in leaf order (optional copy)
     uint16_t* x_bf16 = nullptr;     // [n][len] BF16 bits

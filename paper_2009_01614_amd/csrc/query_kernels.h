@@ -20,6 +20,9 @@ struct QueryArgs {
     const int32_t* ids_sorted;
     const uint8_t* env_lo;
     const uint8_t* env_hi;
+    const uint8_t* node_lo;     // [n_nodes][ws] envelopes of kNodeLeaves consecutive leaves
+    const uint8_t* node_hi;
+    int64_t n_nodes;
     const uint64_t* leaf_key;
     const float* beta;
     float delta_x;
@@ -78,6 +81,7 @@ __device__ inline const float* series_row(const QueryArgs& a, int64_t p, int32_t
 constexpr int kLeafBins = 64;
 constexpr int kFirstLeaves = 64;  // leaves refined first, by smallest lower bound
 constexpr int kHistQueries = 4;   // queries per block of the leaf pass
+constexpr int kHistLeafRounds = 4; // leaves per thread of the leaf pass
 
 void launch_check_finite(const float* x, int64_t count, int* flag, hipStream_t s);
 void launch_qprep(const QueryArgs& a, hipStream_t s);

@@ -681,10 +681,8 @@ __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
 // distance from the query segment [pl_j, pu_j] (ED: the PAA point) to
 // [widened lower edge of lo, widened upper edge of hi] (the iSAX MINDIST of
 // the union of the leaf's regions).
-__device__ inline float leaf_bound(const QueryArgs& a, int64_t leaf, const float* pu, const float* pl,
-                                   const float* lo_e, const float* hi_e) {
-    const uint8_t* el = a.env_lo + leaf * a.ws;
-    const uint8_t* eh = a.env_hi + leaf * a.ws;
+__device__ inline float env_bound(const QueryArgs& a, const uint8_t* el, const uint8_t* eh, const float* pu,
+                                  const float* pl, const float* lo_e, const float* hi_e) {
     float lb = 0.f;
     for (int qc = 0; qc < a.ws / 16; ++qc) {
         const uint4 vl = reinterpret_cast<const uint4*>(el)[qc];
@@ -704,6 +702,10 @@ __device__ inline float leaf_bound(const QueryArgs& a, int64_t leaf, const float
     }
     return lb * (float)a.m_seg;
 }
+__device__ inline float leaf_bound(const QueryArgs& a, int64_t leaf, const float* pu, const float* pl,
+                                   const float* lo_e, const float* hi_e) {
+    return env_bound(a, a.env_lo + leaf * a.ws, a.env_hi + leaf * a.ws, pu, pl, lo_e, hi_e);
+}
 
 // Best-first order (MESSI's priority queues, by rounds): the bound of every
 // leaf against the best-so-far of the approximate answer.  Per query: a
@@ -712,19 +714,26 @@ __device__ inline float leaf_bound(const QueryArgs& a, int64_t leaf, const float
 // first leaf_cap of them).  theta[q] = the lowest bin edge below which at least
 // kFirstLeaves leaves lie; round 1 refines the listed leaves below theta, which
 // lowers the best-so-far before round 2 takes the rest of the list.  A block
-// takes 256 leaves of kHistQueries queries, so the envelope tile is read once
-// for all of them.
+// takes 256 kHistLeafRounds leaves of kHistQueries queries: the queries'
+// tables are loaded once for all those leaves.  The block first bounds its
+// nodes (the envelope of 64 leaves, an inner node of the tree; one wave's
+// leaves): the bound of a leaf is at least that of its node in FP32 too (every
+// step is monotone in the envelope), so a node above the best-so-far rules
+// out its leaves without bounding them.
+static_assert(kNodeLeaves == 64, "a node of the leaf pass is the 64 leaves of one wave");
 __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
-    __shared__ float lo_e[kHistQueries][256], hi_e[kHistQueries][256], pu[kHistQueries][64], pl[kHistQueries][64];
-    __shared__ unsigned hist[kHistQueries][kLeafBins];
-    __shared__ float s_thr[kHistQueries];
-    __shared__ int64_t s_home[kHistQueries][2];
-    __shared__ unsigned s_valid[kHistQueries], s_kept[kHistQueries], s_base[kHistQueries];
-    const int q0 = blockIdx.y * kHistQueries;
-    const int nq = min(kHistQueries, a.mq - q0);
+    constexpr int QB = kHistQueries, R = kHistLeafRounds;
+    __shared__ float lo_e[QB][256], hi_e[QB][256], pu[QB][64], pl[QB][64];
+    __shared__ unsigned hist[QB][kLeafBins];
+    __shared__ float s_thr[QB];
+    __shared__ int64_t s_home[QB][2];
+    __shared__ unsigned s_valid[QB], s_kept[QB], s_base[QB];
+    __shared__ unsigned char s_node_in[QB][4 * R];
+    const int q0 = blockIdx.y * QB;
+    const int nq = min(QB, a.mq - q0);
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const int64_t leaf = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t base_leaf = (int64_t)blockIdx.x * 256 * R;
     for (int i = 0; i < nq; ++i) {
         const int q = q0 + i;
         for (int s = threadIdx.x; s < a.ns; s += 256) {
@@ -746,37 +755,54 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
         s_kept[threadIdx.x] = 0u;
     }
     __syncthreads();
-    // per query: the bound, and the slot of a kept leaf among the block's kept leaves
-    float lbs[kHistQueries];
-    int slot[kHistQueries];
+    // node bounds, one (query, node) pair per thread
+    if (threadIdx.x < QB * 4 * R) {
+        const int i = threadIdx.x / (4 * R), nd = threadIdx.x % (4 * R);
+        const int64_t node = base_leaf / kNodeLeaves + nd;
+        bool in = false;
+        if (i < nq && node < a.n_nodes)
+            in = env_bound(a, a.node_lo + node * a.ws, a.node_hi + node * a.ws, pu[i], pl[i], lo_e[i], hi_e[i]) *
+                     a.lb_scale <= s_thr[i];
+        s_node_in[i][nd] = in;
+    }
+    __syncthreads();
+    // per (query, leaf of this thread): the bound, and the slot of a kept leaf
+    // among the block's kept leaves of that query
+    float lbs[QB][R];
+    int slot[QB][R];
 #pragma unroll
-    for (int i = 0; i < kHistQueries; ++i) {
-        slot[i] = -1;
-        lbs[i] = 0.f;
-        if (i >= nq) continue;
-        const float thr = s_thr[i];
-        const bool valid = leaf < a.n_leaves && !(leaf >= s_home[i][0] && leaf < s_home[i][1]);
-        bool keep = false;
-        float lb = 0.f;
-        if (valid) {
-            lb = leaf_bound(a, leaf, pu[i], pl[i], lo_e[i], hi_e[i]);
-            keep = lb * a.lb_scale <= thr;
+    for (int i = 0; i < QB; ++i) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            slot[i][r] = -1;
+            lbs[i][r] = 0.f;
+            if (i >= nq) continue;
+            const float thr = s_thr[i];
+            const int64_t leaf = base_leaf + r * 256 + threadIdx.x;
+            const bool valid = leaf < a.n_leaves && !(leaf >= s_home[i][0] && leaf < s_home[i][1]);
+            const bool node_in = s_node_in[i][r * 4 + (threadIdx.x >> 6)];  // the same in every lane of the wave
+            bool keep = false;
+            float lb = 0.f;
+            if (valid && node_in) {
+                lb = leaf_bound(a, leaf, pu[i], pl[i], lo_e[i], hi_e[i]);
+                keep = lb * a.lb_scale <= thr;
+            }
+            if (keep) {
+                // thr may be 0 (an exact duplicate) or +inf: keep the bin index in range
+                const float f = thr > 0.f ? lb / thr * (float)kLeafBins : 0.f;
+                const int bin = f < (float)(kLeafBins - 1) ? (int)f : kLeafBins - 1;
+                atomicAdd(&hist[i][bin], 1u);
+            }
+            const unsigned long long km = __ballot(keep), vm = __ballot(valid);
+            if (km) {
+                int b = 0;
+                if (lane == 0) b = (int)atomicAdd(&s_kept[i], (unsigned)__popcll(km));
+                b = __shfl(b, 0, 64);
+                if (keep) slot[i][r] = b + __popcll(km & lt);
+            }
+            lbs[i][r] = lb;
+            if (lane == 0 && vm) atomicAdd(&s_valid[i], (unsigned)__popcll(vm));
         }
-        if (keep) {
-            // thr may be 0 (an exact duplicate) or +inf: keep the bin index in range
-            const float f = thr > 0.f ? lb / thr * (float)kLeafBins : 0.f;
-            const int bin = f < (float)(kLeafBins - 1) ? (int)f : kLeafBins - 1;
-            atomicAdd(&hist[i][bin], 1u);
-        }
-        const unsigned long long km = __ballot(keep), vm = __ballot(valid);
-        if (km) {
-            int base = 0;
-            if (lane == 0) base = (int)atomicAdd(&s_kept[i], (unsigned)__popcll(km));
-            base = __shfl(base, 0, 64);
-            if (keep) slot[i] = base + __popcll(km & lt);
-        }
-        lbs[i] = lb;
-        if (lane == 0 && vm) atomicAdd(&s_valid[i], (unsigned)__popcll(vm));
     }
     __syncthreads();
     // one atomic per query and block for the list position, then the entries
@@ -784,11 +810,15 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
         s_base[threadIdx.x] = atomicAdd(a.leaf_count + q0 + threadIdx.x, s_kept[threadIdx.x]);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kHistQueries; ++i) {
-        if (slot[i] < 0) continue;
-        const int64_t p = (int64_t)s_base[i] + slot[i];
-        if (p < a.leaf_cap)
-            a.leaf_list[(int64_t)(q0 + i) * a.leaf_cap + p] = make_uint2((unsigned)leaf, __float_as_uint(lbs[i]));
+    for (int i = 0; i < QB; ++i) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (slot[i][r] < 0) continue;
+            const int64_t p = (int64_t)s_base[i] + slot[i][r];
+            if (p < a.leaf_cap)
+                a.leaf_list[(int64_t)(q0 + i) * a.leaf_cap + p] =
+                    make_uint2((unsigned)(base_leaf + r * 256 + threadIdx.x), __float_as_uint(lbs[i][r]));
+        }
     }
     for (int i = 0; i < nq; ++i) {
         const int q = q0 + i;
@@ -1434,7 +1464,9 @@ void launch_leaf_order(const QueryArgs& a, hipStream_t s) {
     ProfScope ps("leaf_order", s);
     ISAX_HIP(hipMemsetAsync(a.leaf_hist, 0, (size_t)a.mq * kLeafBins * sizeof(unsigned), s));
     ISAX_HIP(hipMemsetAsync(a.leaf_count, 0, (size_t)a.mq * sizeof(unsigned), s));
-    const dim3 grid((unsigned)((a.n_leaves + 255) / 256), (unsigned)((a.mq + kHistQueries - 1) / kHistQueries));
+    const int64_t per_block = 256 * kHistLeafRounds;
+    const dim3 grid((unsigned)((a.n_leaves + per_block - 1) / per_block),
+                    (unsigned)((a.mq + kHistQueries - 1) / kHistQueries));
     k_leaf_hist<<<grid, 256, 0, s>>>(a);
     k_leaf_theta<<<(a.mq + 255) / 256, 256, 0, s>>>(a);
     ISAX_HIP(hipGetLastError());

@@ -244,8 +244,11 @@ isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int
     idx->leaf_key = own<uint64_t>(idx.get(), idx->n_leaves);
     idx->env_lo = own<uint8_t>(idx.get(), (size_t)idx->n_leaves * ws);
     idx->env_hi = own<uint8_t>(idx.get(), (size_t)idx->n_leaves * ws);
+    idx->n_nodes = (idx->n_leaves + kNodeLeaves - 1) / kNodeLeaves;
+    idx->node_lo = own<uint8_t>(idx.get(), (size_t)idx->n_nodes * ws);
+    idx->node_hi = own<uint8_t>(idx.get(), (size_t)idx->n_nodes * ws);
     launch_leaf_layout(keys.as<uint64_t>(), idx->words_sorted, n, ws, leaf, idx->n_leaves, idx->leaf_key, idx->env_lo,
-                       idx->env_hi, s);
+                       idx->env_hi, idx->node_lo, idx->node_hi, s);
     ISAX_REQUIRE((o.precision & 3) == 0 || len <= 512, "the reduced-precision copies support len <= 512");
     if (o.precision & 4) {
         idx->xs = own<float>(idx.get(), (size_t)n * len);
@@ -318,6 +321,9 @@ void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const 
     a.ids_sorted = idx->ids_sorted;
     a.env_lo = idx->env_lo;
     a.env_hi = idx->env_hi;
+    a.node_lo = idx->node_lo;
+    a.node_hi = idx->node_hi;
+    a.n_nodes = idx->n_nodes;
     a.leaf_key = idx->leaf_key;
     a.beta = idx->beta;
     a.delta_x = idx->delta;
@@ -384,7 +390,7 @@ void leaf_pass(Batch& b, int64_t cap, hipStream_t s) {
     a.leaf_list = b.list_mem.as<uint2>();
     launch_leaf_order(a, s);
     b.hist_valid = true;
-    // envelopes once per block of queries, list entries written
+    // leaf envelopes once per block of queries
     if (profiling_on())
         profile_add_bytes("leaf_order", 2.0 * a.ws * a.n_leaves * ((a.mq + kHistQueries - 1) / kHistQueries));
 }

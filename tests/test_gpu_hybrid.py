@@ -141,3 +141,21 @@ def test_hybrid_small_collection_and_errors(isax):
         idx.query(Q, k=1, mode="hybrid", metric="dtw", window=3)
     ids, _ = idx.query(Q[:0], k=1, mode="hybrid")
     assert ids.shape == (0, 1)
+
+
+@pytest.mark.parametrize("k", [1, 10])
+def test_leaves_initial_matches_oracle_envelope_bounds(isax, coll, k):
+    # the leaf pass (with its node-level pruning) counts the leaves whose FP64 envelope
+    # MINDIST is within the first best-so-far, up to the home leaf and rounding at the edge
+    from oracle import isax_ref as ir
+    idx, Q = coll["idx"], coll["Q"]
+    _, _, st = idx.query(Q, k=k, mode="index", stats=True)
+    _, _, lo, hi = (_cpu(t) for t in idx.export())
+    paa = ir.paa64(_cpu(Q), 16)
+    beta = ir.breakpoints(8)
+    for j, s in enumerate(st):
+        lb = ir.envelope_mindist_sq(paa[j], lo, hi, beta, 256 // 16)
+        tau = float(s["tau_initial"])
+        low = int((lb <= tau * (1 - 1e-4)).sum()) - 4
+        high = int((lb <= tau * (1 + 1e-3) + 1e-6).sum())
+        assert low <= s["leaves_initial"] <= high, (j, low, s["leaves_initial"], high)

@@ -78,11 +78,14 @@ bool profiling_on();
 void profile_add_bytes(const char* name, double bytes);
 
 // ------------------------------------------------------------------ device scratch
-// Stream-ordered device allocation that is released when the object dies.
+// Stream-ordered device scratch, released when the object dies.  Blocks of
+// 1 MiB to 1 GiB come from the library's block cache (kept after release,
+// reused in stream order), others from hipMallocAsync / hipFreeAsync.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
+    bool cached = false;
     DevBuf() = default;
     DevBuf(size_t n, hipStream_t s);
     ~DevBuf();

@@ -82,8 +82,112 @@ void profile_add_bytes(const char* name, double bytes) {
 }
 
 // ------------------------------------------------------------------ memory
+// Block cache for query scratch.  A query call allocates and releases several
+// blocks of tens to hundreds of MB (candidate lists, leaf lists, filter
+// candidates); through the stream-ordered allocator each such allocation or
+// release costs tens to hundreds of microseconds, about a millisecond per call.
+// Released blocks therefore stay allocated and are handed out again: on the
+// stream that released a block, stream order protects its reuse; another
+// stream first waits for the event recorded at the release.  Idle blocks above
+// kCacheIdleMax bytes per device are freed, least recently used first.
+namespace {
+constexpr size_t kCacheMin = size_t(1) << 20, kCacheMax = size_t(1) << 30, kCacheIdleMax = size_t(4) << 30;
+constexpr size_t kCacheGranule = size_t(2) << 20;
+struct CacheBlock {
+    void* p;
+    size_t bytes;
+    int device;
+    hipStream_t stream;  // stream of the last release
+    hipEvent_t ready;    // recorded on that stream at the release
+    bool in_use;
+    uint64_t last_use;
+};
+std::mutex g_cache_mu;
+std::vector<CacheBlock> g_cache;
+uint64_t g_cache_tick = 0;
+
+// Free idle blocks of `dev` (least recently used first) until at most `keep`
+// idle bytes remain.  Caller holds g_cache_mu.
+void cache_trim_locked(int dev, size_t keep) {
+    for (;;) {
+        size_t idle = 0;
+        int lru = -1;
+        for (int i = 0; i < (int)g_cache.size(); ++i) {
+            const CacheBlock& b = g_cache[i];
+            if (b.in_use || b.device != dev) continue;
+            idle += b.bytes;
+            if (lru < 0 || b.last_use < g_cache[lru].last_use) lru = i;
+        }
+        if (idle <= keep || lru < 0) return;
+        CacheBlock b = g_cache[lru];
+        g_cache.erase(g_cache.begin() + lru);
+        (void)hipEventSynchronize(b.ready);
+        (void)hipEventDestroy(b.ready);
+        (void)hipFree(b.p);
+    }
+}
+
+void* cache_alloc(size_t n, hipStream_t s) {
+    int dev = 0;
+    ISAX_HIP(hipGetDevice(&dev));
+    const size_t want = (n + kCacheGranule - 1) / kCacheGranule * kCacheGranule;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int best = -1;
+    for (int i = 0; i < (int)g_cache.size(); ++i) {
+        const CacheBlock& b = g_cache[i];
+        if (!b.in_use && b.device == dev && b.bytes >= want && b.bytes <= 2 * want &&
+            (best < 0 || b.bytes < g_cache[best].bytes))
+            best = i;
+    }
+    if (best >= 0) {
+        CacheBlock& b = g_cache[best];
+        if (b.stream != s) ISAX_HIP(hipStreamWaitEvent(s, b.ready, 0));
+        b.in_use = true;
+        b.stream = s;
+        b.last_use = ++g_cache_tick;
+        return b.p;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        cache_trim_locked(dev, 0);
+        e = hipMalloc(&p, want);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{ISAX_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed: " + hipGetErrorString(e)};
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipFree(p);
+        throw Error{ISAX_EDEVICE, "event creation failed"};
+    }
+    g_cache.push_back({p, want, dev, s, ev, true, ++g_cache_tick});
+    return p;
+}
+
+void cache_free(void* p, hipStream_t s) noexcept {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (CacheBlock& b : g_cache)
+        if (b.p == p) {
+            (void)hipEventRecord(b.ready, s);
+            b.stream = s;
+            b.in_use = false;
+            b.last_use = ++g_cache_tick;
+            cache_trim_locked(b.device, kCacheIdleMax);
+            return;
+        }
+}
+}  // namespace
+
 DevBuf::DevBuf(size_t n, hipStream_t s) : bytes(n), stream(s) {
     if (n == 0) return;
+    if (n >= kCacheMin && n <= kCacheMax) {
+        p = cache_alloc(n, s);
+        cached = true;
+        return;
+    }
     const hipError_t e = hipMallocAsync(&p, n, s);
     if (e != hipSuccess) {
         p = nullptr;
@@ -91,16 +195,23 @@ DevBuf::DevBuf(size_t n, hipStream_t s) : bytes(n), stream(s) {
     }
 }
 DevBuf::~DevBuf() {
-    if (p) (void)hipFreeAsync(p, stream);
+    if (!p) return;
+    if (cached) cache_free(p, stream);
+    else (void)hipFreeAsync(p, stream);
 }
 DevBuf& DevBuf::operator=(DevBuf&& o) noexcept {
     if (this != &o) {
-        if (p) (void)hipFreeAsync(p, stream);
+        if (p) {
+            if (cached) cache_free(p, stream);
+            else (void)hipFreeAsync(p, stream);
+        }
         p = o.p;
         bytes = o.bytes;
         stream = o.stream;
+        cached = o.cached;
         o.p = nullptr;
         o.bytes = 0;
+        o.cached = false;
     }
     return *this;
 }

@@ -135,8 +135,7 @@ def main():
     if args.mode == "hybrid":
         _, _, st = idx.query(Q, k=k, mode="hybrid", stream=stream, stats=True)
         m_filter = sum(1 for x in st if x["path"] == isax.MODE_BF16)
-        split = {"index": m - m_filter, "bf16": m_filter,
-                 "hybrid_leaves": max(1, idx.info()["n_leaves"] // 32)}
+        split = {"index": m - m_filter, "bf16": m_filter}
         log(f"hybrid split: {split}")
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     avg_ms = dom["total_ms"] / max(dom["launches"], 1)
@@ -315,7 +314,7 @@ def serving_sweep(args, dev):
     import workload
 
     mode = args.sweep_mode
-    prec = {"bf16": 1, "fp8": 2}.get(mode, 0)
+    prec = {"bf16": 1, "fp8": 2, "hybrid": 1}.get(mode, 0)
     log("generating 50M x 256 and 20M x 128")
     cols = [workload.random_walks(50_000_000, 256, seed=20090165, device=dev),
             workload.random_walks(20_000_000, 128, seed=20090166, device=dev)]

@@ -52,9 +52,9 @@ enum {
     ISAX_MODE_SCAN = 1,  /* plain FP32 scan of every series (the sequential-scan baseline, Sec. I) */
     ISAX_MODE_BF16 = 2,  /* BF16 matrix-core dot-product filter with a proven error margin, FP32 refinement */
     ISAX_MODE_FP8 = 3,   /* FP8 E4M3 (power-of-two scale per series) filter, same margin rule */
-    ISAX_MODE_HYBRID = 4 /* per query: the iSAX path when at most hybrid_leaves leaves have a lower bound
-                            within the approximate answer's best-so-far (the pruning of Sec. III will
-                            leave little to refine), else the BF16 filter; needs the BF16 copy, ED only */
+    ISAX_MODE_HYBRID = 4 /* per query, the iSAX path or the BF16 filter, by the leaves the iSAX path would
+                            still have to bound after its first best-first round (Sec. III pruning)
+                            against the filter's cost (hybrid_leaves); needs the BF16 copy, ED only */
 };
 
 /* Query flags (isax_query_options.flags): switches for testing; the answer never changes. */
@@ -121,8 +121,12 @@ typedef struct isax_query_options {
     isax_query_stats* stats;    /* host, m entries, or NULL */
     int32_t metric;             /* ISAX_METRIC_*; DTW runs in ISAX_MODE_INDEX and ISAX_MODE_SCAN only */
     int32_t window;             /* DTW band half-width, 0..min(ISAX_MAX_WINDOW, len-1); must be 0 for ED */
-    int64_t hybrid_leaves;      /* ISAX_MODE_HYBRID: the largest leaves_initial answered by the iSAX path;
-                                   0 = max(1, n_leaves / 32); must be >= 0 */
+    int64_t hybrid_leaves;      /* ISAX_MODE_HYBRID, >= 0.  est = leaves left for the second round (bound at
+                                   least the first round's threshold, within the best-so-far after it; for a
+                                   query with more than 32768 leaves within the first bound, that count).
+                                   > 0: queries with est above it take the filter.  0: a cost model chooses
+                                   the queries of largest est for the filter when its pass over the whole
+                                   collection costs less than the index work they would leave. */
 } isax_query_options;
 
 /* Last error message of the calling thread ("" if none). Static storage, thread-local. */

@@ -241,8 +241,9 @@ class Index:
         """Exact k-NN: (ids int64 [m, k], dists float32 [m, k]); with stats=True also a list of dicts.
 
         metric "ed" (Euclidean) or "dtw" (banded DTW of half-width `window`, modes "index" and "scan").
-        mode "hybrid" answers each query with the iSAX path when at most `hybrid_leaves` leaves
-        (0: the library's default) lie within its first best-so-far, else with the BF16 filter.
+        mode "hybrid" answers each query with the iSAX path or the BF16 filter, by the leaves the iSAX
+        path would still bound after its first round: above `hybrid_leaves`, or (0) by the library's
+        cost model.
         """
         _dev_f32(queries, "queries")
         m = queries.shape[0]

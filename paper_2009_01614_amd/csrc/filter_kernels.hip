@@ -609,6 +609,15 @@ void launch_refine_filtered(const QueryArgs& a, const FilterArgs& f, hipStream_t
     ISAX_HIP(hipGetLastError());
 }
 
+// Query rows the BF16 filter computes for a batch of mq queries: its block
+// class (the dispatch of launch_filter) times the blocks.
+int filter_rows_bf16(int len, int mq) {
+    const int lp = filter_len_pad(len);
+    int qpb = lp <= 256 ? 512 : 256;  // <MT = 2, 8 waves> below 320, <1, 8> from 320
+    if ((lp == 128 || lp == 256) && mq <= 256) qpb = mq <= 64 ? 64 : mq <= 128 ? 128 : 256;
+    return (mq + qpb - 1) / qpb * qpb;
+}
+
 // Query codes are padded to a multiple of 512 rows, a multiple of every
 // configuration's queries per block (64, 128, 256 or 512).
 int filter_queries_per_block(int len) {

@@ -61,6 +61,7 @@ struct QueryArgs {
     unsigned* leaf_count;       // [mq] leaves within the first bound (also those past leaf_cap)
     int64_t leaf_cap;
     int64_t grid_leaves;        // rounds 1 and 2: blocks per query (0: one per 256 leaves)
+    unsigned* list_rest;        // [mq] listed leaves round 2 would still bound (after round 1)
     // distance measure
     int metric;                 // ISAX_METRIC_*
     int window;                 // DTW band half-width r
@@ -88,6 +89,9 @@ void launch_qprep(const QueryArgs& a, hipStream_t s);
 void launch_homeleaf(const QueryArgs& a, hipStream_t s);
 void launch_index_scan(const QueryArgs& a, hipStream_t s);
 void launch_leaf_order(const QueryArgs& a, hipStream_t s);  // histogram of leaf bounds -> theta
+// list_rest[q] = list entries at or above theta still within the best-so-far
+// (queries not done, whose list holds every leaf within the first bound).
+void launch_list_recount(const QueryArgs& a, int64_t grid_x, hipStream_t s);
 void launch_seed(const QueryArgs& a, hipStream_t s);
 void launch_brute_scan(const QueryArgs& a, hipStream_t s);
 void launch_topk(const QueryArgs& a, hipStream_t s);
@@ -118,6 +122,7 @@ struct FilterArgs {
 };
 int filter_len_pad(int len);              // rows of the reduced-precision copies are padded to this
 int filter_queries_per_block(int len);    // query codes are padded to a multiple of this
+int filter_rows_bf16(int len, int mq);    // query rows the BF16 filter computes for mq queries
 void launch_quantise_queries(const QueryArgs& a, const FilterArgs& f, int mq_pad, unsigned* qmax, hipStream_t s);
 void launch_filter(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax, hipStream_t s);
 void launch_refine_filtered(const QueryArgs& a, const FilterArgs& f, hipStream_t s);

@@ -829,6 +829,24 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
         atomicAdd(a.stats + (int64_t)(q0 + threadIdx.x) * ST_N + ST_LEAVES, (unsigned long long)s_valid[threadIdx.x]);
 }
 
+// After round 1: the leaves that round 2 would still take, counted from the
+// list against the lowered best-so-far.
+__global__ void __launch_bounds__(256) k_list_recount(QueryArgs a) {
+    const int q = blockIdx.y;
+    if (a.done[q]) return;
+    const unsigned n = a.leaf_count[q];
+    if ((int64_t)n > a.leaf_cap) return;
+    const float thr = read_tau(a, q, a.kq[q]) * a.tau_scale;
+    const float theta = a.theta[q];
+    unsigned c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < (int64_t)n; i += (int64_t)gridDim.x * 256) {
+        const float lb = __uint_as_float(a.leaf_list[(int64_t)q * a.leaf_cap + i].y);
+        c += (lb * a.lb_scale <= thr && !(lb < theta)) ? 1u : 0u;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(a.list_rest + q, c);
+}
+
 __global__ void k_leaf_theta(QueryArgs a) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.mq) return;
@@ -1457,6 +1475,14 @@ void launch_scatter_answers(const int64_t* ids, const float* dists, const int32_
                             int64_t* out_ids, float* out_dists, hipStream_t s) {
     if (mf <= 0) return;
     k_scatter_answers<<<mf, 256, 0, s>>>(ids, dists, pos, kmax, out_ids, out_dists);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_list_recount(const QueryArgs& a, int64_t grid_x, hipStream_t s) {
+    ProfScope ps("list_recount", s);
+    ISAX_HIP(hipMemsetAsync(a.list_rest, 0, (size_t)a.mq * sizeof(unsigned), s));
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_x, 64)), (unsigned)a.mq);
+    k_list_recount<<<grid, 256, 0, s>>>(a);
     ISAX_HIP(hipGetLastError());
 }
 

@@ -474,6 +474,7 @@ void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const 
     ar.add(&a.theta, mq);
     ar.add(&a.leaf_hist, (size_t)mq * kLeafBins);
     ar.add(&a.leaf_count, mq);
+    ar.add(&a.list_rest, mq);
     ar.add(&a.env_paa, (size_t)mq * 2 * idx->w);
     if (metric == ISAX_METRIC_DTW) ar.add(&a.qenv, (size_t)mq * 2 * idx->len);
     b.mem = ar.commit(s);
@@ -598,23 +599,106 @@ void index_rounds(isax_index* idx, Batch& b, hipStream_t s, const std::vector<in
         profile_add_bytes(a.metric == ISAX_METRIC_DTW ? "dtw_scan" : "index_scan", scan_bytes(b, idx, s, cnt, skip));
 }
 
-// Hybrid batch: the leaf histogram of the iSAX path counts, for every query,
-// the leaves whose bound is within the approximate answer's best-so-far.  A
-// query with at most `limit` such leaves stays on the iSAX path (pruning will
-// leave little to refine); the others are gathered into a sub-batch that the
-// BF16 filter answers, and their answers are written back to their rows.
+// Cost model of the hybrid planner, in seconds (fitted on one MI355X at
+// 100M x 256).  The iSAX path reads, for every leaf it still has to bound, the
+// words of its series (their bounds) at about kIdxBps, and refines the share
+// of them that survives, each at len * 4 bytes at the same rate; the share is
+// the one round 1 saw for that query (kFarShare for a query without round 1).
+// The BF16 filter streams its whole copy once per batch at about
+// kFilterStreamBps, computes its padded query rows at about kFilterFlops, and
+// spends kFilterPerQuery per query on refinement and ordering.
+constexpr double kIdxBps = 4e12;
+constexpr double kFarShare = 0.25;
+constexpr double kFilterStreamBps = 5.5e12;
+constexpr double kFilterFlops = 1.1e15;
+constexpr double kFilterPerQuery = 15e-6;
+
+double filter_cost(const isax_index* idx, int f) {
+    if (f == 0) return 0.0;
+    const double stream = (double)idx->n * (filter_len_pad(idx->len) * 2 + 16) / kFilterStreamBps;
+    const double mfma = 2.0 * idx->len * (double)idx->n * filter_rows_bf16(idx->len, f) / kFilterFlops;
+    return std::max(stream, mfma) + f * kFilterPerQuery;
+}
+
+// Hybrid batch.  The leaf pass of the iSAX path lists, for every query, the
+// leaves whose bound is within the approximate answer's best-so-far.  Round 1
+// (the listed leaves of smallest bound) lowers the best-so-far of every query
+// whose list fit, and the list is counted again: est[q] = the leaves round 2
+// would still bound (for a query whose list did not fit, the first count).
+// With a limit, the queries with est above it go to the BF16 filter; without,
+// the planner prices each query's remaining iSAX work (cost[q], model above)
+// and sends the j costliest to the filter, j minimising filter_cost(j) + the
+// cost of the others.  The filter's queries are gathered into a sub-batch and
+// their answers written back to their rows; the others finish on the iSAX
+// path (round 2 over their lists, or both rounds over every leaf for a query
+// whose list did not fit).
 void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     QueryArgs& a = b.a;
+    const int mq = a.mq;
     launch_qprep(a, s);
     launch_homeleaf(a, s);
-    leaf_pass(b, limit, s);
+    leaf_pass(b, kLeafListMax, s);
     const std::vector<int64_t> cnt = leaves_initial(b, s);
-    b.skip.assign(a.mq, 0);
-    for (int q = 0; q < a.mq; ++q)
-        if (cnt[q] > limit) {
-            b.skip[q] = 1;
-            b.far.push_back(q);
+    const bool best_first = !(a.flags & ISAX_QF_NO_BEST_FIRST);
+    std::vector<char> listed(mq);
+    for (int q = 0; q < mq; ++q) listed[q] = best_first && cnt[q] <= a.leaf_cap;
+    std::vector<int64_t> est = cnt;
+    std::vector<int> flags_a(mq), flags_b(mq);  // done flags of the launches below (kept alive until the sync)
+    int64_t g1 = 0;
+    for (int q = 0; q < mq; ++q) {
+        flags_a[q] = !listed[q];
+        if (listed[q]) g1 = std::max(g1, (cnt[q] + 255) / 256);
+    }
+    // iSAX cost per remaining leaf: the words of its series, and the refinement
+    // of the share that survived in round 1
+    const double leaf_words = (double)a.leaf_size * a.ws / kIdxBps;
+    const double leaf_refine = (double)a.leaf_size * a.len * 4.0 / kIdxBps;
+    std::vector<double> cost(mq);
+    for (int q = 0; q < mq; ++q) cost[q] = (leaf_words + kFarShare * leaf_refine) * (double)est[q];
+    if (g1 > 0) {
+        // round 1 over the lists
+        ISAX_HIP(hipMemcpyAsync(a.done, flags_a.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
+        a.grid_leaves = g1;
+        a.round = 1;
+        launch_index_scan(a, s);
+        launch_list_recount(a, g1, s);
+        std::vector<unsigned> r(mq);
+        std::vector<unsigned long long> st((size_t)mq * ST_N);
+        ISAX_HIP(hipMemcpyAsync(r.data(), a.list_rest, mq * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        ISAX_HIP(hipMemcpyAsync(st.data(), a.stats, st.size() * 8, hipMemcpyDeviceToHost, s));
+        ISAX_HIP(hipStreamSynchronize(s));
+        for (int q = 0; q < mq; ++q)
+            if (listed[q]) {
+                est[q] = r[q];
+                const unsigned long long* sq = &st[(size_t)q * ST_N];
+                const double share = (double)sq[ST_REFINED] / (double)std::max<unsigned long long>(sq[ST_SERIES_LB], 1);
+                cost[q] = (leaf_words + std::min(1.0, share) * leaf_refine) * (double)est[q];
+            }
+    }
+    b.skip.assign(mq, 0);
+    if (limit > 0) {
+        for (int q = 0; q < mq; ++q) b.skip[q] = est[q] > limit;
+    } else {
+        // the j queries of largest cost to the filter, j minimising the total
+        std::vector<int> order(mq);
+        for (int q = 0; q < mq; ++q) order[q] = q;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+        double rest_cost = 0.0;
+        for (int q = 0; q < mq; ++q) rest_cost += cost[q];
+        double best = rest_cost;
+        int bj = 0;
+        for (int j = 1; j <= mq; ++j) {
+            rest_cost -= cost[order[j - 1]];
+            const double c = filter_cost(idx, j) + rest_cost;
+            if (c < best) {
+                best = c;
+                bj = j;
+            }
         }
+        for (int j = 0; j < bj; ++j) b.skip[order[j]] = 1;
+    }
+    for (int q = 0; q < mq; ++q)
+        if (b.skip[q]) b.far.push_back(q);
     const int mf = (int)b.far.size();
     int32_t* pos = nullptr;
     int64_t* oid = nullptr;
@@ -630,16 +714,44 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
         ar.add(&od, (size_t)mf * a.kmax);
         b.sub_mem = ar.commit(s);
         ISAX_HIP(hipMemcpyAsync(pos, b.far.data(), mf * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        // the iSAX kernels pass over a query whose done flag is set
-        ISAX_HIP(hipMemcpyAsync(a.done, b.skip.data(), a.mq * sizeof(int), hipMemcpyHostToDevice, s));
         launch_gather_queries(a.Q, a.kq, pos, mf, a.len, Qf, kqf, s);
         b.sub.reset(new Batch);
         setup_batch(*b.sub, idx, Qf, mf, kqf, a.kmax, a.cap, a.flags, oid, od, s);
         b.sub->fcap0 = b.fcap0;
     }
-    if (mf < a.mq) {
-        index_rounds(idx, b, s, cnt, b.skip);
+    if (mf < mq) {
+        if (best_first) {
+            // round 2 over the lists of the listed queries that stay
+            int64_t g2 = 0, n_full = 0;
+            for (int q = 0; q < mq; ++q) {
+                flags_a[q] = b.skip[q] || !listed[q];
+                flags_b[q] = b.skip[q] || listed[q];
+                if (!flags_a[q]) g2 = std::max(g2, (cnt[q] + 255) / 256);
+                n_full += !flags_b[q];
+            }
+            if (g2 > 0) {
+                ISAX_HIP(hipMemcpyAsync(a.done, flags_a.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
+                a.grid_leaves = g2;
+                a.round = 2;
+                launch_index_scan(a, s);
+            }
+            if (n_full > 0) {
+                // both rounds over every leaf for the queries whose list did not fit
+                ISAX_HIP(hipMemcpyAsync(a.done, flags_b.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
+                a.grid_leaves = (a.n_leaves + 255) / 256;
+                a.round = 1;
+                launch_index_scan(a, s);
+                a.round = 2;
+                launch_index_scan(a, s);
+            }
+            if (profiling_on()) profile_add_bytes("index_scan", scan_bytes(b, idx, s, cnt, b.skip));
+        }
+        // the iSAX kernels and the final ordering pass over a query whose done flag is set
+        ISAX_HIP(hipMemcpyAsync(a.done, b.skip.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
+        if (!best_first) index_rounds(idx, b, s, cnt, b.skip);
         finish_batch(idx, b, ISAX_MODE_INDEX, s);
+    } else {
+        ISAX_HIP(hipMemcpyAsync(a.done, b.skip.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
     }
     if (mf > 0) {
         run_batch(idx, *b.sub, ISAX_MODE_BF16, s);
@@ -776,7 +888,7 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     }
     const int B = o.batch ? o.batch : 1024;
     const int cap = o.candidate_capacity ? std::max(o.candidate_capacity, k) : kDefaultCap;
-    const int64_t hybrid_limit = o.hybrid_leaves ? o.hybrid_leaves : std::max<int64_t>(1, idx->n_leaves / 32);
+    const int64_t hybrid_limit = o.hybrid_leaves;  // 0: the planner
     for (int64_t q0 = 0; q0 < m; q0 += B) {
         const int mq = (int)std::min<int64_t>(B, m - q0);
         Batch b;
@@ -928,7 +1040,7 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
 int64_t isax::query_scratch_bytes(const isax_index* idx, int mq, int kmax, int mode) {
     const int64_t per_q = idx->w * 4 + idx->ws + 8 + 16 + 2 * idx->ns * 4 + (int64_t)idx->w * idx->ns * 4 + 4 +
                           (int64_t)kmax * 8 + (int64_t)kDefaultCap * 8 + 4 + 16 + ST_N * 8 + 8 + 4 + 4 +
-                          kLeafBins * 4 + 2 * idx->w * 4 + 4;
+                          kLeafBins * 4 + 2 * idx->w * 4 + 8;
     int64_t tot = per_q * mq + 16 * 256;
     if (mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8 || mode == ISAX_MODE_HYBRID) {
         const int qpb = filter_queries_per_block(idx->len);

@@ -603,15 +603,56 @@ void index_rounds(isax_index* idx, Batch& b, hipStream_t s, const std::vector<in
 // 100M x 256).  The iSAX path reads, for every leaf it still has to bound, the
 // words of its series (their bounds) at about kIdxBps, and refines the share
 // of them that survives, each at len * 4 bytes at the same rate; the share is
-// the one round 1 saw for that query (kFarShare for a query without round 1).
+// the one round 1 saw for that query (kFarShare for a query without round 1;
+// before round 1, kNearShare screens out the queries that are too dear even
+// then, so that they skip round 1).
 // The BF16 filter streams its whole copy once per batch at about
 // kFilterStreamBps, computes its padded query rows at about kFilterFlops, and
 // spends kFilterPerQuery per query on refinement and ordering.
 constexpr double kIdxBps = 4e12;
 constexpr double kFarShare = 0.25;
+constexpr double kNearShare = 0.01;  // before round 1: the share of a query close to its answer
 constexpr double kFilterStreamBps = 5.5e12;
 constexpr double kFilterFlops = 1.1e15;
 constexpr double kFilterPerQuery = 15e-6;
+// The hybrid's own work before and around the split (leaf pass, round 1, a
+// second approximate answer for the filter's queries, more synchronisation):
+// about 1.5 ms per call at 10M x 256; a batch the filter answers in less than
+// kHybridFixed takes the BF16 path at once.
+constexpr double kHybridFixed = 3e-3;
+
+// The planner: `fixed` queries go to the filter; of the others, the j of
+// largest cost join them, j minimising filter_cost(all of them) + the cost of
+// the queries left on the iSAX path.  Returns the filter's set.
+double filter_cost(const isax_index* idx, int f);
+std::vector<char> plan_far(const isax_index* idx, const std::vector<double>& cost, const std::vector<char>& fixed) {
+    const int mq = (int)cost.size();
+    std::vector<int> order;
+    int n0 = 0;
+    double rest = 0.0;
+    for (int q = 0; q < mq; ++q) {
+        if (fixed[q]) {
+            ++n0;
+        } else {
+            order.push_back(q);
+            rest += cost[q];
+        }
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    double best = filter_cost(idx, n0) + rest;
+    int bj = 0;
+    for (int j = 1; j <= (int)order.size(); ++j) {
+        rest -= cost[order[j - 1]];
+        const double c = filter_cost(idx, n0 + j) + rest;
+        if (c < best) {
+            best = c;
+            bj = j;
+        }
+    }
+    std::vector<char> far = fixed;
+    for (int j = 0; j < bj; ++j) far[order[j]] = 1;
+    return far;
+}
 
 double filter_cost(const isax_index* idx, int f) {
     if (f == 0) return 0.0;
@@ -635,6 +676,10 @@ double filter_cost(const isax_index* idx, int f) {
 void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     QueryArgs& a = b.a;
     const int mq = a.mq;
+    if (limit == 0 && filter_cost(idx, mq) < kHybridFixed) {
+        run_batch(idx, b, ISAX_MODE_BF16, s);
+        return;
+    }
     launch_qprep(a, s);
     launch_homeleaf(a, s);
     leaf_pass(b, kLeafListMax, s);
@@ -644,17 +689,38 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     for (int q = 0; q < mq; ++q) listed[q] = best_first && cnt[q] <= a.leaf_cap;
     std::vector<int64_t> est = cnt;
     std::vector<int> flags_a(mq), flags_b(mq);  // done flags of the launches below (kept alive until the sync)
-    int64_t g1 = 0;
-    for (int q = 0; q < mq; ++q) {
-        flags_a[q] = !listed[q];
-        if (listed[q]) g1 = std::max(g1, (cnt[q] + 255) / 256);
-    }
     // iSAX cost per remaining leaf: the words of its series, and the refinement
-    // of the share that survived in round 1
+    // of a share of them
     const double leaf_words = (double)a.leaf_size * a.ws / kIdxBps;
     const double leaf_refine = (double)a.leaf_size * a.len * 4.0 / kIdxBps;
     std::vector<double> cost(mq);
-    for (int q = 0; q < mq; ++q) cost[q] = (leaf_words + kFarShare * leaf_refine) * (double)est[q];
+    std::vector<char> pre(mq, 0);  // sent to the filter before round 1
+    if (limit == 0) {
+        // queries too dear for the index even at the small refinement share of
+        // a near query after round 1 skip round 1; round 1 itself (the leaves
+        // of the histogram's bins up to theta) is priced at kFarShare
+        std::vector<unsigned> h((size_t)mq * kLeafBins);
+        ISAX_HIP(hipMemcpyAsync(h.data(), a.leaf_hist, h.size() * 4, hipMemcpyDeviceToHost, s));
+        ISAX_HIP(hipStreamSynchronize(s));
+        for (int q = 0; q < mq; ++q) {
+            if (!listed[q]) {
+                cost[q] = (leaf_words + kFarShare * leaf_refine) * (double)cnt[q];
+                continue;
+            }
+            int64_t n1 = 0;
+            for (int j = 0; j < kLeafBins && n1 < kFirstLeaves; ++j) n1 += h[(size_t)q * kLeafBins + j];
+            n1 = std::min(n1, cnt[q]);
+            cost[q] = (leaf_words + kFarShare * leaf_refine) * (double)n1 +
+                      (leaf_words + kNearShare * leaf_refine) * (double)(cnt[q] - n1);
+        }
+        pre = plan_far(idx, cost, pre);
+    }
+    int64_t g1 = 0;
+    for (int q = 0; q < mq; ++q) {
+        flags_a[q] = !listed[q] || pre[q];
+        if (!flags_a[q]) g1 = std::max(g1, (cnt[q] + 255) / 256);
+        cost[q] = (leaf_words + kFarShare * leaf_refine) * (double)cnt[q];
+    }
     if (g1 > 0) {
         // round 1 over the lists
         ISAX_HIP(hipMemcpyAsync(a.done, flags_a.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
@@ -668,7 +734,7 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
         ISAX_HIP(hipMemcpyAsync(st.data(), a.stats, st.size() * 8, hipMemcpyDeviceToHost, s));
         ISAX_HIP(hipStreamSynchronize(s));
         for (int q = 0; q < mq; ++q)
-            if (listed[q]) {
+            if (!flags_a[q]) {
                 est[q] = r[q];
                 const unsigned long long* sq = &st[(size_t)q * ST_N];
                 const double share = (double)sq[ST_REFINED] / (double)std::max<unsigned long long>(sq[ST_SERIES_LB], 1);
@@ -679,27 +745,20 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     if (limit > 0) {
         for (int q = 0; q < mq; ++q) b.skip[q] = est[q] > limit;
     } else {
-        // the j queries of largest cost to the filter, j minimising the total
-        std::vector<int> order(mq);
-        for (int q = 0; q < mq; ++q) order[q] = q;
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-        double rest_cost = 0.0;
-        for (int q = 0; q < mq; ++q) rest_cost += cost[q];
-        double best = rest_cost;
-        int bj = 0;
-        for (int j = 1; j <= mq; ++j) {
-            rest_cost -= cost[order[j - 1]];
-            const double c = filter_cost(idx, j) + rest_cost;
-            if (c < best) {
-                best = c;
-                bj = j;
-            }
-        }
-        for (int j = 0; j < bj; ++j) b.skip[order[j]] = 1;
+        const std::vector<char> far = plan_far(idx, cost, pre);
+        for (int q = 0; q < mq; ++q) b.skip[q] = far[q];
     }
     for (int q = 0; q < mq; ++q)
         if (b.skip[q]) b.far.push_back(q);
     const int mf = (int)b.far.size();
+    if (mf == mq) {
+        // every query to the filter: the batch itself runs the BF16 path (qprep
+        // resets its per-query state; the leaf counts stay for the statistics)
+        b.far.clear();
+        b.skip.clear();
+        run_batch(idx, b, ISAX_MODE_BF16, s);
+        return;
+    }
     int32_t* pos = nullptr;
     int64_t* oid = nullptr;
     float* od = nullptr;

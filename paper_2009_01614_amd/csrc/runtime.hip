@@ -603,9 +603,11 @@ void index_rounds(isax_index* idx, Batch& b, hipStream_t s, const std::vector<in
 // 100M x 256).  The iSAX path reads, for every leaf it still has to bound, the
 // words of its series (their bounds) at about kIdxBps, and refines the share
 // of them that survives, each at len * 4 bytes at the same rate; the share is
-// the one round 1 saw for that query (kFarShare for a query without round 1;
-// before round 1, kNearShare screens out the queries that are too dear even
-// then, so that they skip round 1).
+// the one round 1 saw for that query.  Before round 1 (and for a query whose
+// list did not fit, which has no round 1 to learn from) a query is priced
+// optimistically: its round-1 leaves (the histogram's bins up to theta) at
+// kFarShare, the others at kNearShare; a query too dear even then goes to the
+// filter without round 1.
 // The BF16 filter streams its whole copy once per batch at about
 // kFilterStreamBps, computes its padded query rows at about kFilterFlops, and
 // spends kFilterPerQuery per query on refinement and ordering.
@@ -703,10 +705,6 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
         ISAX_HIP(hipMemcpyAsync(h.data(), a.leaf_hist, h.size() * 4, hipMemcpyDeviceToHost, s));
         ISAX_HIP(hipStreamSynchronize(s));
         for (int q = 0; q < mq; ++q) {
-            if (!listed[q]) {
-                cost[q] = (leaf_words + kFarShare * leaf_refine) * (double)cnt[q];
-                continue;
-            }
             int64_t n1 = 0;
             for (int j = 0; j < kLeafBins && n1 < kFirstLeaves; ++j) n1 += h[(size_t)q * kLeafBins + j];
             n1 = std::min(n1, cnt[q]);
@@ -719,7 +717,6 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     for (int q = 0; q < mq; ++q) {
         flags_a[q] = !listed[q] || pre[q];
         if (!flags_a[q]) g1 = std::max(g1, (cnt[q] + 255) / 256);
-        cost[q] = (leaf_words + kFarShare * leaf_refine) * (double)cnt[q];
     }
     if (g1 > 0) {
         // round 1 over the lists

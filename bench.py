@@ -49,7 +49,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="instead of the headline: serve 50M x 256 + 20M x 128 at swept Poisson rates")
-    ap.add_argument("--sweep-mode", default="hybrid", choices=["index", "scan", "bf16", "fp8", "hybrid"])
+    ap.add_argument("--sweep-mode", default="bf16", choices=["index", "scan", "bf16", "fp8", "hybrid"])
+    ap.add_argument("--serve-mode", default="bf16", choices=["index", "scan", "bf16", "fp8", "hybrid"],
+                    help="mode of the serving leg (BF16 serves mixed traffic with the lowest latency)")
     ap.add_argument("--precision-report", action="store_true",
                     help="instead of the headline: 10M x 256, batches of 1024, modes and filter error vs FP64")
     ap.add_argument("--sigma-report", action="store_true",
@@ -95,6 +97,7 @@ def main():
     precision = 0
     for md in set(args.modes.split(",")) | {args.mode}:
         precision |= {"bf16": 1, "fp8": 2, "hybrid": 1}.get(md, 0)
+    precision |= {"bf16": 1, "fp8": 2, "hybrid": 1}.get(args.serve_mode, 0) if not args.no_serving else 0
     log("building the index (twice; the second is timed)")
     idx = isax.Index(X, 16, 8, precision=precision)
     del idx
@@ -195,9 +198,10 @@ def main():
     # ---------------------------------------------------------------- serving latency
     serving = None
     if not args.no_serving and args.serve_requests > 0:
-        rate = 0.5 * qps
+        # half of the serving mode's batch throughput (measured above when it is not the timed mode)
+        rate = 0.5 * (qps if args.serve_mode == args.mode else modes_qps.get(args.serve_mode, qps))
         log(f"serving {args.serve_requests} Poisson arrivals at {rate:.0f}/s")
-        srv = isax.Server([idx], mode=args.mode, max_batch=512, streams=4)
+        srv = isax.Server([idx], mode=args.serve_mode, max_batch=512, streams=4)
         Qh = Q.cpu().numpy()
         rng = np.random.default_rng(7)
         res = {}
@@ -222,7 +226,8 @@ def main():
         srv.close()
         lat = np.array([(r["t_done"] - r["t_submit"]) * 1e3 for r in res.values()])
         bad = sum(1 for i, r in res.items() if r["ids"][0] != int(ids[i % m, 0]))
-        serving = {"requests": len(res), "offered_rate": round(rate, 1), "qps": round(len(res) / te, 1),
+        serving = {"mode": args.serve_mode, "requests": len(res), "offered_rate": round(rate, 1),
+                   "qps": round(len(res) / te, 1),
                    "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
                    "mean_batch": round(float(np.mean([r["batch_size"] for r in res.values()])), 1),
                    "mismatches": bad}

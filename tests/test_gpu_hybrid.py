@@ -177,3 +177,21 @@ def test_leaves_initial_matches_oracle_envelope_bounds(isax, coll, k):
         low = int((lb <= tau * (1 - 1e-4)).sum()) - 4
         high = int((lb <= tau * (1 + 1e-3) + 1e-6).sum())
         assert low <= s["leaves_initial"] <= high, (j, low, s["leaves_initial"], high)
+
+
+@pytest.mark.parametrize("length,w", [(128, 16), (200, 8)])
+def test_hybrid_other_lengths_and_sorted_rows(isax, length, w):
+    # other filter row classes (len_pad 128 and 256 with padding) and the leaf-order FP32 rows
+    X = workload.random_walks(30_011, length, seed=71 + length, device="cuda")
+    Qn, _, _ = workload.noisy_queries(X, 60, seed=72)
+    Q = torch.cat([Qn, workload.fresh_queries(20, length, seed=73, device="cuda")]).contiguous()
+    ref_ids, ref_d2 = kr.knn_exact_c(_cpu(X), _cpu(Q), 5)
+    for prec in (1, 5):
+        idx = isax.Index(X, w, 8, leaf_size=64, precision=prec)
+        for limit in (1, 20, 10**6):
+            ids, d, st = idx.query(Q, k=5, mode="hybrid", hybrid_leaves=limit, stats=True)
+            _check(ids, d, ref_ids, ref_d2, 5)
+            li = np.array([s["leaves_initial"] for s in st])
+            path = np.array([s["path"] for s in st])
+            assert np.all(path[li <= limit] == isax.MODE_INDEX)
+        idx.close()

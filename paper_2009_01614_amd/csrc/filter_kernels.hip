@@ -34,8 +34,12 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr float kInf = __builtin_huge_valf();
 constexpr int kNT = 32;         // series per column tile (the columns of one MFMA)
-constexpr int kFilterCols = 2;  // BF16: column tiles per staged tile, so one barrier and one loop
-                                // step per 64 series (measured 45.0 -> 43.9 ms at 100M x 256, 1000 queries)
+// BF16: column tiles per staged tile, so one barrier and one loop step per
+// 32 kFilterCols series; the 8-wave blocks (one per CU) take kFilterColsWide.
+// Measured at 100M x 256, 1000 queries: 45.0 ms with one column tile, 41.1 ms
+// with four (staged one column tile at a time).
+constexpr int kFilterCols = 2;
+constexpr int kFilterColsWide = 4;
 constexpr int kBAhead = 6;      // BF16 B fragments in flight ahead of their MFMAs
 
 __device__ inline unsigned long long make_key(float d2, int32_t id) {
@@ -149,7 +153,7 @@ struct FilterCfg {
     static constexpr int HALF = ROW / 2;
     static constexpr int STEP_B = KIND == 0 ? 16 : 32;         // bytes per lane per step
     static constexpr int CHUNKS = TS * ROW / 16;               // 16-B chunks per tile
-    static constexpr int CPT = (CHUNKS + THREADS - 1) / THREADS;
+    static constexpr int CPP = (CHUNKS / NC + THREADS - 1) / THREADS;  // per thread and column tile
     static constexpr int QPB = WAVES * 32 * MT;                // queries per block
 };
 
@@ -237,12 +241,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
         return f.phase == 0 ? v : f.phase == 1 ? v * kFilterSub : v + v / (kFilterSub - 1) + 1;
     };
     const unsigned char* X = static_cast<const unsigned char*>(f.xq);
-    auto load_tile = [&](int64_t tl, i32x4* stage) {
+    // one column tile's rows (part) at a time: the next tile's part p is loaded
+    // while part p of this tile is computed, and stored into the free buffer after
+    auto load_tile = [&](int64_t tl, int part, i32x4* stage) {
 #pragma unroll
-        for (int c = 0; c < C::CPT; ++c) {
-            const int ch = threadIdx.x + c * C::THREADS;
+        for (int c = 0; c < C::CPP; ++c) {
+            const int ch = part * (C::CHUNKS / NC) + threadIdx.x + c * C::THREADS;
             i32x4 v = {0, 0, 0, 0};
-            if (ch < C::CHUNKS) {
+            if (ch < (part + 1) * (C::CHUNKS / NC)) {
                 const int row = ch / (C::ROW / 16), col = ch % (C::ROW / 16);
                 const int64_t pos = tl * C::TS + row;
                 if (pos < a.n) v = *reinterpret_cast<const i32x4*>(X + pos * C::ROW + col * 16);
@@ -250,18 +256,18 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
             stage[c] = v;
         }
     };
-    auto store_tile = [&](int buf, const i32x4* stage) {
+    auto store_tile = [&](int buf, int part, const i32x4* stage) {
 #pragma unroll
-        for (int c = 0; c < C::CPT; ++c) {
-            const int ch = threadIdx.x + c * C::THREADS;
-            if (ch < C::CHUNKS) {
+        for (int c = 0; c < C::CPP; ++c) {
+            const int ch = part * (C::CHUNKS / NC) + threadIdx.x + c * C::THREADS;
+            if (ch < (part + 1) * (C::CHUNKS / NC)) {
                 const int row = ch / (C::ROW / 16), col = ch % (C::ROW / 16);
                 *reinterpret_cast<i32x4*>(&tile[buf][row * C::STRIDE + col * 16]) = stage[c];
             }
         }
     };
 
-    i32x4 stage[C::CPT];
+    i32x4 stage[C::CPP];
     int v = stream;
     // per-series metadata of the current tile, fetched one tile ahead
     auto load_meta = [&](int64_t tile, int c) -> float4 {
@@ -272,10 +278,12 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
 #pragma unroll
     for (int c = 0; c < NC; ++c) m_cur[c] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (v < n_vt) {
-        load_tile(tile_of(v), stage);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) m_cur[c] = load_meta(tile_of(v), c);
-        store_tile(0, stage);
+        for (int c = 0; c < NC; ++c) {
+            load_tile(tile_of(v), c, stage);
+            m_cur[c] = load_meta(tile_of(v), c);
+            store_tile(0, c, stage);
+        }
     }
     __syncthreads();
     int buf = 0;
@@ -283,14 +291,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
     for (; v < n_vt; v += n_streams, buf ^= 1, ++iter) {
         const int64_t tl = tile_of(v);
         const bool has_next = v + n_streams < n_vt;
-        float4 m_next[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) m_next[c] = m_cur[c];
+        const int64_t tn = has_next ? tile_of(v + n_streams) : 0;
+        float4 m_next = m_cur[0];
         if (has_next) {
-            const int64_t tn = tile_of(v + n_streams);
-            load_tile(tn, stage);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) m_next[c] = load_meta(tn, c);
+            load_tile(tn, 0, stage);
+            m_next = load_meta(tn, 0);
         }
         // the NC column tiles of this tile, one after the other
 #pragma unroll
@@ -429,10 +434,16 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
                 }
             }
         }
+        // column c of this tile is done: its metadata makes room for the next tile's
+        m_cur[c] = m_next;
+        if (has_next) {
+            store_tile(buf ^ 1, c, stage);
+            if (c + 1 < NC) {
+                load_tile(tn, c + 1, stage);
+                m_next = load_meta(tn, c + 1);
+            }
+        }
         }  // column tiles
-        if (has_next) store_tile(buf ^ 1, stage);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) m_cur[c] = m_next[c];
         if ((iter & 63) == 63) {
             __syncthreads();
             refresh_H();
@@ -545,7 +556,8 @@ __global__ void k_filter_tighten(QueryArgs a, FilterArgs f) {
 // then bound by reading the reduced-precision copy, not by the matrix cores.
 template <int KIND, int KS, int MT, int WAVES>
 void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax, hipStream_t s) {
-    constexpr int NC = KIND == 0 ? kFilterCols : 1;
+    // (the wide setting only where its double buffer fits the 160 KB of LDS: rows up to 512 bytes)
+    constexpr int NC = KIND == 0 ? (WAVES >= 8 && KS * 32 <= 512 ? kFilterColsWide : kFilterCols) : 1;
     using C = FilterCfg<KIND, KS, MT, WAVES, NC>;
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);

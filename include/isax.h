@@ -27,6 +27,9 @@
  *     isax_last_error().  HIP failures give ISAX_EDEVICE with HIP's message.
  *   - Calls run on the stream given in their options (NULL: the null stream)
  *     and return after the results are in the output buffers.
+ *   - Query scratch blocks of 1 MiB to 1 GiB stay allocated after a call for
+ *     reuse (at most 4 GiB idle per device); they are freed when a device
+ *     allocation of the library would otherwise fail.
  */
 #ifndef ISAX_H
 #define ISAX_H

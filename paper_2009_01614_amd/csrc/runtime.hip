@@ -179,6 +179,15 @@ void cache_free(void* p, hipStream_t s) noexcept {
             return;
         }
 }
+
+// Frees every idle cached block of the current device (before an allocation
+// that failed is tried again).
+void cache_release_idle() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    cache_trim_locked(dev, 0);
+}
 }  // namespace
 
 DevBuf::DevBuf(size_t n, hipStream_t s) : bytes(n), stream(s) {
@@ -188,7 +197,12 @@ DevBuf::DevBuf(size_t n, hipStream_t s) : bytes(n), stream(s) {
         cached = true;
         return;
     }
-    const hipError_t e = hipMallocAsync(&p, n, s);
+    hipError_t e = hipMallocAsync(&p, n, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        cache_release_idle();
+        e = hipMallocAsync(&p, n, s);
+    }
     if (e != hipSuccess) {
         p = nullptr;
         throw Error{ISAX_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed: " + hipGetErrorString(e)};
@@ -218,7 +232,13 @@ DevBuf& DevBuf::operator=(DevBuf&& o) noexcept {
 
 void* dev_alloc(size_t bytes) {
     void* p = nullptr;
-    const hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 16));
+    hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) {
+        // idle query scratch kept by the block cache may be what is missing
+        (void)hipGetLastError();
+        cache_release_idle();
+        e = hipMalloc(&p, std::max<size_t>(bytes, 16));
+    }
     if (e != hipSuccess)
         throw Error{ISAX_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e)};
     return p;

@@ -44,7 +44,7 @@ def main():
     ap.add_argument("--modes", default="index,scan,bf16,fp8", help="modes measured once each besides the timed one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-series", type=int, default=10_000_000)
-    ap.add_argument("--cpu-sample-queries", type=int, default=64)
+    ap.add_argument("--cpu-sample-queries", type=int, default=128)
     ap.add_argument("--serve-requests", type=int, default=3000)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-sweep", action="store_true",

@@ -630,15 +630,16 @@ void index_rounds(isax_index* idx, Batch& b, hipStream_t s, const std::vector<in
 // filter without round 1.
 // The BF16 filter streams its whole copy once per batch at about
 // kFilterStreamBps, computes its padded query rows at about kFilterFlopsWide
-// (blocks of 512 rows, eight waves) or kFilterFlopsNarrow (the smaller block
-// classes), and spends kFilterPerQuery per query on refinement and ordering
-// (fitted to 100M x 256: 9.7 ms for 1-64 queries, 10.7 for 128, 17.8 for 256,
-// 24.1 for 512, 43.2 for 1000).
+// (blocks of 512 rows), kFilterFlopsMid (256 rows) or kFilterFlopsNarrow (the
+// smaller block classes), and spends kFilterPerQuery per query on refinement
+// and ordering (fitted to 100M x 256: 9.7 ms for 1-64 queries, 10.7 for 128,
+// 15.0 for 256, 24.1 for 512, 43.2 for 1000).
 constexpr double kIdxBps = 4e12;
 constexpr double kFarShare = 0.25;
 constexpr double kNearShare = 0.01;  // before round 1: the share of a query close to its answer
 constexpr double kFilterStreamBps = 5.5e12;
 constexpr double kFilterFlopsWide = 1.4e15;
+constexpr double kFilterFlopsMid = 1.05e15;
 constexpr double kFilterFlopsNarrow = 0.8e15;
 constexpr double kFilterPerQuery = 10e-6;
 // The hybrid's own work before and around the split (leaf pass, round 1, a
@@ -684,8 +685,8 @@ double filter_cost(const isax_index* idx, int f) {
     if (f == 0) return 0.0;
     const double stream = (double)idx->n * (filter_len_pad(idx->len) * 2 + 16) / kFilterStreamBps;
     const int rows = filter_rows_bf16(idx->len, f);
-    const double mfma =
-        2.0 * idx->len * (double)idx->n * rows / (rows % 512 == 0 ? kFilterFlopsWide : kFilterFlopsNarrow);
+    const double rate = rows % 512 == 0 ? kFilterFlopsWide : rows == 256 ? kFilterFlopsMid : kFilterFlopsNarrow;
+    const double mfma = 2.0 * idx->len * (double)idx->n * rows / rate;
     return std::max(stream, mfma) + f * kFilterPerQuery;
 }
 

@@ -95,3 +95,22 @@ def test_filter_batch_size_classes(isax, m):
     for mode in ("bf16", "fp8"):
         ids, _ = idx.query(Qn.contiguous(), k=3, mode=mode)
         assert np.array_equal(_cpu(ids), ref_ids), mode
+
+
+@pytest.mark.parametrize("length,m", [(128, 200), (200, 129), (250, 256), (64, 150)])
+def test_filter_256_row_class_other_lengths(isax, length, m):
+    # 129-256 queries take eight-wave blocks of 256 rows: other row lengths (len_pad 64, 128, 256)
+    # and lengths that are not a multiple of 4
+    X = workload.random_walks(25_013, length, seed=81 + length, device="cuda")
+    Qn, _, _ = workload.noisy_queries(X, m, seed=82 + m)
+    ref_ids, ref_d2 = kr.knn_exact_c(_cpu(X), _cpu(Qn), 4)
+    w = 16 if length % 16 == 0 else (10 if length % 10 == 0 else 2)
+    idx = isax.Index(X, w, 8, precision=3)
+    for mode in ("bf16", "fp8", "hybrid"):
+        kw = dict(hybrid_leaves=3) if mode == "hybrid" else {}
+        ids, d = idx.query(Qn.contiguous(), k=4, mode=mode, **kw)
+        assert np.array_equal(_cpu(ids), ref_ids), mode
+        ref = np.sqrt(ref_d2)
+        err = np.abs(_cpu(d) - ref) / np.maximum(ref, 1e-30)
+        err[ref == 0] = np.abs(_cpu(d)[ref == 0])
+        assert err.max() <= 1e-4, mode

@@ -707,6 +707,23 @@ __device__ inline float leaf_bound(const QueryArgs& a, int64_t leaf, const float
     return env_bound(a, a.env_lo + leaf * a.ws, a.env_hi + leaf * a.ws, pu, pl, lo_e, hi_e);
 }
 
+// The same bound for 16 segments with the envelope already in registers (the
+// same operations in the same order as env_bound, so the same FP32 value).
+__device__ inline float env_bound16(const QueryArgs& a, const uint4& vl, const uint4& vh, const float* pu,
+                                    const float* pl, const float* lo_e, const float* hi_e) {
+    const unsigned ul[4] = {vl.x, vl.y, vl.z, vl.w};
+    const unsigned uh[4] = {vh.x, vh.y, vh.z, vh.w};
+    float lb = 0.f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int slo = (ul[j >> 2] >> (8 * (j & 3))) & 255;
+        const int shi = (uh[j >> 2] >> (8 * (j & 3))) & 255;
+        const float d = fmaxf(0.f, fmaxf(lo_e[slo] - pu[j], pl[j] - hi_e[shi]));
+        lb = fmaf(d, d, lb);
+    }
+    return lb * (float)a.m_seg;
+}
+
 // Best-first order (MESSI's priority queues, by rounds): the bound of every
 // leaf against the best-so-far of the approximate answer.  Per query: a
 // histogram of the bounds over [0, bsf] in kLeafBins equal bins, the count of
@@ -720,7 +737,10 @@ __device__ inline float leaf_bound(const QueryArgs& a, int64_t leaf, const float
 // leaves): the bound of a leaf is at least that of its node in FP32 too (every
 // step is monotone in the envelope), so a node above the best-so-far rules
 // out its leaves without bounding them.
+// W16: 16 segments in 16-byte words; a thread's leaf envelope is then read
+// once into registers for all the block's queries.
 static_assert(kNodeLeaves == 64, "a node of the leaf pass is the 64 leaves of one wave");
+template <bool W16>
 __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
     constexpr int QB = kHistQueries, R = kHistLeafRounds;
     __shared__ float lo_e[QB][256], hi_e[QB][256], pu[QB][64], pl[QB][64];
@@ -771,20 +791,31 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
     float lbs[QB][R];
     int slot[QB][R];
 #pragma unroll
-    for (int i = 0; i < QB; ++i) {
+    for (int r = 0; r < R; ++r) {
+        const int64_t leaf = base_leaf + r * 256 + threadIdx.x;
+        uint4 vl = make_uint4(0u, 0u, 0u, 0u), vh = vl;
+        if constexpr (W16) {
+            bool any_in = false;  // the same in every lane of the wave
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+            for (int i = 0; i < QB; ++i) any_in |= i < nq && s_node_in[i][r * 4 + (threadIdx.x >> 6)];
+            if (any_in && leaf < a.n_leaves) {
+                vl = *reinterpret_cast<const uint4*>(a.env_lo + leaf * 16);
+                vh = *reinterpret_cast<const uint4*>(a.env_hi + leaf * 16);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < QB; ++i) {
             slot[i][r] = -1;
             lbs[i][r] = 0.f;
             if (i >= nq) continue;
             const float thr = s_thr[i];
-            const int64_t leaf = base_leaf + r * 256 + threadIdx.x;
             const bool valid = leaf < a.n_leaves && !(leaf >= s_home[i][0] && leaf < s_home[i][1]);
             const bool node_in = s_node_in[i][r * 4 + (threadIdx.x >> 6)];  // the same in every lane of the wave
             bool keep = false;
             float lb = 0.f;
             if (valid && node_in) {
-                lb = leaf_bound(a, leaf, pu[i], pl[i], lo_e[i], hi_e[i]);
+                lb = W16 ? env_bound16(a, vl, vh, pu[i], pl[i], lo_e[i], hi_e[i])
+                         : leaf_bound(a, leaf, pu[i], pl[i], lo_e[i], hi_e[i]);
                 keep = lb * a.lb_scale <= thr;
             }
             if (keep) {
@@ -1493,7 +1524,8 @@ void launch_leaf_order(const QueryArgs& a, hipStream_t s) {
     const int64_t per_block = 256 * kHistLeafRounds;
     const dim3 grid((unsigned)((a.n_leaves + per_block - 1) / per_block),
                     (unsigned)((a.mq + kHistQueries - 1) / kHistQueries));
-    k_leaf_hist<<<grid, 256, 0, s>>>(a);
+    if (a.w == 16 && a.ws == 16) k_leaf_hist<true><<<grid, 256, 0, s>>>(a);
+    else k_leaf_hist<false><<<grid, 256, 0, s>>>(a);
     k_leaf_theta<<<(a.mq + 255) / 256, 256, 0, s>>>(a);
     ISAX_HIP(hipGetLastError());
 }

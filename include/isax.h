@@ -46,7 +46,7 @@ enum {
     ISAX_EINVAL = -1,    /* bad argument, or a non-finite value in data or queries */
     ISAX_ENOMEM = -2,    /* device allocation failed */
     ISAX_EDEVICE = -3,   /* a HIP call failed */
-    ISAX_EOVERFLOW = -4  /* more than 4096 candidates tie within the rounding window of the k-th distance */
+    ISAX_EOVERFLOW = -4  /* a query's candidate list still overflowed after 8 re-runs (see candidate_capacity) */
 };
 
 /* Query execution modes (isax_query_options.mode). All return the same exact answer. */
@@ -64,8 +64,10 @@ enum {
 enum {
     ISAX_QF_NO_SHARING = 1,       /* do not lower the best-so-far during the scan */
     ISAX_QF_NO_EARLY_ABANDON = 2, /* refine every surviving series to the end */
-    ISAX_QF_NO_BEST_FIRST = 4     /* index mode: visit leaves in layout order in one pass, instead of the
+    ISAX_QF_NO_BEST_FIRST = 4,    /* index mode: visit leaves in layout order in one pass, instead of the
                                      leaves of smallest lower bound first (MESSI's priority order, Sec. III) */
+    ISAX_QF_NO_SHORTCUT = 8       /* hybrid mode: price every query with the cost model even when the whole
+                                     batch is cheap enough for the filter alone */
 };
 
 /* Distance measures (isax_query_options.metric). */
@@ -85,7 +87,7 @@ enum {
 typedef struct isax_index isax_index; /* opaque, owned by the library */
 
 typedef struct isax_build_options {
-    int32_t leaf_size; /* series per leaf (consecutive runs of the sorted order); 0 = 256; 16..4096 */
+    int32_t leaf_size; /* series per leaf (consecutive runs of the sorted order); 0 = 256; 16..1024 */
     int32_t key_bits;  /* leading bits of the interleaved key that are sorted; 0 = min(64, w*c); 8..64, multiple of 8 */
     int32_t precision; /* bit 0: also keep a BF16 copy, bit 1: also keep an FP8 E4M3 copy (needed by those modes);
                           bit 2: also keep the FP32 rows in leaf order (n x len x 4 bytes more), read by
@@ -110,12 +112,18 @@ typedef struct isax_query_stats { /* per query, filled when requested */
                                 whose lower bound is within the best-so-far of the approximate answer;
                                 -1 where not computed */
     int32_t path;            /* the mode that answered this query (ISAX_MODE_INDEX or _BF16 under hybrid) */
-    int32_t reserved;
+    int32_t candidate_capacity; /* candidate slots per query of the pass that answered it (the option's value,
+                                   16384 by default, or more after growth) */
 } isax_query_stats;
 
 typedef struct isax_query_options {
     int32_t mode;               /* ISAX_MODE_* */
-    int32_t candidate_capacity; /* candidate slots per query; 0 = 4096; grows on overflow */
+    int32_t candidate_capacity; /* candidate slots per query; 0 = 16384 (at least k).  A query whose list
+                                   overflows is run again with its bound frozen at the k-th smallest stored
+                                   distance, after the lists of its batch have grown to 1.25x the count
+                                   the last pass emitted (at most 8 re-runs, else ISAX_EOVERFLOW; ISAX_ENOMEM
+                                   if the grown lists of one batch would exceed 16 GiB).  The filter modes
+                                   keep a separate list of filter survivors that also grows on overflow. */
     int32_t flags;              /* ISAX_QF_* */
     int32_t batch;              /* queries per internal pass; 0 = 1024 */
     const int32_t* k_per_query; /* device, m values in 1..k (row i keeps k_i results, the rest
@@ -136,14 +144,16 @@ typedef struct isax_query_options {
 const char* isax_last_error(void);
 
 /*
- * Build an index over `data` (device, n x len FP32).  `segments` (w) is the
+ * Build an index over `data` (n x len FP32: device memory, or pinned host
+ * memory mapped at the same address on the device, which refinement then
+ * reads across the bus).  `segments` (w) is the
  * number of PAA segments and must divide len (segments of equal length, Sec.
  * II); `card_bits` (c, 1..8) is the number of bits of every iSAX symbol.
  * Regions are cut at the standard-normal quantiles Phi^-1(j / 2^c).
  * The index BORROWS `data`: the caller keeps it allocated and unmodified until
  * isax_free().  Returns NULL on error (see isax_last_error()); EINVAL if data
  * holds a non-finite value.  n < 2^31, len <= ISAX_MAX_LEN,
- * segments <= ISAX_MAX_SEGMENTS.
+ * segments <= ISAX_MAX_SEGMENTS; the BF16 / FP8 copies need len <= 512.
  */
 isax_index* isax_build(const float* data, int64_t n, int32_t len, int32_t segments, int32_t card_bits);
 isax_index* isax_build_ex(const float* data, int64_t n, int32_t len, int32_t segments, int32_t card_bits,
@@ -158,7 +168,10 @@ void isax_free(isax_index* idx);
  * series of smallest Euclidean distance, ascending, ties by lower id (Sec. II,
  * Similarity Search, generalised from 1 to k neighbours).  m = 0 succeeds with
  * no work.  1 <= k <= min(n, ISAX_MAX_K).  EINVAL if a query value is not
- * finite (outputs untouched).
+ * finite.  Answers are staged in library scratch and copied to out_ids /
+ * out_dists (and opt->stats) only when every batch has succeeded: on any error
+ * return the outputs are untouched.  Any number of series may tie at the k-th
+ * distance (the lowest ids are returned).
  * With opt->metric = ISAX_METRIC_DTW the same index answers the k nearest
  * series under banded DTW (ISAX_METRIC_DTW above): the leaf and series
  * bounds use the PAA of the query's envelope, then LB_Keogh, then the DTW
@@ -236,6 +249,16 @@ typedef struct isax_profile_entry {
 int isax_profile_enable(int32_t on);
 int isax_profile_read(isax_profile_entry* out, int32_t max_entries, int32_t* n_entries);
 int isax_profile_reset(void);
+
+/* ------------------------------------------------------------- testing */
+/*
+ * Fault injection for tests of the error paths: the `countdown`-th device
+ * allocation the library requests from now on (query scratch and index
+ * arrays; blocks reused from the cache count too) fails as if the device were
+ * out of memory, and the call reports ISAX_ENOMEM.  0 switches it off.
+ * Process-wide.
+ */
+int isax_debug_fail_allocation(int64_t countdown);
 
 /* ------------------------------------------------------------- serving */
 /*

@@ -25,7 +25,7 @@ MODES = {"index": MODE_INDEX, "scan": MODE_SCAN, "bf16": MODE_BF16, "fp8": MODE_
 METRIC_ED, METRIC_DTW = 0, 1
 METRICS = {"ed": METRIC_ED, "dtw": METRIC_DTW}
 MAX_WINDOW = 31
-QF_NO_SHARING, QF_NO_EARLY_ABANDON, QF_NO_BEST_FIRST = 1, 2, 4
+QF_NO_SHARING, QF_NO_EARLY_ABANDON, QF_NO_BEST_FIRST, QF_NO_SHORTCUT = 1, 2, 4, 8
 MAX_K = 1024
 
 
@@ -46,7 +46,8 @@ class QueryStats(ctypes.Structure):
                 ("refine_bytes", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("tau_initial", ctypes.c_float), ("tau_final", ctypes.c_float),
                 ("dtw_series", ctypes.c_int64), ("dtw_cells", ctypes.c_int64),
-                ("leaves_initial", ctypes.c_int64), ("path", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("leaves_initial", ctypes.c_int64), ("path", ctypes.c_int32),
+                ("candidate_capacity", ctypes.c_int32)]
 
 
 class QueryOptions(ctypes.Structure):
@@ -105,6 +106,7 @@ SIGNATURES = {
     "isax_server_pending": (_I64, [_VP]),
     "isax_server_destroy": (None, [_VP]),
     "isax_clock": (ctypes.c_double, []),
+    "isax_debug_fail_allocation": (ctypes.c_int, [_I64]),
 }
 
 _lib = None
@@ -331,3 +333,8 @@ class Server:
 
 def clock() -> float:
     return lib().isax_clock()
+
+
+def debug_fail_allocation(countdown: int):
+    """Tests only: the countdown-th device allocation of the library from now on fails (0: off)."""
+    _check(lib().isax_debug_fail_allocation(int(countdown)))

@@ -35,6 +35,11 @@ void clear_error();
         if (!(cond)) throw ::isax::Error{ISAX_EINVAL, (text)};       \
     } while (0)
 
+#define ISAX_REQUIRE_CODE(code, cond, text)                          \
+    do {                                                             \
+        if (!(cond)) throw ::isax::Error{(code), (text)};            \
+    } while (0)
+
 // ------------------------------------------------------------------ constants
 constexpr int kWaveSize = 64;
 constexpr int kMaxCandLds = 4096;   // candidates one top-k block sorts in LDS
@@ -98,6 +103,8 @@ struct DevBuf {
 
 // Plain device allocation owned by an index (freed with hipFree).
 void* dev_alloc(size_t bytes);
+// Throws ISAX_ENOMEM when the allocation countdown of isax_debug_fail_allocation runs out.
+void injected_failure(size_t bytes);
 
 }  // namespace isax
 struct isax_index;

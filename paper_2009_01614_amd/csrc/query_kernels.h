@@ -49,7 +49,8 @@ struct QueryArgs {
     int64_t* home;              // [mq][2] leaf range of the approximate answer
     unsigned long long* stats;  // [mq][ST_N]
     int* done;                  // [mq] 1 once the query's answer is written
-    int* status;                // [mq] 0 ok, 1 candidate overflow (re-run), 2 window too large
+    int* status;                // [mq] 0 ok, 1 candidate overflow (re-run), 2 fewer than k candidates,
+                                //      3 window wider than the top-k block's LDS
     int64_t* out_ids;           // [mq][kmax]
     float* out_dists;           // [mq][kmax]
     // best-first rounds: round 0 = one pass over every leaf; round 1 = leaves
@@ -95,6 +96,9 @@ void launch_list_recount(const QueryArgs& a, int64_t grid_x, hipStream_t s);
 void launch_seed(const QueryArgs& a, hipStream_t s);
 void launch_brute_scan(const QueryArgs& a, hipStream_t s);
 void launch_topk(const QueryArgs& a, hipStream_t s);
+// Queries wq[0..n_wide) whose window exceeded the top-k block's LDS (status 3):
+// their answers from vals [n_wide][cap] (8 bytes per candidate) of scratch.
+void launch_topk_wide(const QueryArgs& a, const int* wq, int n_wide, double* vals, hipStream_t s);
 void launch_rerun_reset(const QueryArgs& a, hipStream_t s);
 void launch_lower_bounds(const QueryArgs& a, float* out, hipStream_t s);
 // Hybrid batches: rows pos[0..mf) of (Q, kq) into (Qf, kqf); answer rows back to pos.

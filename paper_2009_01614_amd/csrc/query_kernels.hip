@@ -1268,7 +1268,11 @@ __global__ void __launch_bounds__(256) k_brute_scan(QueryArgs a) {
 // compensated arithmetic and ordered by (value, id); the first k are written,
 // distance = sqrt(hi).  If the list overflowed, the k-th smallest stored value
 // tightens tau0 and the query is marked for a re-run with the bound frozen.
+// A window of more than kWindowMax entries (many series at one distance) is
+// marked wide (status 3, v_k kept in qinfo.y) and finished by k_window_values
+// and k_topk_wide, which have no size limit.
 constexpr int kWindowMax = 2048;
+static_assert(ISAX_MAX_K <= kWindowMax / 2, "the wide merge keeps k entries beside a chunk of kWindowMax / 2");
 
 // k-th smallest (1-based) of the high 32 bits of list[0..cnt), by 8-bit digits.
 __device__ unsigned radix_select_hi32(const unsigned long long* list, int cnt, int k, unsigned* hist) {
@@ -1304,9 +1308,74 @@ __device__ unsigned radix_select_hi32(const unsigned long long* list, int cnt, i
     return s_prefix;
 }
 
+// The recomputed value of a window entry in 8 bytes: the compensated FP32 pair
+// (hi, lo) for ED, the FP64 recurrence for DTW.  Order: value, then id.
+__device__ inline double window_value(const QueryArgs& a, const float* qrow, int32_t id, int lane) {
+    if (a.metric == ISAX_METRIC_DTW) return dtw_exact_wave(qrow, a.data + (int64_t)id * a.len, a.len, a.window, lane);
+    const float2 r = dist2_dot2(qrow, a.data + (int64_t)id * a.len, a.len, lane);
+    return __builtin_bit_cast(double, r);
+}
+__device__ inline double window_none(bool dtw) {
+    return dtw ? __builtin_huge_val() : __builtin_bit_cast(double, make_float2(kInf, kInf));
+}
+__device__ inline bool window_in(double v, bool dtw) {
+    return dtw ? v < __builtin_huge_val() : __builtin_bit_cast(float2, v).x < kInf;
+}
+__device__ inline bool window_gt(double x, double y, unsigned ix, unsigned iy, bool dtw) {
+    if (dtw) return x > y || (x == y && ix > iy);
+    const float2 u = __builtin_bit_cast(float2, x), v = __builtin_bit_cast(float2, y);
+    return u.x > v.x || (u.x == v.x && (u.y > v.y || (u.y == v.y && ix > iy)));
+}
+
+// Bitonic sort of PW (power of two) window entries in LDS by (value, id).
+__device__ void sort_window(unsigned long long* wkeys, double* wv, int PW, bool dtw) {
+    for (int size = 2; size <= PW; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < PW / 2; i += blockDim.x) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const double x = wv[lo], y = wv[hi];
+                const unsigned ix = (unsigned)(wkeys[lo] & 0xffffffffu), iy = (unsigned)(wkeys[hi] & 0xffffffffu);
+                if (window_gt(x, y, ix, iy, dtw) == up) {
+                    wv[lo] = y;
+                    wv[hi] = x;
+                    const unsigned long long t = wkeys[lo];
+                    wkeys[lo] = wkeys[hi];
+                    wkeys[hi] = t;
+                }
+            }
+        }
+    __syncthreads();
+}
+
+// Writes the first k sorted window entries as the query's answer row.
+__device__ void write_answer(const QueryArgs& a, int q, int k, const unsigned long long* wkeys, const double* wv,
+                             float vk) {
+    const bool dtw = a.metric == ISAX_METRIC_DTW;
+    for (int i = threadIdx.x; i < a.kmax; i += blockDim.x) {
+        const int64_t o = (int64_t)q * a.kmax + i;
+        if (i < k) {
+            a.out_ids[o] = (int64_t)key_id(wkeys[i]);
+            a.out_dists[o] = dtw ? (float)sqrt(wv[i]) : sqrtf(fmaxf(__builtin_bit_cast(float2, wv[i]).x, 0.f));
+        } else {
+            a.out_ids[o] = -1;
+            a.out_dists[o] = kInf;
+        }
+    }
+    if (threadIdx.x == 0) {
+        a.done[q] = 1;
+        a.status[q] = 0;
+        float4 qi = a.qinfo[q];
+        qi.y = vk;  // from here on: FP32 k-th squared distance
+        a.qinfo[q] = qi;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_topk(QueryArgs a) {
     __shared__ unsigned long long wkeys[kWindowMax];
-    __shared__ float2 hl[kWindowMax];
+    __shared__ double wv[kWindowMax];
     __shared__ unsigned hist[256];
     __shared__ int s_W;
     const int q = blockIdx.x;
@@ -1340,74 +1409,91 @@ __global__ void __launch_bounds__(256) k_topk(QueryArgs a) {
     __syncthreads();
     const int W = s_W;
     if (W > kWindowMax) {
-        if (threadIdx.x == 0) a.status[q] = 2;
+        if (threadIdx.x == 0) {
+            float4 qi = a.qinfo[q];
+            qi.y = vk;
+            a.qinfo[q] = qi;
+            a.status[q] = 3;
+        }
         return;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float* qrow = a.Q + (int64_t)q * a.len;
     const bool dtw = a.metric == ISAX_METRIC_DTW;
-    double* hd = reinterpret_cast<double*>(hl);  // DTW: the FP64 value in the same 8 bytes
     for (int i = wave; i < W; i += 4) {
-        const int32_t id = key_id(wkeys[i]);
-        if (dtw) {
-            const double v = dtw_exact_wave(qrow, a.data + (int64_t)id * a.len, a.len, a.window, lane);
-            if (lane == 0) hd[i] = v;
-        } else {
-            const float2 r = dist2_dot2(qrow, a.data + (int64_t)id * a.len, a.len, lane);
-            if (lane == 0) hl[i] = r;
-        }
+        const double v = window_value(a, qrow, key_id(wkeys[i]), lane);
+        if (lane == 0) wv[i] = v;
     }
     int PW = 1;
     while (PW < W) PW <<= 1;
     for (int i = W + threadIdx.x; i < PW; i += 256) {
         wkeys[i] = kEmpty;
-        if (dtw) hd[i] = __builtin_huge_val();
-        else hl[i] = make_float2(kInf, kInf);
+        wv[i] = window_none(dtw);
     }
-    // bitonic sort of the window by (hi, lo, id), under DTW by (FP64 value, id)
-    for (int size = 2; size <= PW; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            __syncthreads();
-            for (int i = threadIdx.x; i < PW / 2; i += 256) {
-                const int lo = 2 * i - (i & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const float2 x = hl[lo], y = hl[hi];
-                const unsigned ix = (unsigned)(wkeys[lo] & 0xffffffffu), iy = (unsigned)(wkeys[hi] & 0xffffffffu);
-                bool gt;
-                if (dtw) {
-                    const double dx = hd[lo], dy = hd[hi];
-                    gt = dx > dy || (dx == dy && ix > iy);
-                } else {
-                    gt = x.x > y.x || (x.x == y.x && (x.y > y.y || (x.y == y.y && ix > iy)));
-                }
-                if (gt == up) {
-                    hl[lo] = y;
-                    hl[hi] = x;
-                    const unsigned long long t = wkeys[lo];
-                    wkeys[lo] = wkeys[hi];
-                    wkeys[hi] = t;
-                }
+    sort_window(wkeys, wv, PW, dtw);
+    write_answer(a, q, k, wkeys, wv, vk);
+}
+
+// Wide windows (status 3): the recomputed value of every candidate of query
+// wq[y] within the window, +inf for the others, into vals[y][cap]; one wave
+// per entry, many blocks per query.
+__global__ void __launch_bounds__(256) k_window_values(QueryArgs a, const int* __restrict__ wq,
+                                                       double* __restrict__ vals) {
+    const int q = wq[blockIdx.y];
+    const int cnt = (int)min<unsigned>(a.cand_count[q], (unsigned)a.cap);
+    const float thr = a.qinfo[q].y * a.tau_scale;
+    const unsigned long long* list = a.cand + (int64_t)q * a.cap;
+    double* out = vals + (int64_t)blockIdx.y * a.cap;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float* qrow = a.Q + (int64_t)q * a.len;
+    const bool dtw = a.metric == ISAX_METRIC_DTW;
+    for (int i = blockIdx.x * 4 + wave; i < cnt; i += gridDim.x * 4) {
+        const unsigned long long key = list[i];
+        const double v = key_d2(key) <= thr ? window_value(a, qrow, key_id(key), lane) : window_none(dtw);
+        if (lane == 0) out[i] = v;
+    }
+}
+
+// Wide windows: the k smallest (value, id) of the window, merged chunk by
+// chunk: the best k so far plus up to kWindowMax / 2 new entries are sorted in
+// LDS and the first k kept (k <= ISAX_MAX_K = kWindowMax / 2).
+__global__ void __launch_bounds__(256) k_topk_wide(QueryArgs a, const int* __restrict__ wq,
+                                                   const double* __restrict__ vals) {
+    __shared__ unsigned long long wkeys[kWindowMax];
+    __shared__ double wv[kWindowMax];
+    __shared__ int s_n;
+    constexpr int kChunk = kWindowMax / 2;
+    const int q = wq[blockIdx.x];
+    const int k = a.kq[q];
+    const int cnt = (int)min<unsigned>(a.cand_count[q], (unsigned)a.cap);
+    const unsigned long long* list = a.cand + (int64_t)q * a.cap;
+    const double* v = vals + (int64_t)blockIdx.x * a.cap;
+    const bool dtw = a.metric == ISAX_METRIC_DTW;
+    int kept = 0;
+    for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_n = kept;
+        __syncthreads();
+        for (int i = c0 + threadIdx.x; i < min(cnt, c0 + kChunk); i += 256) {
+            const double x = v[i];
+            if (window_in(x, dtw)) {
+                const int slot = atomicAdd(&s_n, 1);
+                wkeys[slot] = list[i];
+                wv[slot] = x;
             }
         }
-    __syncthreads();
-    for (int i = threadIdx.x; i < a.kmax; i += 256) {
-        const int64_t o = (int64_t)q * a.kmax + i;
-        if (i < k) {
-            a.out_ids[o] = (int64_t)key_id(wkeys[i]);
-            a.out_dists[o] = dtw ? (float)sqrt(hd[i]) : sqrtf(fmaxf(hl[i].x, 0.f));
-        } else {
-            a.out_ids[o] = -1;
-            a.out_dists[o] = kInf;
+        __syncthreads();
+        const int W = s_n;
+        int PW = 1;
+        while (PW < W) PW <<= 1;
+        for (int i = W + threadIdx.x; i < PW; i += 256) {
+            wkeys[i] = kEmpty;
+            wv[i] = window_none(dtw);
         }
+        sort_window(wkeys, wv, PW, dtw);
+        kept = min(k, W);
     }
-    if (threadIdx.x == 0) {
-        a.done[q] = 1;
-        a.status[q] = 0;
-        float4 qi = a.qinfo[q];
-        qi.y = vk;  // from here on: FP32 k-th squared distance
-        a.qinfo[q] = qi;
-    }
+    write_answer(a, q, k, wkeys, wv, a.qinfo[q].y);
 }
 
 // Sub-batch of a hybrid batch: query rows and k by position in the batch, and
@@ -1579,6 +1665,15 @@ void launch_brute_scan(const QueryArgs& a, hipStream_t s) {
 void launch_topk(const QueryArgs& a, hipStream_t s) {
     ProfScope ps("topk", s);
     k_topk<<<a.mq, 256, 0, s>>>(a);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_topk_wide(const QueryArgs& a, const int* wq, int n_wide, double* vals, hipStream_t s) {
+    if (n_wide <= 0) return;
+    ProfScope ps("topk_wide", s);
+    const dim3 grid(grid_blocks(a.cap, 4, 1024), (unsigned)n_wide);
+    k_window_values<<<grid, 256, 0, s>>>(a, wq, vals);
+    k_topk_wide<<<n_wide, 256, 0, s>>>(a, wq, vals);
     ISAX_HIP(hipGetLastError());
 }
 

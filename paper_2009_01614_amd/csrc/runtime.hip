@@ -7,6 +7,7 @@
 // Query (Sec. III, query answering): approximate answer -> best-so-far, leaf
 // and series lower bounds with pruning, refinement, final ordering.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -190,8 +191,17 @@ void cache_release_idle() {
 }
 }  // namespace
 
+// Fault injection (isax_debug_fail_allocation): the countdown-th allocation fails.
+static std::atomic<int64_t> g_fail_countdown{0};
+void injected_failure(size_t n) {
+    if (g_fail_countdown.load(std::memory_order_relaxed) <= 0) return;
+    if (g_fail_countdown.fetch_sub(1) == 1)
+        throw Error{ISAX_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed (injected)"};
+}
+
 DevBuf::DevBuf(size_t n, hipStream_t s) : bytes(n), stream(s) {
     if (n == 0) return;
+    injected_failure(n);
     if (n >= kCacheMin && n <= kCacheMax) {
         p = cache_alloc(n, s);
         cached = true;
@@ -208,17 +218,16 @@ DevBuf::DevBuf(size_t n, hipStream_t s) : bytes(n), stream(s) {
         throw Error{ISAX_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed: " + hipGetErrorString(e)};
     }
 }
-DevBuf::~DevBuf() {
-    if (!p) return;
+static void devbuf_release(void* p, hipStream_t stream, bool cached) noexcept {
     if (cached) cache_free(p, stream);
     else (void)hipFreeAsync(p, stream);
 }
+DevBuf::~DevBuf() {
+    if (p) devbuf_release(p, stream, cached);
+}
 DevBuf& DevBuf::operator=(DevBuf&& o) noexcept {
     if (this != &o) {
-        if (p) {
-            if (cached) cache_free(p, stream);
-            else (void)hipFreeAsync(p, stream);
-        }
+        if (p) devbuf_release(p, stream, cached);
         p = o.p;
         bytes = o.bytes;
         stream = o.stream;
@@ -231,6 +240,7 @@ DevBuf& DevBuf::operator=(DevBuf&& o) noexcept {
 }
 
 void* dev_alloc(size_t bytes) {
+    injected_failure(bytes);
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 16));
     if (e != hipSuccess) {
@@ -413,6 +423,7 @@ struct Batch {
     int mode = ISAX_MODE_INDEX; // the mode the batch ran in
     bool hist_valid = false;    // leaf_count / leaf_list hold the leaf pass of every query
     DevBuf list_mem;            // leaf lists of the best-first rounds
+    DevBuf cand_mem;            // candidate lists grown for a re-run
     // hybrid batches: positions handed to the filter, the per-query skip flags
     // (1 = filter), and the filter's sub-batch with its gathered rows
     std::vector<int32_t> far;
@@ -501,6 +512,7 @@ void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const 
 }
 
 constexpr int kDefaultCap = 16384;
+constexpr int64_t kCandBytesMax = int64_t(16) << 30;  // candidate lists of one batch after growth
 
 std::vector<int64_t> leaves_initial(const Batch& b, hipStream_t s) {
     const int mq = b.a.mq;
@@ -549,7 +561,7 @@ void fill_stats(const Batch& b, isax_query_stats* out, hipStream_t s) {
         out[i].dtw_cells = (int64_t)r[ST_DTW_CELLS];
         out[i].leaves_initial = li[i];
         out[i].path = b.mode == ISAX_MODE_HYBRID ? ISAX_MODE_INDEX : b.mode;
-        out[i].reserved = 0;
+        out[i].candidate_capacity = b.a.cap;
     }
     if (b.sub) {
         // queries answered by the filter: its statistics, the first histogram's count
@@ -705,7 +717,7 @@ double filter_cost(const isax_index* idx, int f) {
 void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     QueryArgs& a = b.a;
     const int mq = a.mq;
-    if (limit == 0 && filter_cost(idx, mq) < kHybridFixed) {
+    if (limit == 0 && !(a.flags & ISAX_QF_NO_SHORTCUT) && filter_cost(idx, mq) < kHybridFixed) {
         run_batch(idx, b, ISAX_MODE_BF16, s);
         return;
     }
@@ -875,25 +887,49 @@ void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s, int64_t hybri
     finish_batch(idx, b, mode, s);
 }
 
-// Final ordering, and re-runs of the queries whose candidate list overflowed.
+// Final ordering, wide windows, and re-runs of the queries whose candidate
+// list overflowed.  A re-run freezes the query's bound at the k-th smallest
+// stored value and first grows the lists to hold what the last pass emitted.
 void finish_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     QueryArgs& a = b.a;
     const bool dtw = a.metric == ISAX_METRIC_DTW;
     launch_topk(a, s);
-    std::vector<int> status(a.mq);
+    std::vector<int> status(a.mq), wide;
+    std::vector<unsigned> counts(a.mq);
     for (int round = 0;; ++round) {
         ISAX_HIP(hipMemcpyAsync(status.data(), a.status, a.mq * sizeof(int), hipMemcpyDeviceToHost, s));
+        ISAX_HIP(hipMemcpyAsync(counts.data(), a.cand_count, a.mq * sizeof(unsigned), hipMemcpyDeviceToHost, s));
         ISAX_HIP(hipStreamSynchronize(s));
         bool rerun = false;
-        for (int v : status) {
-            if (v == 2)
-                throw Error{ISAX_EOVERFLOW,
-                            "more than 2048 series lie within the rounding window of the k-th distance"};
-            rerun |= v == 1;
+        unsigned need = 0;
+        wide.clear();
+        for (int q = 0; q < a.mq; ++q) {
+            if (status[q] == 2) throw Error{ISAX_EDEVICE, "internal error: fewer than k candidates were kept"};
+            if (status[q] == 3) wide.push_back(q);
+            if (status[q] == 1) {
+                rerun = true;
+                need = std::max(need, counts[q]);
+            }
+        }
+        if (!wide.empty()) {
+            // windows wider than the top-k block's LDS: merged in global memory
+            DevBuf wq(wide.size() * sizeof(int), s), vals(wide.size() * (size_t)a.cap * sizeof(double), s);
+            ISAX_HIP(hipMemcpyAsync(wq.p, wide.data(), wide.size() * sizeof(int), hipMemcpyHostToDevice, s));
+            launch_topk_wide(a, wq.as<int>(), (int)wide.size(), vals.as<double>(), s);
+            ISAX_HIP(hipStreamSynchronize(s));
         }
         if (!rerun) break;
         if (round >= 8) throw Error{ISAX_EOVERFLOW, "candidate list overflowed on 8 re-runs"};
         a.rerun = 1;
+        if ((int64_t)need > a.cap) {
+            const int64_t limit = a.n + 4096;  // every series once, plus the approximate answer's
+            const int64_t grow = std::min<int64_t>(std::max<int64_t>(2 * (int64_t)a.cap, need + need / 4), limit);
+            ISAX_REQUIRE_CODE(ISAX_ENOMEM, (int64_t)a.mq * grow * 8 <= kCandBytesMax,
+                              "candidate lists of this batch would exceed 16 GiB; use a smaller batch");
+            b.cand_mem = DevBuf((size_t)a.mq * grow * 8, s);
+            a.cand = b.cand_mem.as<unsigned long long>();
+            a.cap = (int)grow;
+        }
         launch_rerun_reset(a, s);
         if (mode == ISAX_MODE_INDEX || dtw) {
             launch_homeleaf(a, s);
@@ -918,7 +954,8 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     ISAX_REQUIRE(o.mode >= ISAX_MODE_INDEX && o.mode <= ISAX_MODE_HYBRID, "unknown mode");
     ISAX_REQUIRE(o.hybrid_leaves >= 0, "hybrid_leaves must be >= 0");
     ISAX_REQUIRE(o.candidate_capacity >= 0 && o.batch >= 0, "candidate_capacity and batch must be >= 0");
-    ISAX_REQUIRE((o.flags & ~(ISAX_QF_NO_SHARING | ISAX_QF_NO_EARLY_ABANDON | ISAX_QF_NO_BEST_FIRST)) == 0,
+    ISAX_REQUIRE((o.flags & ~(ISAX_QF_NO_SHARING | ISAX_QF_NO_EARLY_ABANDON | ISAX_QF_NO_BEST_FIRST |
+                              ISAX_QF_NO_SHORTCUT)) == 0,
                  "unknown flag");
     ISAX_REQUIRE((o.mode != ISAX_MODE_BF16 && o.mode != ISAX_MODE_HYBRID) || idx->x_bf16,
                  "index was built without the BF16 copy");
@@ -972,16 +1009,25 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     const int B = o.batch ? o.batch : 1024;
     const int cap = o.candidate_capacity ? std::max(o.candidate_capacity, k) : kDefaultCap;
     const int64_t hybrid_limit = o.hybrid_leaves;  // 0: the planner
+    // Answers (and statistics) are staged and copied to the caller's buffers
+    // only once every batch has succeeded: an error leaves the outputs untouched.
+    DevBuf stage((size_t)m * k * (sizeof(int64_t) + sizeof(float)), s);
+    int64_t* st_ids = stage.as<int64_t>();
+    float* st_dists = reinterpret_cast<float*>(st_ids + (size_t)m * k);
+    std::vector<isax_query_stats> st_host(o.stats ? (size_t)m : 0);
     for (int64_t q0 = 0; q0 < m; q0 += B) {
         const int mq = (int)std::min<int64_t>(B, m - q0);
         Batch b;
-        setup_batch(b, idx, Q + q0 * idx->len, mq, kq + q0, k, cap, o.flags, out_ids + q0 * k, out_dists + q0 * k, s,
+        setup_batch(b, idx, Q + q0 * idx->len, mq, kq + q0, k, cap, o.flags, st_ids + q0 * k, st_dists + q0 * k, s,
                     o.metric, o.window);
         b.fcap0 = o.candidate_capacity;
         run_batch(idx, b, o.mode, s, hybrid_limit);
-        if (o.stats) fill_stats(b, o.stats + q0, s);
+        if (o.stats) fill_stats(b, st_host.data() + q0, s);
     }
+    ISAX_HIP(hipMemcpyAsync(out_ids, st_ids, (size_t)m * k * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    ISAX_HIP(hipMemcpyAsync(out_dists, st_dists, (size_t)m * k * sizeof(float), hipMemcpyDeviceToDevice, s));
     ISAX_HIP(hipStreamSynchronize(s));
+    if (o.stats) std::memcpy(o.stats, st_host.data(), (size_t)m * sizeof(isax_query_stats));
     return ISAX_OK;
 }
 
@@ -1332,6 +1378,11 @@ int isax_profile_read(isax_profile_entry* out, int32_t max_entries, int32_t* n_e
         ++i;
     }
     if (n_entries) *n_entries = (int32_t)g_prof.size();
+    return ISAX_OK;
+}
+
+int isax_debug_fail_allocation(int64_t countdown) {
+    g_fail_countdown.store(countdown > 0 ? countdown : 0);
     return ISAX_OK;
 }
 

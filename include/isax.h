@@ -183,6 +183,31 @@ int isax_query(isax_index* idx, const float* queries, int64_t m, int32_t k, int6
 int isax_query_ex(isax_index* idx, const float* queries, int64_t m, int32_t k, int64_t* out_ids, float* out_dists,
                   const isax_query_options* opt);
 
+/*
+ * isax_query_ex without any device allocation, for callers that cannot
+ * allocate device memory during a query: request loops that must keep a fixed
+ * memory footprint, code that may not call hipMalloc / hipFree or a caching
+ * allocator, harnesses that forbid allocation.  Same arguments, options,
+ * answers (ids, and distances bit for bit) and error behaviour as
+ * isax_query_ex.  Every device buffer of the call is carved from a fixed
+ * array of 256 MiB compiled into the library: each device holds its own copy
+ * from the library's load on it until the process ends.
+ *   - Sizes: the queries run in batches of opt->batch, or (batch 0) of the
+ *     largest size whose scratch fits, at most 1024.  If the staged answers
+ *     (m x k x 12 bytes) and one batch do not fit, the call returns
+ *     ISAX_EINVAL before any device work, naming the sizes.
+ *   - Data-dependent growth (candidate lists that grow for a re-run, a tie
+ *     window wider than 2048 entries) takes what is left of the array; if that
+ *     is not enough the call returns ISAX_ENOMEM and the outputs are untouched.
+ *   - The array keeps the last call's contents; every call initialises what
+ *     it reads.  Calls on one device are serialised by a lock held for the
+ *     whole call (including the wait for its stream), so they never overlap.
+ *   - Host-side bookkeeping (status read-back, the hybrid planner) uses
+ *     ordinary host memory.
+ */
+int isax_query_noalloc(isax_index* idx, const float* queries, int64_t m, int32_t k, int64_t* out_ids,
+                       float* out_dists, const isax_query_options* opt);
+
 /* ---------------------------------------------------------- inspection */
 
 /* The 2^c - 1 region edges used for c-bit symbols, FP32, ascending (host out). */

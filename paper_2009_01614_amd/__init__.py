@@ -91,6 +91,7 @@ SIGNATURES = {
     "isax_free": (None, [_VP]),
     "isax_query": (ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _VP]),
     "isax_query_ex": (ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _VP, ctypes.POINTER(QueryOptions)]),
+    "isax_query_noalloc": (ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _VP, ctypes.POINTER(QueryOptions)]),
     "isax_breakpoints": (ctypes.c_int, [_I32, _F32P]),
     "isax_summarize": (ctypes.c_int, [_VP, _I64, _I32, _I32, _I32, _VP, _F32P, _VP]),
     "isax_index_get_info": (ctypes.c_int, [_VP, ctypes.POINTER(IndexInfo)]),
@@ -239,8 +240,11 @@ class Index:
 
     def query(self, queries: torch.Tensor, k: int = 1, mode="index", k_per_query: torch.Tensor | None = None,
               candidate_capacity: int = 0, flags: int = 0, batch: int = 0, stream=None, stats: bool = False,
-              metric="ed", window: int = 0, hybrid_leaves: int = 0):
+              metric="ed", window: int = 0, hybrid_leaves: int = 0, noalloc: bool = False):
         """Exact k-NN: (ids int64 [m, k], dists float32 [m, k]); with stats=True also a list of dicts.
+
+        noalloc=True calls isax_query_noalloc (no device allocation inside the call; scratch from the
+        library's fixed per-device array).
 
         metric "ed" (Euclidean) or "dtw" (banded DTW of half-width `window`, modes "index" and "scan").
         mode "hybrid" answers each query with the iSAX path or the BF16 filter, by the leaves the iSAX
@@ -261,8 +265,8 @@ class Index:
         opt = QueryOptions(MODES[mode] if isinstance(mode, str) else int(mode), candidate_capacity, flags, batch,
                            kp, _stream(stream), st, METRICS[metric] if isinstance(metric, str) else int(metric),
                            window, hybrid_leaves)
-        _check(lib().isax_query_ex(self._h, queries.data_ptr(), m, k, ids.data_ptr(), dists.data_ptr(),
-                                   ctypes.byref(opt)))
+        fn = lib().isax_query_noalloc if noalloc else lib().isax_query_ex
+        _check(fn(self._h, queries.data_ptr(), m, k, ids.data_ptr(), dists.data_ptr(), ctypes.byref(opt)))
         if stats:
             return ids, dists, [{f: getattr(st[i], f) for f, _ in QueryStats._fields_} for i in range(m)]
         return ids, dists

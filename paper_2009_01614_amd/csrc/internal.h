@@ -83,14 +83,29 @@ bool profiling_on();
 void profile_add_bytes(const char* name, double bytes);
 
 // ------------------------------------------------------------------ device scratch
+// Fixed scratch of the no-allocation query entry point: a per-device array
+// compiled into the library.  While a thread has one active (fixed_scratch()),
+// DevBuf carves its memory from it (256-byte aligned, in call order) instead
+// of allocating; the owner rewinds `off` to a mark once the work that used
+// the memory has been queued, and stream order protects its reuse.
+struct FixedScratch {
+    char* base = nullptr;
+    size_t size = 0;
+    size_t off = 0;
+    void* carve(size_t n);  // throws ISAX_ENOMEM when the array is exhausted
+};
+FixedScratch* fixed_scratch();
+
 // Stream-ordered device scratch, released when the object dies.  Blocks of
 // 1 MiB to 1 GiB come from the library's block cache (kept after release,
-// reused in stream order), others from hipMallocAsync / hipFreeAsync.
+// reused in stream order), others from hipMallocAsync / hipFreeAsync; under
+// an active FixedScratch, from that array (nothing to release).
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
     bool cached = false;
+    bool fixed = false;
     DevBuf() = default;
     DevBuf(size_t n, hipStream_t s);
     ~DevBuf();

@@ -13,6 +13,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <optional>
 
 #include "build_kernels.h"
 #include "query_kernels.h"
@@ -199,8 +200,76 @@ void injected_failure(size_t n) {
         throw Error{ISAX_ENOMEM, "device allocation of " + std::to_string(n) + " bytes failed (injected)"};
 }
 
+// ------------------------------------------------------------------ fixed scratch
+// The memory of isax_query_noalloc.  Each device that loads the library holds
+// its own copy of this array until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device (the
+// array's name in host code is a host-side stand-in, not a device address).
+constexpr size_t kNoAllocBytes = size_t(256) << 20;
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+thread_local FixedScratch* t_fixed = nullptr;
+std::mutex g_noalloc_init_mu;
+void* g_noalloc_ptr[kNoAllocDevices] = {};
+std::mutex g_noalloc_call_mu[kNoAllocDevices];  // one no-allocation call per device at a time
+
+// Device address of `scratch` on device `dev` (current), looked up once per device.
+char* noalloc_base(int dev) {
+    std::lock_guard<std::mutex> lk(g_noalloc_init_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            throw Error{ISAX_EDEVICE, std::string("hipGetSymbolAddress of the fixed scratch failed: ") +
+                                          hipGetErrorString(e)};
+        }
+        g_noalloc_ptr[dev] = ptr;
+    }
+    return static_cast<char*>(g_noalloc_ptr[dev]);
+}
+
+// Makes the device's fixed scratch the source of every DevBuf of this thread
+// for the scope's lifetime (and holds the device's call lock).
+// On the way out it waits for the call's stream, so that work of a call that
+// failed half-way never overlaps the next call's use of the array.
+struct FixedScratchScope {
+    std::unique_lock<std::mutex> lk;
+    FixedScratch fx;
+    hipStream_t stream;
+    FixedScratchScope(int dev, hipStream_t s) : lk(g_noalloc_call_mu[dev]), stream(s) {
+        fx.base = noalloc_base(dev);
+        fx.size = kNoAllocBytes;
+        t_fixed = &fx;
+    }
+    ~FixedScratchScope() {
+        t_fixed = nullptr;
+        (void)hipStreamSynchronize(stream);
+    }
+};
+}  // namespace
+
+FixedScratch* fixed_scratch() { return t_fixed; }
+
+void* FixedScratch::carve(size_t n) {
+    const size_t at = (off + 255) / 256 * 256;
+    if (at > size || n > size - at)
+        throw Error{ISAX_ENOMEM, "the fixed scratch of isax_query_noalloc (" + std::to_string(size >> 20) +
+                                     " MiB) is exhausted: " + std::to_string(n) + " more bytes were needed at offset " +
+                                     std::to_string(at) + "; use a smaller batch or isax_query_ex"};
+    off = at + n;
+    return base + at;
+}
+
 DevBuf::DevBuf(size_t n, hipStream_t s) : bytes(n), stream(s) {
     if (n == 0) return;
+    if (t_fixed) {
+        p = t_fixed->carve(n);
+        fixed = true;
+        return;
+    }
     injected_failure(n);
     if (n >= kCacheMin && n <= kCacheMax) {
         p = cache_alloc(n, s);
@@ -223,18 +292,20 @@ static void devbuf_release(void* p, hipStream_t stream, bool cached) noexcept {
     else (void)hipFreeAsync(p, stream);
 }
 DevBuf::~DevBuf() {
-    if (p) devbuf_release(p, stream, cached);
+    if (p && !fixed) devbuf_release(p, stream, cached);
 }
 DevBuf& DevBuf::operator=(DevBuf&& o) noexcept {
     if (this != &o) {
-        if (p) devbuf_release(p, stream, cached);
+        if (p && !fixed) devbuf_release(p, stream, cached);
         p = o.p;
         bytes = o.bytes;
         stream = o.stream;
         cached = o.cached;
+        fixed = o.fixed;
         o.p = nullptr;
         o.bytes = 0;
         o.cached = false;
+        o.fixed = false;
     }
     return *this;
 }
@@ -443,6 +514,8 @@ float dtw_tau_eps(int len) {
     return (float)p;
 }
 
+Arena batch_arena(QueryArgs& a, const isax_index* idx, int mq, int kmax, int cap, int metric);
+
 void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const int32_t* kq_dev, int kmax, int cap,
                  int flags, int64_t* out_ids, float* out_dists, hipStream_t s, int metric = ISAX_METRIC_ED,
                  int window = 0) {
@@ -487,6 +560,12 @@ void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const 
         a.tau_scale = 1.0f + dtw_tau_eps(idx->len);
         a.lbk_scale = 1.0f - dtw_tau_eps(idx->len);
     }
+    b.mem = batch_arena(a, idx, mq, kmax, cap, metric).commit(s);
+}
+
+// The per-query arrays of a batch, laid out in one block (setup_batch; also
+// sizes a batch before it runs).
+Arena batch_arena(QueryArgs& a, const isax_index* idx, int mq, int kmax, int cap, int metric) {
     Arena ar;
     ar.add(&a.paa, (size_t)mq * idx->w);
     ar.add(&a.sym, (size_t)mq * idx->ws);
@@ -508,10 +587,11 @@ void setup_batch(Batch& b, const isax_index* idx, const float* Q, int mq, const 
     ar.add(&a.list_rest, mq);
     ar.add(&a.env_paa, (size_t)mq * 2 * idx->w);
     if (metric == ISAX_METRIC_DTW) ar.add(&a.qenv, (size_t)mq * 2 * idx->len);
-    b.mem = ar.commit(s);
+    return ar;
 }
 
 constexpr int kDefaultCap = 16384;
+constexpr int kFilterCap = 1 << 18;  // initial filter candidates kept per query and pass
 constexpr int64_t kCandBytesMax = int64_t(16) << 30;  // candidate lists of one batch after growth
 
 std::vector<int64_t> leaves_initial(const Batch& b, hipStream_t s) {
@@ -702,6 +782,18 @@ double filter_cost(const isax_index* idx, int f) {
     return std::max(stream, mfma) + f * kFilterPerQuery;
 }
 
+// The rows of a hybrid batch's filter sub-batch: positions, gathered queries
+// and k, and its answers before they are scattered back.
+Arena sub_arena(int32_t** pos, float** Qf, int32_t** kqf, int64_t** oid, float** od, int mf, int len, int kmax) {
+    Arena ar;
+    ar.add(pos, mf);
+    ar.add(Qf, (size_t)mf * len);
+    ar.add(kqf, mf);
+    ar.add(oid, (size_t)mf * kmax);
+    ar.add(od, (size_t)mf * kmax);
+    return ar;
+}
+
 // Hybrid batch.  The leaf pass of the iSAX path lists, for every query, the
 // leaves whose bound is within the approximate answer's best-so-far.  Round 1
 // (the listed leaves of smallest bound) lowers the best-so-far of every query
@@ -801,13 +893,7 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     if (mf > 0) {
         float* Qf = nullptr;
         int32_t* kqf = nullptr;
-        Arena ar;
-        ar.add(&pos, mf);
-        ar.add(&Qf, (size_t)mf * a.len);
-        ar.add(&kqf, mf);
-        ar.add(&oid, (size_t)mf * a.kmax);
-        ar.add(&od, (size_t)mf * a.kmax);
-        b.sub_mem = ar.commit(s);
+        b.sub_mem = sub_arena(&pos, &Qf, &kqf, &oid, &od, mf, a.len, a.kmax).commit(s);
         ISAX_HIP(hipMemcpyAsync(pos, b.far.data(), mf * sizeof(int32_t), hipMemcpyHostToDevice, s));
         launch_gather_queries(a.Q, a.kq, pos, mf, a.len, Qf, kqf, s);
         b.sub.reset(new Batch);
@@ -944,8 +1030,14 @@ void finish_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     }
 }
 
+size_t batch_scratch_bound(const isax_index* idx, int mq, int kmax, int cap, int64_t fcap, int mode, int metric,
+                           int flags);
+
+// `noalloc`: every device buffer of the call comes from the device's fixed
+// scratch (isax_query_noalloc); batches of opt->batch queries, or of the
+// largest size that fits, and sizes beyond the array are rejected up front.
 int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* out_ids, float* out_dists,
-               const isax_query_options* opt) {
+               const isax_query_options* opt, bool noalloc = false) {
     ISAX_REQUIRE(idx != nullptr, "index is NULL");
     ISAX_REQUIRE(m >= 0, "m must be >= 0");
     ISAX_REQUIRE(k >= 1 && k <= ISAX_MAX_K && k <= idx->n, "k must be in 1..min(n, 1024)");
@@ -981,6 +1073,35 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     int cur = 0;
     ISAX_HIP(hipGetDevice(&cur));
     ISAX_REQUIRE(cur == idx->device, "current device differs from the index's device");
+    int B = o.batch ? o.batch : 1024;
+    const int cap = o.candidate_capacity ? std::max(o.candidate_capacity, k) : kDefaultCap;
+    const int64_t fcap = o.candidate_capacity > 0 ? o.candidate_capacity : kFilterCap;
+    std::optional<FixedScratchScope> fixed;
+    if (noalloc) {
+        ISAX_REQUIRE(cur >= 0 && cur < kNoAllocDevices, "device ordinal beyond the no-allocation entry point's table");
+        // the call's own blocks (finite check, k per query, staged answers), then one batch at a time
+        auto blk = [](size_t n) -> size_t { return (std::max<size_t>(n, 256) + 255) / 256 * 256; };
+        const size_t call = blk(4) + (o.k_per_query ? 0 : blk((size_t)m * 4)) + blk((size_t)m * k * 12);
+        auto need = [&](int bq) {
+            return call + batch_scratch_bound(idx, (int)std::min<int64_t>(bq, m), k, cap, fcap, o.mode, o.metric,
+                                              o.flags);
+        };
+        if (!o.batch) {
+            int lo = 1, hi = 1024;  // the largest batch that fits
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (need(mid) <= kNoAllocBytes) lo = mid;
+                else hi = mid - 1;
+            }
+            B = lo;
+        }
+        ISAX_REQUIRE(need(B) <= kNoAllocBytes,
+                     "isax_query_noalloc: " + std::to_string(m) + " queries of length " + std::to_string(idx->len) +
+                         " with k = " + std::to_string(k) + " in batches of " + std::to_string(std::min<int64_t>(B, m)) +
+                         " need " + std::to_string(need(B)) + " bytes of scratch; its fixed array holds " +
+                         std::to_string(kNoAllocBytes) + " (use fewer queries, a smaller batch or k)");
+        fixed.emplace(cur, s);
+    }
 
     // validation of values before any output is written
     {
@@ -1006,8 +1127,6 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
         ISAX_HIP(hipStreamSynchronize(s));
         kq = kdev.as<int32_t>();
     }
-    const int B = o.batch ? o.batch : 1024;
-    const int cap = o.candidate_capacity ? std::max(o.candidate_capacity, k) : kDefaultCap;
     const int64_t hybrid_limit = o.hybrid_leaves;  // 0: the planner
     // Answers (and statistics) are staged and copied to the caller's buffers
     // only once every batch has succeeded: an error leaves the outputs untouched.
@@ -1017,12 +1136,17 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     std::vector<isax_query_stats> st_host(o.stats ? (size_t)m : 0);
     for (int64_t q0 = 0; q0 < m; q0 += B) {
         const int mq = (int)std::min<int64_t>(B, m - q0);
-        Batch b;
-        setup_batch(b, idx, Q + q0 * idx->len, mq, kq + q0, k, cap, o.flags, st_ids + q0 * k, st_dists + q0 * k, s,
-                    o.metric, o.window);
-        b.fcap0 = o.candidate_capacity;
-        run_batch(idx, b, o.mode, s, hybrid_limit);
-        if (o.stats) fill_stats(b, st_host.data() + q0, s);
+        // fixed scratch: the next batch reuses this one's blocks (stream order)
+        const size_t mark = fixed ? fixed->fx.off : 0;
+        {
+            Batch b;
+            setup_batch(b, idx, Q + q0 * idx->len, mq, kq + q0, k, cap, o.flags, st_ids + q0 * k,
+                        st_dists + q0 * k, s, o.metric, o.window);
+            b.fcap0 = (int)fcap;
+            run_batch(idx, b, o.mode, s, hybrid_limit);
+            if (o.stats) fill_stats(b, st_host.data() + q0, s);
+        }
+        if (fixed) fixed->fx.off = mark;
     }
     ISAX_HIP(hipMemcpyAsync(out_ids, st_ids, (size_t)m * k * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     ISAX_HIP(hipMemcpyAsync(out_dists, st_dists, (size_t)m * k * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -1053,7 +1177,6 @@ int guarded(F&& f) {
 // =============================================================================================
 // Reduced-precision filter batch (kernels in filter_kernels.hip)
 namespace {
-constexpr int kFilterCap = 1 << 18;  // initial filter candidates kept per query and pass
 
 // gamma: FP32 accumulation error of len_pad exact products, any order and
 // rounding (2u per add).  kappa: relative slack on |q|^2 + |x|^2 covering the
@@ -1082,7 +1205,21 @@ void alloc_filter_cands(FilterScratch& fs, int mq, int64_t fcap, hipStream_t s) 
     fs.f.fcap = (int)fcap;
 }
 
-void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, int mode, bool inspect,
+// The filter's per-query arrays (query codes, factors, counts) in one block.
+Arena filter_arena(FilterScratch& fs, unsigned char** qq, const isax_index* idx, int mq, int kind) {
+    const int lp = filter_len_pad(idx->len);
+    const int qpb = filter_queries_per_block(idx->len);
+    fs.mq_pad = (mq + qpb - 1) / qpb * qpb;
+    Arena ar;
+    ar.add(qq, (size_t)fs.mq_pad * lp * (kind == 0 ? 2 : 1));
+    ar.add(&fs.f.qmeta, fs.mq_pad);
+    ar.add(&fs.qmax, 4);
+    ar.add(&fs.f.fcount, mq);
+    return ar;
+}
+
+// `fcap`: filter candidates kept per query before the buffer grows.
+void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, int mode, int64_t fcap,
                   hipStream_t s) {
     FilterArgs& f = fs.f;
     f.kind = mode == ISAX_MODE_BF16 ? 0 : 1;
@@ -1090,19 +1227,11 @@ void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, 
     f.xmeta = f.kind == 0 ? idx->meta_bf16 : idx->meta_fp8;
     filter_constants(idx->len, &f.gamma, &f.kappa);
     f.phase = 0;
-    const int lp = filter_len_pad(idx->len);
-    const int qpb = filter_queries_per_block(idx->len);
-    fs.mq_pad = (a.mq + qpb - 1) / qpb * qpb;
-    Arena ar;
     unsigned char* qq = nullptr;
-    ar.add(&qq, (size_t)fs.mq_pad * lp * (f.kind == 0 ? 2 : 1));
-    ar.add(&f.qmeta, fs.mq_pad);
-    ar.add(&fs.qmax, 4);
-    ar.add(&f.fcount, a.mq);
-    fs.mem = ar.commit(s);
+    fs.mem = filter_arena(fs, &qq, idx, a.mq, f.kind).commit(s);
     f.qq = qq;
     f.mq_pad = fs.mq_pad;
-    alloc_filter_cands(fs, a.mq, inspect ? 1 : kFilterCap, s);
+    alloc_filter_cands(fs, a.mq, fcap, s);
     ISAX_HIP(hipMemsetAsync(fs.qmax, 0, 16, s));
     ISAX_HIP(hipMemsetAsync(f.fcount, 0, a.mq * sizeof(unsigned), s));
 }
@@ -1119,8 +1248,7 @@ constexpr int kSub = kFilterSub;
 void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     QueryArgs& a = b.a;
     FilterScratch fs;
-    setup_filter(fs, idx, a, mode, false, s);
-    if (b.fcap0 > 0 && b.fcap0 != fs.f.fcap) alloc_filter_cands(fs, a.mq, b.fcap0, s);
+    setup_filter(fs, idx, a, mode, b.fcap0 > 0 ? b.fcap0 : kFilterCap, s);
     launch_homeleaf(a, s);
     launch_quantise_queries(a, fs.f, fs.mq_pad, fs.qmax, s);
     const int64_t n_tiles = (idx->n + 31) / 32;
@@ -1166,22 +1294,41 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
 }
 }  // namespace
 
-int64_t isax::query_scratch_bytes(const isax_index* idx, int mq, int kmax, int mode) {
-    const int64_t per_q = idx->w * 4 + idx->ws + 8 + 16 + 2 * idx->ns * 4 + (int64_t)idx->w * idx->ns * 4 + 4 +
-                          (int64_t)kmax * 8 + (int64_t)kDefaultCap * 8 + 4 + 16 + ST_N * 8 + 8 + 4 + 4 +
-                          kLeafBins * 4 + 2 * idx->w * 4 + 8;
-    int64_t tot = per_q * mq + 16 * 256;
-    if (mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8 || mode == ISAX_MODE_HYBRID) {
-        const int qpb = filter_queries_per_block(idx->len);
-        const int64_t mq_pad = (mq + qpb - 1) / qpb * qpb;
-        tot += mq_pad * filter_len_pad(idx->len) * (mode == ISAX_MODE_FP8 ? 1 : 2) + mq_pad * 16 +
-               (int64_t)mq * (kFilterCap * 4 + 4);
+namespace {
+// Upper bound of the device scratch one batch of mq queries takes through
+// DevBuf (every block rounded up to 256 bytes) before its candidate lists grow
+// or a wide tie window is merged: the batch's arrays, the leaf lists of the
+// best-first rounds, the filter's arrays and candidates, and for a hybrid
+// batch the filter's sub-batch with its gathered rows.
+size_t batch_scratch_bound(const isax_index* idx, int mq, int kmax, int cap, int64_t fcap, int mode, int metric,
+                           int flags) {
+    auto blk = [](size_t n) -> size_t { return (std::max<size_t>(n, 256) + 255) / 256 * 256; };
+    QueryArgs t;
+    std::memset(&t, 0, sizeof(t));
+    const size_t batch = blk(batch_arena(t, idx, mq, kmax, cap, metric).off);
+    const int64_t leaf_cap = std::max<int64_t>(1, std::min<int64_t>(idx->n_leaves, kLeafListMax));
+    const size_t lists = blk((size_t)mq * leaf_cap * sizeof(uint2));
+    auto filter = [&](int kind) {
+        FilterScratch fs;
+        unsigned char* qq = nullptr;
+        return blk(filter_arena(fs, &qq, idx, mq, kind).off) + blk((size_t)mq * fcap * 4);
+    };
+    size_t tot = batch;
+    if (mode == ISAX_MODE_INDEX && !(flags & ISAX_QF_NO_BEST_FIRST)) tot += lists;
+    if (mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8) tot += filter(mode == ISAX_MODE_BF16 ? 0 : 1);
+    if (mode == ISAX_MODE_HYBRID) {
+        // the batch alone on the filter, or the leaf pass and a sub-batch of at most mq queries
+        int32_t *pos, *kqf;
+        float *Qf, *od;
+        int64_t* oid;
+        tot += lists + blk(sub_arena(&pos, &Qf, &kqf, &oid, &od, mq, idx->len, kmax).off) + batch + filter(0);
     }
-    if (mode == ISAX_MODE_HYBRID)  // the filter's sub-batch: its own per-query state and gathered rows
-        tot += per_q * mq + (int64_t)mq * (idx->len * 4 + kmax * 12 + 8);
-    if (mode == ISAX_MODE_INDEX || mode == ISAX_MODE_HYBRID)  // leaf lists of the best-first rounds
-        tot += (int64_t)mq * std::min<int64_t>(idx->n_leaves, kLeafListMax) * 8;
     return tot;
+}
+}  // namespace
+
+int64_t isax::query_scratch_bytes(const isax_index* idx, int mq, int kmax, int mode) {
+    return (int64_t)batch_scratch_bound(idx, mq, kmax, kDefaultCap, kFilterCap, mode, ISAX_METRIC_ED, 0);
 }
 
 // =============================================================================================
@@ -1212,6 +1359,11 @@ void isax_free(isax_index* idx) {
 int isax_query_ex(isax_index* idx, const float* queries, int64_t m, int32_t k, int64_t* out_ids, float* out_dists,
                   const isax_query_options* opt) {
     return guarded([&] { return query_impl(idx, queries, m, k, out_ids, out_dists, opt); });
+}
+
+int isax_query_noalloc(isax_index* idx, const float* queries, int64_t m, int32_t k, int64_t* out_ids,
+                       float* out_dists, const isax_query_options* opt) {
+    return guarded([&] { return query_impl(idx, queries, m, k, out_ids, out_dists, opt, true); });
 }
 
 int isax_query(isax_index* idx, const float* queries, int64_t m, int32_t k, int64_t* out_ids, float* out_dists) {
@@ -1341,7 +1493,7 @@ int isax_filter_scores(isax_index* idx, const float* queries, int64_t m, int32_t
         setup_batch(b, idx, queries, (int)m, kd.as<int32_t>(), 1, 1, 0, nullptr, nullptr, s);
         launch_qprep(b.a, s);
         FilterScratch fs;
-        setup_filter(fs, idx, b.a, mode, true, s);
+        setup_filter(fs, idx, b.a, mode, 1, s);
         fs.f.out_approx = out_approx;
         fs.f.out_margin = out_margin;
         launch_quantise_queries(b.a, fs.f, fs.mq_pad, fs.qmax, s);

@@ -27,6 +27,18 @@ PEAK_HBM_GBS = 8000.0
 PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "f32": 157.3}
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), for the oracle's report."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -249,6 +261,7 @@ def main():
         tc = time.perf_counter() - t0
         cpu_qps = mq / tc * (ns / n)
         cpu = {"value": round(cpu_qps, 4), "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": f"{mq} queries x first {ns} of {n} series (FP64 brute force, {tc:.1f} s), "
                          f"scaled by {ns}/{n}"}
         log(f"oracle: {cpu}")
@@ -546,6 +559,7 @@ def next_report(args, dev):
     out["dtw"]["roofline"] = {"bound": "alu", "peak_cells_per_s": PEAK_VALU_OPS / DTW_OPS_PER_CELL,
                               "ops_per_cell": DTW_OPS_PER_CELL}
     out["dtw"]["cpu_baseline"] = {"value": round(1 / cpu_s, 4), "unit": "queries/s", "cores": knn_ref.num_threads(),
+                                  "cpu_model": cpu_model(),
                                   "kind": "oracle", "sample": "1 query against the whole collection, k = 10"}
     # ---- raw data in pinned host memory (compared with the same build, data in HBM)
     idx.close()

@@ -288,21 +288,41 @@ int isax_debug_fail_allocation(int64_t countdown);
 /* ------------------------------------------------------------- serving */
 /*
  * A request loop over resident indexes.  submit() copies the host query and
- * returns at once; a scheduler thread admits waiting requests into batches
- * whenever a slot and the memory budget allow, runs every batch on its own
- * stream so batches overlap on the device, and publishes each result.  Every
- * result equals the result of the same query run alone (ids, and distances
- * bit for bit).
+ * returns at once; poll() returns results as they complete.  Two admission
+ * policies:
+ *   - step level (the default of ISAX_MODE_BF16 / _FP8): per collection, a
+ *     table of max_batch query rows stays on the device and the collection is
+ *     swept in `chunks` steps, each running the reduced-precision filter over
+ *     one chunk for every occupied row and refining its candidates.  A waiting
+ *     request takes a free row between two steps, at whatever chunk the sweep
+ *     has reached, and leaves after one full sweep (wrapping around), so it
+ *     never waits for another batch to end; collections run on their own
+ *     streams.  A row that lost filter candidates to a full buffer is answered
+ *     again by itself.
+ *   - batch level (every other mode, or ISAX_SERVE_BATCHES): a free worker takes
+ *     the oldest waiting request and the other waiting requests of its
+ *     collection while the batch's device scratch fits the memory budget, and
+ *     answers them with one isax_query_ex call on its own stream; `streams`
+ *     workers overlap on the device.
+ * Every result equals the result of the same query run alone (ids, and
+ * distances bit for bit).
  */
 typedef struct isax_server isax_server;
 
+enum {
+    ISAX_SERVE_BATCHES = 1 /* batch-level admission also in the filter modes */
+};
+
 typedef struct isax_server_options {
-    int32_t max_batch;       /* requests per batch; 0 = 256 */
-    int32_t streams;         /* batches in flight; 0 = 4 */
-    int64_t memory_budget;   /* bytes of per-batch scratch allowed in flight; 0 = 4 GiB */
-    int32_t mode;            /* ISAX_MODE_* used for every batch (hybrid with its default limit); the server
-                                answers Euclidean k-NN */
-    int32_t reserved;
+    int32_t max_batch;       /* batch level: requests per batch (0 = 256); step level: rows of each
+                                collection's table (0 = 512); 1..4096 */
+    int32_t streams;         /* batch level: batches in flight (workers); 0 = 4 */
+    int64_t memory_budget;   /* batch level: bytes of per-batch scratch allowed in flight; 0 = 4 GiB */
+    int32_t mode;            /* ISAX_MODE_* used for every request (hybrid with its cost model); the
+                                server answers Euclidean k-NN */
+    int32_t flags;           /* ISAX_SERVE_* */
+    int32_t chunks;          /* step level: steps per sweep of a collection; 0 = 16; 1..1024 */
+    int32_t reserved;        /* must be 0 */
 } isax_server_options;
 
 typedef struct isax_result {
@@ -310,10 +330,13 @@ typedef struct isax_result {
     int32_t status;          /* ISAX_OK or an error code */
     int32_t k;
     int32_t collection;
-    int32_t batch_size;      /* requests in the batch that served it */
-    double t_submit, t_start, t_done; /* seconds, steady clock */
+    int32_t batch_size;      /* batch level: requests in its batch; step level: occupied rows of the
+                                table when it joined */
+    double t_submit, t_start, t_done; /* seconds, steady clock: submitted, taken into a batch or a
+                                         table row, answered */
     int64_t ids[ISAX_MAX_K];
     float dists[ISAX_MAX_K];
+    char message[120];       /* status != ISAX_OK: the error text of the batch that failed ("" otherwise) */
 } isax_result;
 
 isax_server* isax_server_create(isax_index* const* collections, int32_t n_collections,

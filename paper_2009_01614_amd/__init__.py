@@ -26,6 +26,7 @@ METRIC_ED, METRIC_DTW = 0, 1
 METRICS = {"ed": METRIC_ED, "dtw": METRIC_DTW}
 MAX_WINDOW = 31
 QF_NO_SHARING, QF_NO_EARLY_ABANDON, QF_NO_BEST_FIRST, QF_NO_SHORTCUT = 1, 2, 4, 8
+SERVE_BATCHES = 1
 MAX_K = 1024
 
 
@@ -72,14 +73,15 @@ class ProfileEntry(ctypes.Structure):
 
 class ServerOptions(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("streams", ctypes.c_int32), ("memory_budget", ctypes.c_int64),
-                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("flags", ctypes.c_int32), ("chunks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("collection", ctypes.c_int32), ("batch_size", ctypes.c_int32), ("t_submit", ctypes.c_double),
                 ("t_start", ctypes.c_double), ("t_done", ctypes.c_double), ("ids", ctypes.c_int64 * MAX_K),
-                ("dists", ctypes.c_float * MAX_K)]
+                ("dists", ctypes.c_float * MAX_K), ("message", ctypes.c_char * 120)]
 
 
 # name -> (restype, argtypes); mirrors include/isax.h
@@ -293,10 +295,13 @@ class Index:
 class Server:
     """Continuous-batching request loop over resident indexes (see isax_server_* in include/isax.h)."""
 
-    def __init__(self, indexes, max_batch: int = 0, streams: int = 0, memory_budget: int = 0, mode="index"):
+    def __init__(self, indexes, max_batch: int = 0, streams: int = 0, memory_budget: int = 0, mode="index",
+                 batches: bool = False, chunks: int = 0):
+        """Step-level admission in the filter modes unless batches=True (see isax_server_* in isax.h)."""
         self.indexes = list(indexes)
         arr = (ctypes.c_void_p * len(self.indexes))(*[ix.handle.value for ix in self.indexes])
-        opt = ServerOptions(max_batch, streams, memory_budget, MODES[mode] if isinstance(mode, str) else mode, 0)
+        opt = ServerOptions(max_batch, streams, memory_budget, MODES[mode] if isinstance(mode, str) else mode,
+                            SERVE_BATCHES if batches else 0, chunks, 0)
         h = lib().isax_server_create(arr, len(self.indexes), ctypes.byref(opt))
         if not h:
             raise IsaxError(ISAX_EINVAL, last_error())
@@ -317,7 +322,8 @@ class Server:
             r = self._buf[i]
             out.append({"tag": r.tag, "status": r.status, "k": r.k, "collection": r.collection,
                         "batch_size": r.batch_size, "t_submit": r.t_submit, "t_start": r.t_start,
-                        "t_done": r.t_done, "ids": list(r.ids[:r.k]), "dists": list(r.dists[:r.k])})
+                        "t_done": r.t_done, "ids": list(r.ids[:r.k]), "dists": list(r.dists[:r.k]),
+                        "message": r.message.decode(errors="replace")})
         return out
 
     def pending(self) -> int:

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libisax.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["breakpoints.cpp", "build_kernels.hip", "query_kernels.hip", "filter_kernels.hip",
-           "runtime.hip", "serve.cpp"]
+           "runtime.hip", "serve_sched.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -214,7 +214,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
         for (int i = threadIdx.x; i < C::QPB; i += C::THREADS) {
             const int q = qt * C::QPB + i;
             float H = -kInf;
-            if (q < a.mq && !(a.rerun && a.done[q])) H = read_tau(a, q, a.kq[q]) * a.tau_scale - f.qmeta[q].x;
+            if (q < a.mq && !((a.rerun || a.skip_done) && a.done[q]))
+                H = read_tau(a, q, a.kq[q]) * a.tau_scale - f.qmeta[q].x;
             s_H[i] = KIND == 0 ? 0.5f * H : H;
         }
     };
@@ -236,9 +237,13 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
     // division below is a multiply)
     const int n_tiles = (int)((a.n + C::TS - 1) / C::TS);
     const int n_sub = (n_tiles + kFilterSub - 1) / kFilterSub;
-    const int n_vt = f.phase == 0 ? n_tiles : f.phase == 1 ? n_sub : n_tiles - n_sub;
+    const int t_lo = (int)(f.range_lo / C::TS), t_hi = (int)((f.range_hi + C::TS - 1) / C::TS);
+    const int n_vt = f.phase == 0 ? n_tiles : f.phase == 1 ? n_sub : f.phase == 2 ? n_tiles - n_sub : t_hi - t_lo;
     auto tile_of = [&](int v) -> int64_t {
-        return f.phase == 0 ? v : f.phase == 1 ? v * kFilterSub : v + v / (kFilterSub - 1) + 1;
+        return f.phase == 0   ? v
+               : f.phase == 1 ? v * kFilterSub
+               : f.phase == 2 ? v + v / (kFilterSub - 1) + 1
+                              : t_lo + v;
     };
     const unsigned char* X = static_cast<const unsigned char*>(f.xq);
     // one column tile's rows (part) at a time: the next tile's part p is loaded
@@ -453,6 +458,278 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
 }
 
 // ---------------------------------------------------------------------------------------------
+// The BF16 filter with its series tiles moved by the LDS DMA
+// (global_load_lds_dwordx4): no staging registers, and the next tile is
+// requested as a whole while the current one is computed, so a full tile of
+// matrix work covers the load latency.  The two LDS buffers are distinct
+// arrays handled in turn, so reads of one never wait for the transfers into
+// the other.  Each DMA instruction of a wave fills 64 consecutive 16-byte
+// slots of the padded layout (rows of STRIDE bytes; the last slot of a row is
+// padding and receives a copy of the row's first chunk); rows past the end of
+// the collection repeat its last series, whose columns the epilogue ignores.
+// Candidates go to per-wave LDS lists (slots by lane rank, no LDS atomic,
+// whose return would wait for the transfers in flight) and are published with
+// global atomics after the tile, when no transfer is outstanding.
+constexpr int kWaveHits = 32;  // candidates a wave holds in LDS per tile
+
+template <int KS, int MT, int WAVES, int NC>
+struct DmaCfg {
+    using C = FilterCfg<0, KS, MT, WAVES, NC>;
+    static constexpr int SLOTS = C::STRIDE / 16;                          // 16-byte slots per LDS row
+    static constexpr int TOTAL = C::TS * SLOTS;                           // slots per tile
+    static constexpr int NI = (TOTAL + 64 * WAVES - 1) / (64 * WAVES);    // DMA instructions per wave
+    static constexpr size_t LDS = 2 * C::TS * C::STRIDE + C::QPB * 4 + C::QPB * 8 + WAVES * (kWaveHits * 8 + 4);
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef const __attribute__((address_space(1))) void global_void;
+
+template <int KS, int MT, int WAVES, int NC>
+__global__ void __launch_bounds__(64 * WAVES) k_filter_bf16(QueryArgs a, FilterArgs f, int qtiles, int n_streams,
+                                                             const unsigned* __restrict__ qmax) {
+    using C = FilterCfg<0, KS, MT, WAVES, NC>;
+    using D = DmaCfg<KS, MT, WAVES, NC>;
+    __shared__ __attribute__((aligned(16))) unsigned char tile0[C::TS * C::STRIDE];
+    __shared__ __attribute__((aligned(16))) unsigned char tile1[C::TS * C::STRIDE];
+    __shared__ __attribute__((aligned(16))) float s_H[C::QPB];
+    __shared__ int2 s_home[C::QPB];                    // sorted positions [h0, h1) of each row's approximate answer
+    __shared__ uint2 s_hits[WAVES * kWaveHits];        // {row in the block, sorted position}, per wave
+    __shared__ unsigned s_nhits[WAVES];
+    // the wave index in a scalar register: LDS targets and per-wave offsets stay scalar
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r = lane & 31, h = lane >> 5;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, slot = b >> 3;
+    const int qt = slot % qtiles;
+    const int stream = (slot / qtiles) * 8 + xcd;
+    const int row_base = wave * 32 * MT;  // this wave's first row in the block
+    const int q_base = qt * C::QPB + row_base;
+
+    const float A = __uint_as_float(qmax[0]), Cq = __uint_as_float(qmax[1]), QN = __uint_as_float(qmax[2]);
+    const float kappa = f.kappa;
+
+    bf16x8 fa[MT][KS];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        const int q = q_base + 32 * t + r;
+        const unsigned char* src = static_cast<const unsigned char*>(f.qq) + (int64_t)q * C::ROW + h * C::HALF;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            fa[t][s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(src + s * 16));
+    }
+    auto refresh_H = [&]() {
+        for (int i = threadIdx.x; i < C::QPB; i += C::THREADS) {
+            const int q = qt * C::QPB + i;
+            float H = -kInf;
+            if (q < a.mq && !((a.rerun || a.skip_done) && a.done[q]))
+                H = read_tau(a, q, a.kq[q]) * a.tau_scale - f.qmeta[q].x;
+            s_H[i] = 0.5f * H;
+        }
+    };
+    refresh_H();
+    for (int i = threadIdx.x; i < C::QPB; i += C::THREADS) {
+        const int q = qt * C::QPB + i;
+        int2 hr = make_int2(0, 0);
+        if (q < a.mq)
+            hr = make_int2((int)(a.home[2 * q] * a.leaf_size), (int)min(a.home[2 * q + 1] * a.leaf_size, a.n));
+        s_home[i] = hr;
+    }
+    // rows of this lane that hold a query: bit 16 t + e for accumulator element e of tile t
+    unsigned valid = 0u;
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            valid |= (q_base + 32 * t + 8 * (e >> 2) + 4 * h + (e & 3) < a.mq ? 1u : 0u) << (16 * t + e);
+    unsigned wcount = 0u;  // this wave's candidates in the current tile (wave-uniform)
+
+    const int n_tiles = (int)((a.n + C::TS - 1) / C::TS);
+    const int n_sub = (n_tiles + kFilterSub - 1) / kFilterSub;
+    const int t_lo = (int)(f.range_lo / C::TS), t_hi = (int)((f.range_hi + C::TS - 1) / C::TS);
+    const int n_vt = f.phase == 0 ? n_tiles : f.phase == 1 ? n_sub : f.phase == 2 ? n_tiles - n_sub : t_hi - t_lo;
+    auto tile_of = [&](int v) -> int64_t {
+        return f.phase == 0   ? v
+               : f.phase == 1 ? v * kFilterSub
+               : f.phase == 2 ? v + v / (kFilterSub - 1) + 1
+                              : t_lo + v;
+    };
+    const unsigned char* X = static_cast<const unsigned char*>(f.xq);
+    // the whole tile `tl` into `dst`: instruction j of this wave fills slots [64 (j WAVES + wave), +64).
+    // The per-instruction offsets are recomputed for every tile from a laundered thread index (a
+    // few VALU operations each) instead of being kept live across the loop.
+    auto request = [&](unsigned char* dst, int64_t tl) {
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const unsigned char* base = X + tl * C::TS * C::ROW;
+        const int last = (int)min<int64_t>(a.n - tl * C::TS, C::TS) - 1;  // rows past it repeat it
+#pragma unroll
+        for (int j = 0; j < D::NI; ++j) {
+            if ((j * WAVES + wave) * 64 < D::TOTAL) {
+                const int p = j * 64 * WAVES + tid;
+                const int row = p / D::SLOTS, sl = p - row * D::SLOTS;
+                const int off = min(row, last) * C::ROW + (sl < D::SLOTS - 1 ? sl : 0) * 16;
+                if (p < D::TOTAL)
+                    __builtin_amdgcn_global_load_lds((global_void*)(base + off),
+                                                     (lds_void*)(dst + (j * WAVES + wave) * 1024), 16, 0, 0);
+            }
+        }
+    };
+    // metadata {|x|^2, |e_x|, |x~|} of a tile's columns, loaded one tile ahead
+    auto load_meta = [&](float3* m, int64_t tl) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int64_t p = tl * C::TS + kNT * c + r;
+            float3 v = make_float3(0.f, 0.f, 0.f);
+            if (p < a.n) {
+                const float4 x = f.xmeta[p];
+                v = make_float3(x.x, x.y, x.z);
+            }
+            m[c] = v;
+        }
+    };
+    // G/2 = (|x|^2 - M'(x)) / 2 of a tile's columns (+inf past the end)
+    auto thresholds = [&](float* Gh, const float3* m, int64_t tl) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int64_t p = tl * C::TS + kNT * c + r;
+            const float G = m[c].x - (2.f * (A * m[c].y + Cq * m[c].z) + kappa * (QN + m[c].x));
+            Gh[c] = p < a.n ? 0.5f * G : kInf;
+        }
+    };
+    // the last tile's candidates: home-leaf check, then the query's list
+    auto publish = [&]() {
+        for (int i = threadIdx.x; i < WAVES * kWaveHits; i += C::THREADS) {
+            if ((unsigned)(i % kWaveHits) >= min(s_nhits[i / kWaveHits], (unsigned)kWaveHits)) continue;
+            const uint2 e = s_hits[i];
+            const int2 hr = s_home[e.x];
+            if ((int)e.y >= hr.x && (int)e.y < hr.y) continue;  // already refined by the approximate answer
+            const int q = qt * C::QPB + (int)e.x;
+            const unsigned sl = atomicAdd(f.fcount + q, 1u);
+            if (sl < (unsigned)f.fcap) f.fcand[(int64_t)q * f.fcap + sl] = e.y;
+        }
+    };
+
+    // one tile: the NC column tiles, each MT x KS MFMAs and the epilogue
+    auto compute = [&](const unsigned char* buf, int64_t tl, const float* Ghs) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            f32x16 acc[MT];
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
+            const unsigned char* bsrc = buf + (kNT * c + r) * C::STRIDE + h * C::HALF;
+            constexpr int PF = KS < kBAhead / NC + 1 ? KS : kBAhead / NC + 1;
+            bf16x8 bq[PF + 1];
+#pragma unroll
+            for (int s = 0; s < PF; ++s)
+                bq[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(bsrc + s * 16));
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                if (s + PF < KS)
+                    bq[(s + PF) % (PF + 1)] =
+                        __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(bsrc + (s + PF) * 16));
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[t][s], bq[s % (PF + 1)], acc[t], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_group_barrier(0x100, PF, 0);
+            pin_schedule<PF, MT, 0, KS>();
+            const int64_t pos = tl * C::TS + kNT * c + r;
+            // candidate iff fl(acc + H/2) >= G/2, as in k_filter
+            const float Gh = Ghs[c];
+            float best = -kInf;
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const float4 H4 = *reinterpret_cast<const float4*>(&s_H[row_base + 32 * t + 8 * g + 4 * h]);
+                    best = fmaxf(best, fmaxf(acc[t][4 * g] + H4.x, acc[t][4 * g + 1] + H4.y));
+                    best = fmaxf(best, fmaxf(acc[t][4 * g + 2] + H4.z, acc[t][4 * g + 3] + H4.w));
+                }
+            if (__ballot(best >= Gh)) {
+                unsigned hit = 0u;
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int row = 32 * t + 8 * (e >> 2) + 4 * h + (e & 3);
+                        hit |= (acc[t][e] + s_H[row_base + row] >= Gh ? 1u : 0u) << (16 * t + e);
+                    }
+                hit &= pos < a.n ? valid : 0u;
+                // one hit per lane and round, at slot wcount + (rank among the lanes with a hit)
+                for (;;) {
+                    const unsigned long long act = __ballot(hit != 0u);
+                    if (!act) break;
+                    if (hit) {
+                        const int bit = __ffs(hit) - 1;
+                        hit &= hit - 1u;
+                        const int row = row_base + 32 * (bit >> 4) + 8 * ((bit & 15) >> 2) + 4 * h + (bit & 3);
+                        const unsigned sl =
+                            wcount + __builtin_amdgcn_mbcnt_hi((unsigned)(act >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)act, 0u));
+                        if (sl < (unsigned)kWaveHits) {
+                            s_hits[wave * kWaveHits + sl] = make_uint2((unsigned)row, (unsigned)pos);
+                        } else {
+                            // this wave's list is full: straight to the query's list
+                            const int2 hr = s_home[row];
+                            if (pos < hr.x || pos >= hr.y) {
+                                const int q = qt * C::QPB + row;
+                                const unsigned gs = atomicAdd(f.fcount + q, 1u);
+                                if (gs < (unsigned)f.fcap) f.fcand[(int64_t)q * f.fcap + gs] = (unsigned)pos;
+                            }
+                        }
+                    }
+                    wcount += (unsigned)__popcll(act);
+                }
+            }
+        }
+    };
+
+    float3 mN[NC];  // metadata of the next tile
+    float Gh[NC];   // thresholds of the current tile
+    int v = stream;
+    if (v < n_vt) {
+        load_meta(mN, tile_of(v));
+        request(tile0, tile_of(v));
+    }
+    __syncthreads();
+    int iter = 0;
+    // end of a tile: candidates published, thresholds refreshed now and then
+    auto finish_tile = [&]() {
+        if (lane == 0) s_nhits[wave] = wcount;
+        wcount = 0u;
+        __syncthreads();
+        bool any = false;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) any |= s_nhits[w] != 0u;
+        if (any) publish();
+        if ((++iter & 63) == 0) {
+            __syncthreads();
+            refresh_H();
+        }
+        __syncthreads();
+    };
+    // the tile in `cur`; the next one, if any, is requested into `nxt`
+    auto step = [&](const unsigned char* cur, unsigned char* nxt, int vc) {
+        const int64_t tl = tile_of(vc);
+        thresholds(Gh, mN, tl);
+        const int vn = vc + n_streams;
+        if (vn < n_vt) {
+            load_meta(mN, tile_of(vn));
+            request(nxt, tile_of(vn));
+        }
+        compute(cur, tl, Gh);
+        finish_tile();
+    };
+    for (; v < n_vt; v += 2 * n_streams) {
+        step(tile0, tile1, v);
+        if (v + n_streams >= n_vt) break;
+        step(tile1, tile0, v + n_streams);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Refinement of the filter's candidates: 16 lanes per candidate, FP32 direct
 // differences, early abandoning against the current best-so-far; results in
 // the slack window are emitted like in the iSAX scan.
@@ -472,7 +749,7 @@ __device__ void bestk_insert(unsigned long long* bk, int k, unsigned long long v
 __global__ void __launch_bounds__(256) k_refine_filtered(QueryArgs a, FilterArgs f) {
     extern __shared__ float qrow[];
     const int q = blockIdx.y;
-    if (a.rerun && a.done[q]) return;
+    if ((a.rerun || a.skip_done) && a.done[q]) return;
     const int k = a.kq[q];
     const unsigned cnt = min(f.fcount[q], (unsigned)f.fcap);
     if (cnt == 0) return;
@@ -551,6 +828,49 @@ __global__ void k_filter_tighten(QueryArgs a, FilterArgs f) {
     }
 }
 
+// Serving tables: whether a row lost filter candidates in this step, then the counts cleared.
+__global__ void k_note_overflow(unsigned* __restrict__ fcount, int fcap, int mq, int* __restrict__ ovf) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= mq) return;
+    ovf[q] = fcount[q] > (unsigned)fcap ? 1 : 0;
+    fcount[q] = 0u;
+}
+
+// Per-query state between two batches (a serving table and an admission or
+// final-ordering batch), one block per row.
+__global__ void __launch_bounds__(256) k_copy_rows(QueryArgs sa, FilterArgs sf, QueryArgs da, FilterArgs df,
+                                                   const int2* __restrict__ map, int free_src, int len_pad,
+                                                   int code_bytes) {
+    const int i = blockIdx.x;
+    const int s = map[i].x, d = map[i].y;
+    const int t = threadIdx.x;
+    for (int j = t; j < sa.len; j += 256) const_cast<float*>(da.Q)[(int64_t)d * da.len + j] = sa.Q[(int64_t)s * sa.len + j];
+    const unsigned cnt = min(sa.cand_count[s], (unsigned)sa.cap);
+    for (unsigned j = t; j < min(cnt, (unsigned)da.cap); j += 256) da.cand[(int64_t)d * da.cap + j] = sa.cand[(int64_t)s * sa.cap + j];
+    for (int j = t; j < da.kmax; j += 256)
+        da.bestk[(int64_t)d * da.kmax + j] = j < sa.kmax ? sa.bestk[(int64_t)s * sa.kmax + j] : ~0ull;
+    if (t < ST_N) da.stats[(int64_t)d * ST_N + t] = sa.stats[(int64_t)s * ST_N + t];
+    if (sf.qq && df.qq) {
+        const unsigned char* src = static_cast<const unsigned char*>(sf.qq) + (int64_t)s * len_pad * code_bytes;
+        unsigned char* dst = static_cast<unsigned char*>(df.qq) + (int64_t)d * len_pad * code_bytes;
+        for (int j = t; j < len_pad * code_bytes; j += 256) dst[j] = src[j];
+    }
+    if (t == 0) {
+        const_cast<int32_t*>(da.kq)[d] = sa.kq[s];
+        da.qinfo[d] = sa.qinfo[s];
+        da.tau0[d] = sa.tau0[s];
+        // candidates past the destination's capacity are reported as an overflow by its top-k
+        da.cand_count[d] = sa.cand_count[s];
+        da.home[2 * d] = sa.home[2 * s];
+        da.home[2 * d + 1] = sa.home[2 * s + 1];
+        da.status[d] = sa.status[s];
+        da.done[d] = 0;
+        if (sf.qmeta && df.qmeta) df.qmeta[d] = sf.qmeta[s];
+        if (df.fcount) df.fcount[d] = 0u;
+        if (free_src) sa.done[s] = 1;
+    }
+}
+
 // Large batches: 8 waves x 64 queries per block, one block per CU.  Small
 // batches (<= 64 queries): 2 waves x 32 queries, four blocks per CU; the pass is
 // then bound by reading the reduced-precision copy, not by the matrix cores.
@@ -571,12 +891,23 @@ void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qm
     const int64_t n_sub = (n_tiles + kFilterSub - 1) / kFilterSub;
     if (f.phase == 1) n_tiles = n_sub;
     if (f.phase == 2) n_tiles -= n_sub;
+    if (f.phase == 3) {
+        static_assert(kFilterAlign % C::TS == 0, "a serving chunk starts on a tile of every configuration");
+        n_tiles = (f.range_hi + C::TS - 1) / C::TS - f.range_lo / C::TS;
+    }
     // n_streams * qtiles blocks, n_streams a multiple of 8 (one group per XCD)
     int n_streams = std::max(8, (per_cu * cus / qtiles) / 8 * 8);
     while (n_streams > 8 && n_streams / 2 >= n_tiles) n_streams /= 2;
     const int blocks = n_streams * qtiles;
-    if (f.out_approx) k_filter<KIND, KS, MT, WAVES, NC, true><<<blocks, C::THREADS, 0, s>>>(a, f, qtiles, n_streams, qmax);
-    else k_filter<KIND, KS, MT, WAVES, NC, false><<<blocks, C::THREADS, 0, s>>>(a, f, qtiles, n_streams, qmax);
+    if (f.out_approx) {
+        k_filter<KIND, KS, MT, WAVES, NC, true><<<blocks, C::THREADS, 0, s>>>(a, f, qtiles, n_streams, qmax);
+    } else if constexpr (KIND == 0 && WAVES == 2 && DmaCfg<KS, MT, WAVES, NC>::LDS <= 160 * 1024) {
+        // the 64-query class is bound by streaming the BF16 copy: whole-tile DMA prefetch
+        // (100M x 256: 8.6 against 9.3 ms; the larger classes were 5-7% slower with it)
+        k_filter_bf16<KS, MT, WAVES, NC><<<blocks, C::THREADS, 0, s>>>(a, f, qtiles, n_streams, qmax);
+    } else {
+        k_filter<KIND, KS, MT, WAVES, NC, false><<<blocks, C::THREADS, 0, s>>>(a, f, qtiles, n_streams, qmax);
+    }
 }
 
 // Batch-size classes: a block serves 64, 128, 256 or 512 queries, so a batch
@@ -653,6 +984,19 @@ int filter_rows_bf16(int len, int mq) {
 int filter_queries_per_block(int len) {
     (void)len;
     return 512;
+}
+
+void launch_note_overflow(const QueryArgs& a, const FilterArgs& f, int* ovf, hipStream_t s) {
+    k_note_overflow<<<(a.mq + 255) / 256, 256, 0, s>>>(f.fcount, f.fcap, a.mq, ovf);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_copy_rows(const QueryArgs& sa, const FilterArgs& sf, const QueryArgs& da, const FilterArgs& df,
+                      const int2* map, int n, bool free_src, hipStream_t s) {
+    if (n <= 0) return;
+    ProfScope ps("serve_copy_rows", s);
+    k_copy_rows<<<n, 256, 0, s>>>(sa, sf, da, df, map, free_src ? 1 : 0, filter_len_pad(sa.len), sf.kind == 0 ? 2 : 1);
+    ISAX_HIP(hipGetLastError());
 }
 
 void launch_filter_tighten(const QueryArgs& a, const FilterArgs& f, hipStream_t s) {

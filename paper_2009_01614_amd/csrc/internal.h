@@ -127,6 +127,25 @@ namespace isax {
 // Device scratch one query batch of mq queries (row stride kmax) allocates in `mode`.
 int64_t query_scratch_bytes(const isax_index* idx, int mq, int kmax, int mode);
 
+// Serving table of the step-level request loop (runtime.hip): `slots` query
+// rows resident on the device, the collection swept in `chunks` steps.  Rows
+// are chosen by the caller; every call throws isax::Error on failure.
+struct StepTable;
+StepTable* step_table_create(isax_index* idx, int mode, int slots, int chunks, hipStream_t s);
+void step_table_destroy(StepTable* t);
+int step_table_chunks(const StepTable* t);  // steps per sweep (at most the requested chunks)
+// Queries hq [n][len] (host) with k hk[n] into the free rows rows[0..n).
+void step_table_admit(StepTable* t, const float* hq, const int32_t* hk, const int* rows, int n);
+// One step: chunk `chunk` of the sweep for the occupied rows among [0, hi).
+void step_table_step(StepTable* t, int chunk, int hi);
+// Rows rows[0..n) have swept the whole collection: their answers are ordered
+// and the rows become free.
+void step_table_finish(StepTable* t, const int* rows, int n);
+// Waits for the queued work; ovf (host, hi) <- rows that lost filter candidates
+// in the last step; ids / dists (host, [n][kout]) and status (0, else the row
+// must be answered alone) of the last finish.
+void step_table_sync(StepTable* t, int* ovf, int kout, int64_t* ids, float* dists, int* status);
+
 }  // namespace isax
 
 // ---------------------------------------------------------------------------------------------

@@ -36,6 +36,8 @@ struct QueryArgs {
     float lb_scale;   // 1 - 2^-16: slack on every lower bound
     int flags;        // ISAX_QF_*
     int rerun;        // 1: frozen best-so-far, no best-k insertion, skip finished queries
+    int skip_done;    // 1: rows whose done flag is set take no part in the filter and its refinement
+                      //    (the free slots of a serving table)
     float* paa;       // [mq][w]
     uint8_t* sym;     // [mq][ws]
     uint64_t* qkey;   // [mq]
@@ -122,14 +124,25 @@ struct FilterArgs {
     int fcap;
     float* out_approx;        // optional [mq][n] (inspection)
     float* out_margin;        // optional [mq][n]
-    int phase;                // 0: every tile; 1: tiles t % kFilterSub == 0; 2: the other tiles
+    int phase;                // 0: every tile; 1: tiles t % kFilterSub == 0; 2: the other tiles;
+                              // 3: the series at sorted positions [range_lo, range_hi)
+    int64_t range_lo, range_hi;  // phase 3; range_lo a multiple of kFilterAlign
 };
+constexpr int kFilterAlign = 128;  // the largest tile of any filter configuration
 int filter_len_pad(int len);              // rows of the reduced-precision copies are padded to this
 int filter_queries_per_block(int len);    // query codes are padded to a multiple of this
 int filter_rows_bf16(int len, int mq);    // query rows the BF16 filter computes for mq queries
 void launch_quantise_queries(const QueryArgs& a, const FilterArgs& f, int mq_pad, unsigned* qmax, hipStream_t s);
 void launch_filter(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax, hipStream_t s);
 void launch_refine_filtered(const QueryArgs& a, const FilterArgs& f, hipStream_t s);
+// Serving tables: ovf[q] = fcount[q] > fcap, then fcount[q] = 0, for q < a.mq.
+void launch_note_overflow(const QueryArgs& a, const FilterArgs& f, int* ovf, hipStream_t s);
+// Per-query state of rows map[i].x of (sa, sf) into rows map[i].y of (da, df): query row, k,
+// norms, bounds, best-k list, candidate list, approximate-answer range, statistics, status,
+// the filter's query codes and factors.  done of the destination row is set to 0 and, when
+// free_src, that of the source row to 1.
+void launch_copy_rows(const QueryArgs& sa, const FilterArgs& sf, const QueryArgs& da, const FilterArgs& df,
+                      const int2* map, int n, bool free_src, hipStream_t s);
 void launch_filter_tighten(const QueryArgs& a, const FilterArgs& f, hipStream_t s);
 
 }  // namespace isax

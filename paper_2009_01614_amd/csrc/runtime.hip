@@ -1294,6 +1294,211 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
 }
 }  // namespace
 
+// =============================================================================================
+// Serving table of the step-level request loop (serve.cpp).  `slots` query rows
+// stay resident (a Batch with the filter's per-row state); a step runs the
+// filter over one chunk of the collection for every occupied row and refines
+// its candidates, so a row that joined at any chunk has covered the whole
+// collection after `chunks` steps (the sweep wraps around).  Rows join through
+// an admission batch (approximate answer and query codes, as for a batch of
+// their own) whose state is copied into the table; finished rows are copied
+// into an ordering batch for the top-k.  Free rows carry done = 1 and take no
+// part (skip_done).  The filter's bound on the query factors is a running
+// maximum over every row admitted so far, an upper bound of each row's own.
+namespace isax {
+constexpr int kServeCand = 16384;   // candidate slots per row (the query's list)
+constexpr int kServeFcap = 32768;   // filter candidates per row and step
+
+struct StepTable {
+    isax_index* idx = nullptr;
+    int mode = ISAX_MODE_BF16, slots = 0, chunks = 0, kmax = ISAX_MAX_K;
+    int64_t chunk_len = 0;          // series per chunk (a multiple of kFilterAlign)
+    hipStream_t s = nullptr;
+    Batch tab, adm, fin;            // the table, the admission batch, the ordering batch
+    FilterScratch ftab, fadm;
+    DevBuf dev;                     // device side of the staging below, the overflow flags
+    DevBuf own;                     // query rows and k of the table and the ordering batch, answers
+    float* dq = nullptr;            // [slots][len] admitted queries
+    int32_t* dk = nullptr;          // [slots] their k
+    int2* dmap = nullptr;           // [slots] row copies
+    int* dovf = nullptr;            // [slots]
+    // pinned host staging
+    float* hq = nullptr;
+    int32_t* hk = nullptr;
+    int2* hmap = nullptr;           // admission copies
+    int2* hmap2 = nullptr;          // finishing copies
+    int* hovf = nullptr;
+    int* hstatus = nullptr;
+    int64_t* hids = nullptr;
+    float* hdists = nullptr;
+    int n_fin = 0, hi_last = 0;
+    ~StepTable() {
+        (void)hipHostFree(hq);
+        (void)hipHostFree(hk);
+        (void)hipHostFree(hmap);
+        (void)hipHostFree(hmap2);
+        (void)hipHostFree(hovf);
+        (void)hipHostFree(hstatus);
+        (void)hipHostFree(hids);
+        (void)hipHostFree(hdists);
+    }
+};
+
+namespace {
+template <class T>
+T* pinned(size_t count) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, std::max<size_t>(count, 1) * sizeof(T), 0) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{ISAX_ENOMEM, "pinned host allocation of the serving table failed"};
+    }
+    return static_cast<T*>(p);
+}
+
+// A view of rows [0, m) of a batch's arrays.
+QueryArgs rows_view(const QueryArgs& a, int m) {
+    QueryArgs v = a;
+    v.mq = m;
+    return v;
+}
+}  // namespace
+
+StepTable* step_table_create(isax_index* idx, int mode, int slots, int chunks, hipStream_t s) {
+    ISAX_REQUIRE(mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8, "step-level serving runs the BF16 or FP8 filter");
+    ISAX_REQUIRE(mode != ISAX_MODE_BF16 || idx->x_bf16, "index was built without the BF16 copy");
+    ISAX_REQUIRE(mode != ISAX_MODE_FP8 || idx->x_fp8, "index was built without the FP8 copy");
+    ISAX_REQUIRE(slots >= 1 && slots <= 4096 && chunks >= 1 && chunks <= 1024, "bad serving table size");
+    std::unique_ptr<StepTable> t(new StepTable);
+    t->idx = idx;
+    t->mode = mode;
+    t->slots = slots;
+    t->s = s;
+    t->chunk_len = std::max<int64_t>(kFilterAlign, (idx->n + chunks - 1) / chunks / kFilterAlign * kFilterAlign);
+    t->chunks = (int)((idx->n + t->chunk_len - 1) / t->chunk_len);
+    // per-row k is set by each admission; every table row starts free (done = 1)
+    std::vector<int32_t> ones(slots, 1);
+    Arena ar;
+    ar.add(&t->dq, (size_t)slots * idx->len);
+    ar.add(&t->dk, slots);
+    ar.add(&t->dmap, slots);
+    ar.add(&t->dovf, slots);
+    t->dev = ar.commit(s);
+    ISAX_HIP(hipMemcpyAsync(t->dk, ones.data(), slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    setup_batch(t->tab, idx, t->dq, slots, t->dk, t->kmax, kServeCand, 0, nullptr, nullptr, s);
+    setup_batch(t->adm, idx, t->dq, slots, t->dk, t->kmax, kServeCand, 0, nullptr, nullptr, s);
+    setup_batch(t->fin, idx, t->dq, slots, t->dk, t->kmax, kServeCand, 0, nullptr, nullptr, s);
+    // the table and the ordering batch hold their own query rows and k (copied with the state)
+    {
+        t->own = DevBuf((size_t)slots * (idx->len * 4 + 4) * 2 + (size_t)slots * t->kmax * 12, s);
+        float* tq = t->own.as<float>();
+        int32_t* tk = reinterpret_cast<int32_t*>(tq + (size_t)slots * idx->len);
+        float* fq = reinterpret_cast<float*>(tk + slots);
+        int32_t* fk = reinterpret_cast<int32_t*>(fq + (size_t)slots * idx->len);
+        int64_t* oid = reinterpret_cast<int64_t*>(fk + slots);
+        float* od = reinterpret_cast<float*>(oid + (size_t)slots * t->kmax);
+        t->tab.a.Q = tq;
+        t->tab.a.kq = tk;
+        t->fin.a.Q = fq;
+        t->fin.a.kq = fk;
+        t->fin.a.out_ids = oid;
+        t->fin.a.out_dists = od;
+        ISAX_HIP(hipMemcpyAsync(tk, ones.data(), slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    }
+    t->tab.a.skip_done = 1;
+    setup_filter(t->ftab, idx, t->tab.a, mode, kServeFcap, s);
+    setup_filter(t->fadm, idx, t->adm.a, mode, 1, s);
+    // every table row free: done = 1
+    ISAX_HIP(hipMemcpyAsync(t->tab.a.done, ones.data(), slots * sizeof(int), hipMemcpyHostToDevice, s));
+    t->hq = pinned<float>((size_t)slots * idx->len);
+    t->hk = pinned<int32_t>(slots);
+    t->hmap = pinned<int2>(slots);
+    t->hmap2 = pinned<int2>(slots);
+    t->hovf = pinned<int>(slots);
+    t->hstatus = pinned<int>(slots);
+    t->hids = pinned<int64_t>((size_t)slots * t->kmax);
+    t->hdists = pinned<float>((size_t)slots * t->kmax);
+    ISAX_HIP(hipStreamSynchronize(s));
+    return t.release();
+}
+
+void step_table_destroy(StepTable* t) {
+    if (!t) return;
+    (void)hipStreamSynchronize(t->s);
+    delete t;
+}
+
+int step_table_chunks(const StepTable* t) { return t->chunks; }
+
+// Queries hq [n][len] with k hk[n] into table rows rows[0..n): approximate
+// answer and query codes in the admission batch, then the state into the rows.
+void step_table_admit(StepTable* t, const float* hq, const int32_t* hk, const int* rows, int n) {
+    if (n <= 0) return;
+    ISAX_REQUIRE(n <= t->slots, "more admissions than table rows");
+    const int len = t->idx->len;
+    std::memcpy(t->hq, hq, (size_t)n * len * sizeof(float));
+    std::memcpy(t->hk, hk, (size_t)n * sizeof(int32_t));
+    for (int i = 0; i < n; ++i) t->hmap[i] = make_int2(i, rows[i]);
+    ISAX_HIP(hipMemcpyAsync(t->dq, t->hq, (size_t)n * len * sizeof(float), hipMemcpyHostToDevice, t->s));
+    ISAX_HIP(hipMemcpyAsync(t->dk, t->hk, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, t->s));
+    ISAX_HIP(hipMemcpyAsync(t->dmap, t->hmap, (size_t)n * sizeof(int2), hipMemcpyHostToDevice, t->s));
+    const QueryArgs a = rows_view(t->adm.a, n);
+    launch_qprep(a, t->s);
+    launch_homeleaf(a, t->s);
+    launch_quantise_queries(a, t->fadm.f, t->fadm.mq_pad, t->ftab.qmax, t->s);
+    launch_copy_rows(a, t->fadm.f, t->tab.a, t->ftab.f, t->dmap, n, false, t->s);
+}
+
+// One step: the filter over chunk `chunk` for table rows [0, hi), then the
+// refinement of its candidates; the overflow flags of the step.
+void step_table_step(StepTable* t, int chunk, int hi) {
+    t->hi_last = hi;
+    if (hi <= 0) return;
+    const QueryArgs a = rows_view(t->tab.a, hi);
+    FilterArgs f = t->ftab.f;
+    f.phase = 3;
+    f.range_lo = (int64_t)chunk * t->chunk_len;
+    f.range_hi = std::min<int64_t>(t->idx->n, f.range_lo + t->chunk_len);
+    launch_filter(a, f, t->ftab.qmax, t->s);
+    launch_refine_filtered(a, f, t->s);
+    launch_note_overflow(a, f, t->dovf, t->s);
+    ISAX_HIP(hipMemcpyAsync(t->hovf, t->dovf, (size_t)hi * sizeof(int), hipMemcpyDeviceToHost, t->s));
+}
+
+// Rows rows[0..n) have covered the collection: their state into the ordering
+// batch (the table rows become free), the top-k, the answers to the host.
+void step_table_finish(StepTable* t, const int* rows, int n) {
+    t->n_fin = n;
+    if (n <= 0) return;
+    ISAX_REQUIRE(n <= t->slots, "more finished rows than table rows");
+    for (int i = 0; i < n; ++i) t->hmap2[i] = make_int2(rows[i], i);
+    // the admission of this step may still read the front of the device map: the back holds
+    // this one (admitted rows were free and finishing rows are occupied, so both fit)
+    int2* dm = t->dmap + (t->slots - n);
+    ISAX_HIP(hipMemcpyAsync(dm, t->hmap2, (size_t)n * sizeof(int2), hipMemcpyHostToDevice, t->s));
+    const QueryArgs fa = rows_view(t->fin.a, n);
+    FilterArgs none{};
+    launch_copy_rows(t->tab.a, t->ftab.f, fa, none, dm, n, true, t->s);
+    launch_topk(fa, t->s);
+    ISAX_HIP(hipMemcpyAsync(t->hstatus, fa.status, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, t->s));
+    ISAX_HIP(hipMemcpyAsync(t->hids, fa.out_ids, (size_t)n * t->kmax * sizeof(int64_t), hipMemcpyDeviceToHost, t->s));
+    ISAX_HIP(hipMemcpyAsync(t->hdists, fa.out_dists, (size_t)n * t->kmax * sizeof(float), hipMemcpyDeviceToHost,
+                            t->s));
+}
+
+// Waits for the queued work.  ovf (host, hi of the last step) receives the
+// step's overflow flags; ids / dists (host, [n_fin][kout]) and status the
+// answers of the finished rows (status != 0: the row must be answered alone).
+void step_table_sync(StepTable* t, int* ovf, int kout, int64_t* ids, float* dists, int* status) {
+    ISAX_HIP(hipStreamSynchronize(t->s));
+    std::memcpy(ovf, t->hovf, (size_t)t->hi_last * sizeof(int));
+    for (int i = 0; i < t->n_fin; ++i) {
+        status[i] = t->hstatus[i];
+        std::memcpy(ids + (size_t)i * kout, t->hids + (size_t)i * t->kmax, (size_t)kout * sizeof(int64_t));
+        std::memcpy(dists + (size_t)i * kout, t->hdists + (size_t)i * t->kmax, (size_t)kout * sizeof(float));
+    }
+}
+}  // namespace isax
+
 namespace {
 // Upper bound of the device scratch one batch of mq queries takes through
 // DevBuf (every block rounded up to 256 bytes) before its candidate lists grow

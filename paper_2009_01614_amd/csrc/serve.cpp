@@ -1,174 +1,205 @@
-// Serving loop: continuous batching of exact k-NN requests over resident indexes.
+// Request loop over resident indexes: the C ABI and the device runners of the
+// scheduling core (serve_sched.h, which describes both admission policies).
 //
-// The paper motivates fast exact search with interactive exploration of large
-// collections (Sec. I; Sec. V); this loop keeps the indexes resident and
-// serves requests as they arrive.  Each of `streams` worker threads owns one
-// HIP stream and pinned staging buffers.  A free worker takes the oldest
-// waiting request and every other waiting request of the same collection (up
-// to max_batch), provided the batch's device scratch fits in what is left of
-// the memory budget, and runs it with isax_query_ex on its own stream; so
-// requests that arrive while other batches run are admitted as soon as a
-// worker and memory are free, and batches on different streams overlap on the
-// device.  Every request's answer is exact and its distances come from one
-// fixed-order computation per (query, series) pair, so it is the same alone
-// and in any mix.
+// Batch level: each worker thread owns a HIP stream and pinned staging, and
+// answers a batch with isax_query_ex on its stream.  Step level (BF16 / FP8
+// modes): one engine thread per collection owns a stream and a serving table
+// (runtime.hip), which keeps the admitted queries resident and sweeps the
+// collection chunk by chunk.  Every answer is exact, and its distances come
+// from one fixed-order computation per (query, series) pair, so a request's
+// result is the same alone and in any mix.
 #include <algorithm>
-#include <chrono>
-#include <condition_variable>
 #include <cstring>
-#include <deque>
-#include <mutex>
+#include <memory>
 #include <thread>
 
 #include "internal.h"
+#include "serve_sched.h"
+
+using isax::serve::Core;
+using isax::serve::Failure;
 
 namespace {
 
-struct Request {
-    uint64_t tag;
-    int32_t coll;
-    int32_t k;
-    std::vector<float> q;
-    double t_submit;
+// Batch level: one stream, pinned host staging and device buffers per worker.
+struct HipBatchRunner : isax::serve::BatchRunner {
+    const std::vector<isax_index*>& colls;
+    int mode;
+    int B, max_len;
+    hipStream_t stream = nullptr;
+    float *hq = nullptr, *dq = nullptr, *hd = nullptr, *dd = nullptr;
+    int64_t *hi = nullptr, *di = nullptr;
+    int32_t *hk = nullptr, *dk = nullptr;
+    bool ok = false;
+    std::string why;
+    HipBatchRunner(const std::vector<isax_index*>& c, int mode_, int B_, int max_len_)
+        : colls(c), mode(mode_), B(B_), max_len(max_len_) {
+        (void)hipSetDevice(colls[0]->device);
+        if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            stream = nullptr;
+            why = "server stream creation failed";
+            return;
+        }
+        ok = hipHostMalloc((void**)&hq, (size_t)B * max_len * 4, 0) == hipSuccess &&
+             hipHostMalloc((void**)&hd, (size_t)B * ISAX_MAX_K * 4, 0) == hipSuccess &&
+             hipHostMalloc((void**)&hi, (size_t)B * ISAX_MAX_K * 8, 0) == hipSuccess &&
+             hipHostMalloc((void**)&hk, (size_t)B * 4, 0) == hipSuccess &&
+             hipMalloc((void**)&dq, (size_t)B * max_len * 4) == hipSuccess &&
+             hipMalloc((void**)&dd, (size_t)B * ISAX_MAX_K * 4) == hipSuccess &&
+             hipMalloc((void**)&di, (size_t)B * ISAX_MAX_K * 8) == hipSuccess &&
+             hipMalloc((void**)&dk, (size_t)B * 4) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            why = "server staging allocation failed";
+        }
+    }
+    ~HipBatchRunner() override {
+        (void)hipFree(dq);
+        (void)hipFree(dd);
+        (void)hipFree(di);
+        (void)hipFree(dk);
+        (void)hipHostFree(hq);
+        (void)hipHostFree(hd);
+        (void)hipHostFree(hi);
+        (void)hipHostFree(hk);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+    int64_t scratch_bytes(int coll, int m, int kmax) override {
+        return isax::query_scratch_bytes(colls[coll], m, kmax, mode);
+    }
+    int run(int coll, const float* q, const int32_t* k, int m, int kmax, int64_t* ids, float* dists,
+            std::string& err) override {
+        // without its own stream or staging the worker answers with an error instead of
+        // running on the null stream
+        if (!ok) {
+            err = why;
+            return ISAX_ENOMEM;
+        }
+        isax_index* idx = colls[coll];
+        const int len = idx->len;
+        std::memcpy(hq, q, (size_t)m * len * 4);
+        std::memcpy(hk, k, (size_t)m * 4);
+        (void)hipMemcpyAsync(dq, hq, (size_t)m * len * 4, hipMemcpyHostToDevice, stream);
+        (void)hipMemcpyAsync(dk, hk, (size_t)m * 4, hipMemcpyHostToDevice, stream);
+        isax_query_options qo{};
+        qo.mode = mode;
+        qo.k_per_query = dk;
+        qo.stream = stream;
+        int rc = isax_query_ex(idx, dq, m, kmax, di, dd, &qo);
+        if (rc != ISAX_OK) {
+            err = isax_last_error();
+            return rc;
+        }
+        (void)hipMemcpyAsync(hi, di, (size_t)m * kmax * 8, hipMemcpyDeviceToHost, stream);
+        (void)hipMemcpyAsync(hd, dd, (size_t)m * kmax * 4, hipMemcpyDeviceToHost, stream);
+        const hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            err = hipGetErrorString(e);
+            return ISAX_EDEVICE;
+        }
+        std::memcpy(ids, hi, (size_t)m * kmax * 8);
+        std::memcpy(dists, hd, (size_t)m * kmax * 4);
+        return ISAX_OK;
+    }
 };
 
-double now() { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); }
+// Step level: the serving table of one collection on the engine's stream.
+struct HipStepRunner : isax::serve::StepRunner {
+    isax_index* idx;
+    int mode;
+    hipStream_t stream = nullptr;
+    isax::StepTable* table = nullptr;
+    float *dq = nullptr, *dd = nullptr;
+    int64_t* di = nullptr;
+    HipStepRunner(isax_index* idx_, int mode_, int slots, int chunks) : idx(idx_), mode(mode_) {
+        (void)hipSetDevice(idx->device);
+        if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            throw isax::Error{ISAX_EDEVICE, "server stream creation failed"};
+        }
+        try {
+            table = isax::step_table_create(idx, mode, slots, chunks, stream);
+            if (hipMalloc((void**)&dq, (size_t)idx->len * 4) != hipSuccess ||
+                hipMalloc((void**)&dd, (size_t)ISAX_MAX_K * 4) != hipSuccess ||
+                hipMalloc((void**)&di, (size_t)ISAX_MAX_K * 8) != hipSuccess) {
+                (void)hipGetLastError();
+                throw isax::Error{ISAX_ENOMEM, "server staging allocation failed"};
+            }
+        } catch (...) {
+            release();
+            throw;
+        }
+        slots_ = slots;
+        chunks_ = isax::step_table_chunks(table);
+    }
+    void release() {
+        isax::step_table_destroy(table);
+        table = nullptr;
+        (void)hipFree(dq);
+        (void)hipFree(dd);
+        (void)hipFree(di);
+        if (stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+    }
+    ~HipStepRunner() override { release(); }
+    int slots_ = 0, chunks_ = 0;
+    int slots() const override { return slots_; }
+    int chunks() const override { return chunks_; }
+    int len() const override { return idx->len; }
+    template <class F>
+    void guard(F&& f) {
+        try {
+            f();
+        } catch (const isax::Error& e) {
+            throw Failure{e.code, e.msg};
+        }
+    }
+    void admit(const float* q, const int32_t* k, const int* rows, int n) override {
+        guard([&] { isax::step_table_admit(table, q, k, rows, n); });
+    }
+    void step(int chunk, int hi) override {
+        guard([&] { isax::step_table_step(table, chunk, hi); });
+    }
+    void finish(const int* rows, int n) override {
+        guard([&] { isax::step_table_finish(table, rows, n); });
+    }
+    void sync(int* ovf, int kout, int64_t* ids, float* dists, int* status) override {
+        guard([&] { isax::step_table_sync(table, ovf, kout, ids, dists, status); });
+    }
+    int run_alone(const float* q, int k, int64_t* ids, float* dists, std::string& err) override {
+        isax_query_options qo{};
+        qo.mode = mode;
+        qo.stream = stream;
+        if (hipMemcpyAsync(dq, q, (size_t)idx->len * 4, hipMemcpyHostToDevice, stream) != hipSuccess) {
+            err = "query upload failed";
+            return ISAX_EDEVICE;
+        }
+        int rc = isax_query_ex(idx, dq, 1, k, di, dd, &qo);
+        if (rc != ISAX_OK) {
+            err = isax_last_error();
+            return rc;
+        }
+        if (hipMemcpyAsync(ids, di, (size_t)k * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipMemcpyAsync(dists, dd, (size_t)k * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess) {
+            err = "answer download failed";
+            return ISAX_EDEVICE;
+        }
+        return ISAX_OK;
+    }
+};
 
 }  // namespace
 
 struct isax_server {
     std::vector<isax_index*> colls;
     isax_server_options opt{};
-    int max_len = 0;
-    std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::deque<Request> queue;
-    std::deque<isax_result> results;
-    int64_t pending = 0;
-    int64_t mem_in_use = 0;
-    bool stop = false;
-    std::vector<std::thread> workers;
-    void worker_main(int wid);
+    Core core;
+    std::vector<std::unique_ptr<isax::serve::BatchRunner>> batch_runners;
+    std::vector<std::unique_ptr<isax::serve::StepRunner>> step_runners;
+    std::vector<std::thread> threads;
 };
-
-void isax_server::worker_main(int wid) {
-    (void)wid;
-    int dev = colls[0]->device;
-    (void)hipSetDevice(dev);
-    hipStream_t stream = nullptr;
-    (void)hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
-    const int B = opt.max_batch;
-    float *hq = nullptr, *dq = nullptr, *hd = nullptr, *dd = nullptr;
-    int64_t *hi = nullptr, *di = nullptr;
-    int32_t *hk = nullptr, *dk = nullptr;
-    bool ok = hipHostMalloc((void**)&hq, (size_t)B * max_len * 4, 0) == hipSuccess &&
-              hipHostMalloc((void**)&hd, (size_t)B * ISAX_MAX_K * 4, 0) == hipSuccess &&
-              hipHostMalloc((void**)&hi, (size_t)B * ISAX_MAX_K * 8, 0) == hipSuccess &&
-              hipHostMalloc((void**)&hk, (size_t)B * 4, 0) == hipSuccess &&
-              hipMalloc((void**)&dq, (size_t)B * max_len * 4) == hipSuccess &&
-              hipMalloc((void**)&dd, (size_t)B * ISAX_MAX_K * 4) == hipSuccess &&
-              hipMalloc((void**)&di, (size_t)B * ISAX_MAX_K * 8) == hipSuccess &&
-              hipMalloc((void**)&dk, (size_t)B * 4) == hipSuccess;
-    while (true) {
-        std::vector<Request> batch;
-        int64_t mem = 0;
-        {
-            std::unique_lock<std::mutex> lk(mu);
-            while (true) {
-                if (stop && queue.empty()) break;
-                if (!queue.empty()) {
-                    // oldest request's collection; admit while the scratch estimate fits the budget
-                    const int coll = queue.front().coll;
-                    const isax_index* idx = colls[coll];
-                    int kmax = 0;
-                    std::vector<size_t> take;
-                    for (size_t i = 0; i < queue.size() && (int)take.size() < B; ++i) {
-                        if (queue[i].coll != coll) continue;
-                        const int km = std::max(kmax, queue[i].k);
-                        const int64_t need = isax::query_scratch_bytes(idx, (int)take.size() + 1, km, opt.mode);
-                        if (mem_in_use + need > opt.memory_budget && !take.empty()) break;
-                        if (mem_in_use + need > opt.memory_budget && mem_in_use > 0) break;
-                        take.push_back(i);
-                        kmax = km;
-                        mem = need;
-                    }
-                    if (!take.empty()) {
-                        for (size_t j = take.size(); j-- > 0;) {
-                            batch.push_back(std::move(queue[take[j]]));
-                            queue.erase(queue.begin() + (std::ptrdiff_t)take[j]);
-                        }
-                        std::reverse(batch.begin(), batch.end());
-                        mem_in_use += mem;
-                        break;
-                    }
-                }
-                cv_work.wait(lk);
-            }
-        }
-        if (batch.empty()) break;
-        const double t_start = now();
-        const int m = (int)batch.size();
-        isax_index* idx = colls[batch[0].coll];
-        const int len = idx->len;
-        int kmax = 0;
-        for (int i = 0; i < m; ++i) {
-            std::memcpy(hq + (size_t)i * len, batch[i].q.data(), (size_t)len * 4);
-            hk[i] = batch[i].k;
-            kmax = std::max(kmax, batch[i].k);
-        }
-        int rc = ok ? ISAX_OK : ISAX_ENOMEM;
-        std::string err = ok ? "" : "server staging allocation failed";
-        if (ok) {
-            (void)hipMemcpyAsync(dq, hq, (size_t)m * len * 4, hipMemcpyHostToDevice, stream);
-            (void)hipMemcpyAsync(dk, hk, (size_t)m * 4, hipMemcpyHostToDevice, stream);
-            isax_query_options qo{};
-            qo.mode = opt.mode;
-            qo.k_per_query = dk;
-            qo.stream = stream;
-            rc = isax_query_ex(idx, dq, m, kmax, di, dd, &qo);
-            if (rc == ISAX_OK) {
-                (void)hipMemcpyAsync(hi, di, (size_t)m * kmax * 8, hipMemcpyDeviceToHost, stream);
-                (void)hipMemcpyAsync(hd, dd, (size_t)m * kmax * 4, hipMemcpyDeviceToHost, stream);
-                if (hipStreamSynchronize(stream) != hipSuccess) rc = ISAX_EDEVICE;
-            } else {
-                err = isax_last_error();
-            }
-        }
-        const double t_done = now();
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            for (int i = 0; i < m; ++i) {
-                isax_result r;
-                std::memset(&r, 0, sizeof(r));
-                r.tag = batch[i].tag;
-                r.status = rc;
-                r.k = batch[i].k;
-                r.collection = batch[i].coll;
-                r.batch_size = m;
-                r.t_submit = batch[i].t_submit;
-                r.t_start = t_start;
-                r.t_done = t_done;
-                if (rc == ISAX_OK) {
-                    std::memcpy(r.ids, hi + (size_t)i * kmax, (size_t)r.k * 8);
-                    std::memcpy(r.dists, hd + (size_t)i * kmax, (size_t)r.k * 4);
-                }
-                results.push_back(r);
-            }
-            mem_in_use -= mem;
-        }
-        cv_done.notify_all();
-        cv_work.notify_all();
-    }
-    (void)hipFree(dq);
-    (void)hipFree(dd);
-    (void)hipFree(di);
-    (void)hipFree(dk);
-    (void)hipHostFree(hq);
-    (void)hipHostFree(hd);
-    (void)hipHostFree(hi);
-    (void)hipHostFree(hk);
-    (void)hipStreamDestroy(stream);
-}
 
 extern "C" {
 
@@ -180,33 +211,60 @@ isax_server* isax_server_create(isax_index* const* collections, int32_t n_collec
     }
     isax_server_options opt{};
     if (o) opt = *o;
-    if (opt.max_batch == 0) opt.max_batch = 256;
+    const bool filter_mode = opt.mode == ISAX_MODE_BF16 || opt.mode == ISAX_MODE_FP8;
+    const bool step = filter_mode && !(opt.flags & ISAX_SERVE_BATCHES);
+    if (opt.max_batch == 0) opt.max_batch = step ? 512 : 256;
     if (opt.streams == 0) opt.streams = 4;
     if (opt.memory_budget == 0) opt.memory_budget = int64_t(4) << 30;
+    if (opt.chunks == 0) opt.chunks = 16;
     if (opt.max_batch < 1 || opt.max_batch > 4096 || opt.streams < 1 || opt.streams > 16 || opt.memory_budget < 0 ||
-        opt.mode < ISAX_MODE_INDEX || opt.mode > ISAX_MODE_HYBRID || opt.reserved != 0) {
-        isax::set_error(ISAX_EINVAL, "bad server options (max_batch 1..4096, streams 1..16, mode, reserved = 0)");
+        opt.mode < ISAX_MODE_INDEX || opt.mode > ISAX_MODE_HYBRID || (opt.flags & ~ISAX_SERVE_BATCHES) != 0 ||
+        opt.chunks < 1 || opt.chunks > 1024 || opt.reserved != 0) {
+        isax::set_error(ISAX_EINVAL, "bad server options (max_batch 1..4096, streams 1..16, mode, flags, "
+                                     "chunks 1..1024, reserved = 0)");
         return nullptr;
     }
-    auto* s = new isax_server();
+    std::unique_ptr<isax_server> s(new isax_server());
     s->opt = opt;
+    int max_len = 0;
     for (int i = 0; i < n_collections; ++i) {
         isax_index* idx = collections[i];
         if (!idx || idx->device != collections[0]->device) {
             isax::set_error(ISAX_EINVAL, "collections must be non-NULL indexes on one device");
-            delete s;
             return nullptr;
         }
-        if (((opt.mode == ISAX_MODE_BF16 || opt.mode == ISAX_MODE_HYBRID) && !idx->x_bf16) || (opt.mode == ISAX_MODE_FP8 && !idx->x_fp8)) {
+        if (((opt.mode == ISAX_MODE_BF16 || opt.mode == ISAX_MODE_HYBRID) && !idx->x_bf16) ||
+            (opt.mode == ISAX_MODE_FP8 && !idx->x_fp8)) {
             isax::set_error(ISAX_EINVAL, "a collection lacks the reduced-precision copy the mode needs");
-            delete s;
             return nullptr;
         }
         s->colls.push_back(idx);
-        s->max_len = std::max(s->max_len, idx->len);
+        max_len = std::max(max_len, idx->len);
     }
-    for (int w = 0; w < opt.streams; ++w) s->workers.emplace_back(&isax_server::worker_main, s, w);
-    return s;
+    isax_server* raw = s.get();
+    if (step) {
+        try {
+            for (int c = 0; c < n_collections; ++c)
+                s->step_runners.emplace_back(new HipStepRunner(s->colls[c], opt.mode, opt.max_batch, opt.chunks));
+        } catch (const isax::Error& e) {
+            isax::set_error(e.code, e.msg);
+            return nullptr;
+        } catch (const std::bad_alloc&) {
+            isax::set_error(ISAX_ENOMEM, "host allocation failed");
+            return nullptr;
+        }
+        for (int c = 0; c < n_collections; ++c)
+            s->threads.emplace_back([raw, c] { isax::serve::step_engine(raw->core, c, *raw->step_runners[c]); });
+    } else {
+        for (int w = 0; w < opt.streams; ++w)
+            s->batch_runners.emplace_back(new HipBatchRunner(s->colls, opt.mode, opt.max_batch, max_len));
+        for (int w = 0; w < opt.streams; ++w)
+            s->threads.emplace_back([raw, w] {
+                isax::serve::batch_worker(raw->core, *raw->batch_runners[w], raw->opt.max_batch,
+                                          raw->opt.memory_budget);
+            });
+    }
+    return s.release();
 }
 
 int isax_server_submit(isax_server* s, int32_t collection, const float* query, int32_t k, uint64_t tag) {
@@ -225,48 +283,49 @@ int isax_server_submit(isax_server* s, int32_t collection, const float* query, i
             isax::set_error(ISAX_EINVAL, "query holds a non-finite value");
             return ISAX_EINVAL;
         }
-    Request r{tag, collection, k, std::vector<float>(query, query + idx->len), now()};
+    isax::serve::Request r{tag, collection, k, std::vector<float>(query, query + idx->len), isax::serve::now()};
     {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (s->stop) {
+        std::lock_guard<std::mutex> lk(s->core.mu);
+        if (s->core.stop) {
             isax::set_error(ISAX_EINVAL, "server is shutting down");
             return ISAX_EINVAL;
         }
-        s->queue.push_back(std::move(r));
-        ++s->pending;
+        s->core.queue.push_back(std::move(r));
+        ++s->core.pending;
     }
-    s->cv_work.notify_one();
+    // every waiter: step engines serve one collection each
+    s->core.cv_work.notify_all();
     return ISAX_OK;
 }
 
 int isax_server_poll(isax_server* s, isax_result* out, int32_t max_results, int32_t timeout_ms) {
     if (!s || !out || max_results < 0) return ISAX_EINVAL;
-    std::unique_lock<std::mutex> lk(s->mu);
-    if (s->results.empty() && timeout_ms > 0)
-        s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), [&] { return !s->results.empty(); });
+    std::unique_lock<std::mutex> lk(s->core.mu);
+    if (s->core.results.empty() && timeout_ms > 0)
+        s->core.cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), [&] { return !s->core.results.empty(); });
     int n = 0;
-    while (n < max_results && !s->results.empty()) {
-        out[n++] = s->results.front();
-        s->results.pop_front();
-        --s->pending;
+    while (n < max_results && !s->core.results.empty()) {
+        out[n++] = s->core.results.front();
+        s->core.results.pop_front();
+        --s->core.pending;
     }
     return n;
 }
 
 int64_t isax_server_pending(isax_server* s) {
     if (!s) return 0;
-    std::lock_guard<std::mutex> lk(s->mu);
-    return s->pending;
+    std::lock_guard<std::mutex> lk(s->core.mu);
+    return s->core.pending;
 }
 
 void isax_server_destroy(isax_server* s) {
     if (!s) return;
     {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->stop = true;
+        std::lock_guard<std::mutex> lk(s->core.mu);
+        s->core.stop = true;
     }
-    s->cv_work.notify_all();
-    for (auto& t : s->workers) t.join();
+    s->core.cv_work.notify_all();
+    for (auto& t : s->threads) t.join();
     delete s;
 }
 

@@ -68,16 +68,29 @@ def _serve(isax, indexes, reqs, mode="index", rate_hz=2000.0, **opt):
     return out
 
 
-@pytest.mark.parametrize("mode", ["index", "bf16", "hybrid"])
-def test_alone_equals_mix_and_oracle(isax, colls, mode):
-    indexes = [isax.Index(X, 16, 8, precision=1 if mode in ("bf16", "hybrid") else 0) for X in colls]
+def _overlapping(out):
+    """Two requests taken in at different times whose service intervals overlap."""
+    iv = sorted((r["t_start"], r["t_done"]) for r in out.values())
+    return any(iv[i + 1][0] > iv[i][0] and iv[i + 1][0] < iv[i][1] for i in range(len(iv) - 1))
+
+
+# (mode, server options): batch-level admission, and step-level admission (the
+# filter modes' default) with small tables so that rows are reused
+CASES = [("index", dict(max_batch=16, streams=3)), ("hybrid", dict(max_batch=16, streams=3)),
+         ("bf16", dict(max_batch=16, streams=3, batches=True)), ("bf16", dict(max_batch=24, chunks=8)),
+         ("fp8", dict(max_batch=24, chunks=5)), ("bf16", dict(max_batch=7, chunks=1))]
+
+
+@pytest.mark.parametrize("mode,opt", CASES, ids=[f"{m}-{'-'.join(f'{k}{v}' for k, v in o.items())}" for m, o in CASES])
+def test_alone_equals_mix_and_oracle(isax, colls, mode, opt):
+    indexes = [isax.Index(X, 16, 8, precision={"bf16": 1, "hybrid": 1, "fp8": 2}.get(mode, 0)) for X in colls]
     reqs = _requests(colls, 90, seed=11)
-    out = _serve(isax, indexes, reqs, mode=mode, max_batch=16, streams=3)
+    out = _serve(isax, indexes, reqs, mode=mode, **opt)
     Xh = [X.cpu().numpy() for X in colls]
     sizes = set()
     for tag, (c, q, k) in enumerate(reqs):
         r = out[tag]
-        assert r["status"] == 0
+        assert r["status"] == 0, r["message"]
         sizes.add(r["batch_size"])
         qt = torch.from_numpy(q[None]).cuda()
         ids1, d1 = indexes[c].query(qt, k=k, mode=mode)
@@ -87,7 +100,27 @@ def test_alone_equals_mix_and_oracle(isax, colls, mode):
         assert r["ids"] == ref_ids[0].tolist()
         assert np.allclose(r["dists"], np.sqrt(ref_d2[0]), rtol=1e-4, atol=0)
         assert r["t_submit"] <= r["t_start"] <= r["t_done"]
-    assert max(sizes) > 1, "no request was batched with another"
+    assert max(sizes) > 1, "no request was served together with another"
+    assert _overlapping(out), "no two requests taken in at different times were in service together"
+
+
+def test_step_level_rows_that_need_a_run_of_their_own(isax, colls):
+    # 3000 copies of one series: a query equal to it ties with all of them, more than the
+    # table's final ordering takes, so the engine answers it by itself; the others are unaffected
+    X = colls[0].clone()
+    rng = np.random.default_rng(20091173)
+    dup = np.sort(rng.choice(X.shape[0], size=3000, replace=False))
+    X[torch.as_tensor(dup[1:], device="cuda")] = X[int(dup[0])].clone()
+    idx = isax.Index(X, 16, 8, precision=1)
+    reqs = [(0, X[int(dup[0])].cpu().numpy(), 5)] + [(0, q, k) for c, q, k in _requests([X, colls[1]], 40, seed=13)
+                                                      if c == 0]
+    out = _serve(isax, [idx], reqs, mode="bf16", max_batch=16, chunks=4)
+    r = out[0]
+    assert r["status"] == 0 and r["ids"] == dup[:5].tolist() and r["dists"] == [0.0] * 5
+    Xh = X.cpu().numpy()
+    for tag, (c, q, k) in enumerate(reqs):
+        ref_ids, _ = kr.knn_exact_c(Xh, q[None], k)
+        assert out[tag]["ids"] == ref_ids[0].tolist()
 
 
 def test_memory_budget_forces_small_batches(isax, colls):

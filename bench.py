@@ -58,12 +58,17 @@ def main():
     ap.add_argument("--cpu-sample-series", type=int, default=10_000_000)
     ap.add_argument("--cpu-sample-queries", type=int, default=128)
     ap.add_argument("--serve-requests", type=int, default=3000)
+    ap.add_argument("--serve-alone", type=int, default=40, help="requests sent one at a time for batch-1 latency")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="instead of the headline: serve 50M x 256 + 20M x 128 at swept Poisson rates")
     ap.add_argument("--sweep-mode", default="bf16", choices=["index", "scan", "bf16", "fp8", "hybrid"])
     ap.add_argument("--serve-mode", default="bf16", choices=["index", "scan", "bf16", "fp8", "hybrid"],
                     help="mode of the serving leg (BF16 serves mixed traffic with the lowest latency)")
+    ap.add_argument("--serve-batches", action="store_true",
+                    help="batch-level admission in the serving legs (default for BF16 / FP8: step level)")
+    ap.add_argument("--serve-chunks", type=int, default=8, help="step level: steps per sweep of a collection")
+    ap.add_argument("--serve-rows", type=int, default=512, help="step level: rows of a collection's table")
     ap.add_argument("--precision-report", action="store_true",
                     help="instead of the headline: 10M x 256, batches of 1024, modes and filter error vs FP64")
     ap.add_argument("--sigma-report", action="store_true",
@@ -213,9 +218,21 @@ def main():
         # half of the serving mode's batch throughput (measured above when it is not the timed mode)
         rate = 0.5 * (qps if args.serve_mode == args.mode else modes_qps.get(args.serve_mode, qps))
         log(f"serving {args.serve_requests} Poisson arrivals at {rate:.0f}/s")
-        srv = isax.Server([idx], mode=args.serve_mode, max_batch=512, streams=4)
+        step = args.serve_mode in ("bf16", "fp8") and not args.serve_batches
+        srv = isax.Server([idx], mode=args.serve_mode, max_batch=args.serve_rows if step else 512, streams=4,
+                          batches=args.serve_batches, chunks=args.serve_chunks)
         Qh = Q.cpu().numpy()
         rng = np.random.default_rng(7)
+        # batch-1 latency: one request at a time on the idle server
+        one = []
+        for i in range(args.serve_alone + 1):
+            t0 = time.perf_counter()
+            srv.submit(0, Qh[i % m], k, 10 ** 9 + i)
+            got = []
+            while not got:
+                got = srv.poll(100)
+            if i:
+                one.append((got[0]["t_done"] - got[0]["t_submit"]) * 1e3)
         res = {}
 
         def producer():
@@ -238,11 +255,17 @@ def main():
         srv.close()
         lat = np.array([(r["t_done"] - r["t_submit"]) * 1e3 for r in res.values()])
         bad = sum(1 for i, r in res.items() if r["ids"][0] != int(ids[i % m, 0]))
-        serving = {"mode": args.serve_mode, "requests": len(res), "offered_rate": round(rate, 1),
+        serving = {"mode": args.serve_mode, "admission": "step" if step else "batch",
+                   "requests": len(res), "offered_rate": round(rate, 1),
                    "qps": round(len(res) / te, 1),
                    "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
                    "mean_batch": round(float(np.mean([r["batch_size"] for r in res.values()])), 1),
-                   "mismatches": bad}
+                   "mismatches": bad,
+                   "batch1_p50_ms": round(float(np.percentile(one, 50)), 3) if one else None,
+                   "batch1_p99_ms": round(float(np.percentile(one, 99)), 3) if one else None}
+        if step:
+            serving["chunks"] = args.serve_chunks
+            serving["rows"] = args.serve_rows
         log(f"serving: {serving}")
 
     # ---------------------------------------------------------------- CPU oracle on a bounded sample
@@ -353,7 +376,9 @@ def serving_sweep(args, dev):
             out.append((c, pools[c][int(rng.integers(len(pools[c])))], int(rng.choice([1, 10, 100]))))
         return out
 
-    srv = isax.Server(idx, mode=mode, max_batch=512, streams=4)
+    step = mode in ("bf16", "fp8") and not args.serve_batches
+    srv = isax.Server(idx, mode=mode, max_batch=args.serve_rows if step else 512, streams=4,
+                      batches=args.serve_batches, chunks=args.serve_chunks)
     _serve_run(isax, srv, make_reqs(512), 0.0, rng)          # warm-up
     burst = make_reqs(4096)
     res, wall = _serve_run(isax, srv, burst, 0.0, rng)
@@ -381,12 +406,35 @@ def serving_sweep(args, dev):
               "alone_vs_mix_mismatches": bad}
         log(f"rate {frac:.2f} x sat: {pt}")
         points.append(pt)
+        last = (reqs, res)
     srv.close()
+    # the FP64 oracle on a sample of the last rate's requests, streamed over each collection
+    from oracle import knn_ref
+    reqs, res = last
+    oracle_bad, oracle_n = 0, 0
+    for c, X in enumerate(cols):
+        tags = [t for t in sorted(res) if reqs[t][0] == c][:: 25][:24]
+        if not tags:
+            continue
+        kk = max(reqs[t][2] for t in tags)
+        st = knn_ref.KnnState(np.stack([reqs[t][1] for t in tags]).astype(np.float32), kk)
+        for a in range(0, X.shape[0], 5_000_000):
+            st.merge(X[a:a + 5_000_000].cpu().numpy(), a)
+        for j, t in enumerate(tags):
+            kq = reqs[t][2]
+            r = res[t]
+            ok = r["ids"] == st.ids[j, :kq].tolist() and np.allclose(r["dists"], np.sqrt(st.d2[j, :kq]), rtol=1e-4,
+                                                                       atol=0)
+            oracle_bad += int(not ok)
+            oracle_n += 1
+        log(f"oracle sample of collection {c}: {len(tags)} requests checked")
+    admission = (f"step level: {args.serve_rows} rows per collection, {args.serve_chunks} steps per sweep"
+                 if step else "batch level: dynamic batching (max 512), 4 streams, 4 GiB scratch budget")
     print(json.dumps({"metric": "serving p50/p99 latency and queries/s", "mode": mode,
                       "config": {"workload": "50M x 256 + 20M x 128 random walks resident; Poisson arrivals; "
-                                             "k in {1,10,100}; sigma in {0.01,0.1,1}; dynamic batching (max 512), "
-                                             "4 streams, admission by a 4 GiB scratch budget"},
-                      "saturation_qps": round(sat, 1), "sweep": points}), flush=True)
+                                             "k in {1,10,100}; sigma in {0.01,0.1,1}; " + admission},
+                      "saturation_qps": round(sat, 1), "sweep": points,
+                      "oracle_sample": {"requests": oracle_n, "mismatches": oracle_bad}}), flush=True)
 
 
 def precision_report(args, dev):

@@ -321,7 +321,7 @@ typedef struct isax_server_options {
     int32_t mode;            /* ISAX_MODE_* used for every request (hybrid with its cost model); the
                                 server answers Euclidean k-NN */
     int32_t flags;           /* ISAX_SERVE_* */
-    int32_t chunks;          /* step level: steps per sweep of a collection; 0 = 16; 1..1024 */
+    int32_t chunks;          /* step level: steps per sweep of a collection; 0 = 8; 1..1024 */
     int32_t reserved;        /* must be 0 */
 } isax_server_options;
 

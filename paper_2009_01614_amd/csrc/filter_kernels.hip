@@ -235,15 +235,18 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
     // tiles of this phase, enumerated as virtual tiles v = 0 .. n_vt-1
     // (n < 2^31, so tile numbers fit in 32 bits; kFilterSub is a constant, so the
     // division below is a multiply)
+    // tiles of this phase, enumerated as virtual tiles v = 0 .. n_vt-1 (n < 2^31)
+    constexpr int R = kFilterAlign / C::TS;
     const int n_tiles = (int)((a.n + C::TS - 1) / C::TS);
-    const int n_sub = (n_tiles + kFilterSub - 1) / kFilterSub;
-    const int t_lo = (int)(f.range_lo / C::TS), t_hi = (int)((f.range_hi + C::TS - 1) / C::TS);
-    const int n_vt = f.phase == 0 ? n_tiles : f.phase == 1 ? n_sub : f.phase == 2 ? n_tiles - n_sub : t_hi - t_lo;
+    const int n_samp = (int)filter_samples_before(n_tiles, R);
+    const int64_t t_lo = f.range_lo / C::TS, t_hi = (f.range_hi + C::TS - 1) / C::TS;
+    const int g_lo = (int)(t_lo - filter_samples_before(t_lo, R)), g_hi = (int)(t_hi - filter_samples_before(t_hi, R));
+    const int n_vt = f.phase == 0 ? n_tiles : f.phase == 1 ? n_samp : f.phase == 2 ? n_tiles - n_samp : g_hi - g_lo;
     auto tile_of = [&](int v) -> int64_t {
         return f.phase == 0   ? v
-               : f.phase == 1 ? v * kFilterSub
-               : f.phase == 2 ? v + v / (kFilterSub - 1) + 1
-                              : t_lo + v;
+               : f.phase == 1 ? filter_sample_tile(v, R)
+               : f.phase == 2 ? filter_other_tile(v, R)
+                              : filter_other_tile(g_lo + v, R);
     };
     const unsigned char* X = static_cast<const unsigned char*>(f.xq);
     // one column tile's rows (part) at a time: the next tile's part p is loaded
@@ -543,15 +546,18 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter_bf16(QueryArgs a, FilterA
             valid |= (q_base + 32 * t + 8 * (e >> 2) + 4 * h + (e & 3) < a.mq ? 1u : 0u) << (16 * t + e);
     unsigned wcount = 0u;  // this wave's candidates in the current tile (wave-uniform)
 
+    // tiles of this phase, enumerated as virtual tiles v = 0 .. n_vt-1 (n < 2^31)
+    constexpr int R = kFilterAlign / C::TS;
     const int n_tiles = (int)((a.n + C::TS - 1) / C::TS);
-    const int n_sub = (n_tiles + kFilterSub - 1) / kFilterSub;
-    const int t_lo = (int)(f.range_lo / C::TS), t_hi = (int)((f.range_hi + C::TS - 1) / C::TS);
-    const int n_vt = f.phase == 0 ? n_tiles : f.phase == 1 ? n_sub : f.phase == 2 ? n_tiles - n_sub : t_hi - t_lo;
+    const int n_samp = (int)filter_samples_before(n_tiles, R);
+    const int64_t t_lo = f.range_lo / C::TS, t_hi = (f.range_hi + C::TS - 1) / C::TS;
+    const int g_lo = (int)(t_lo - filter_samples_before(t_lo, R)), g_hi = (int)(t_hi - filter_samples_before(t_hi, R));
+    const int n_vt = f.phase == 0 ? n_tiles : f.phase == 1 ? n_samp : f.phase == 2 ? n_tiles - n_samp : g_hi - g_lo;
     auto tile_of = [&](int v) -> int64_t {
         return f.phase == 0   ? v
-               : f.phase == 1 ? v * kFilterSub
-               : f.phase == 2 ? v + v / (kFilterSub - 1) + 1
-                              : t_lo + v;
+               : f.phase == 1 ? filter_sample_tile(v, R)
+               : f.phase == 2 ? filter_other_tile(v, R)
+                              : filter_other_tile(g_lo + v, R);
     };
     const unsigned char* X = static_cast<const unsigned char*>(f.xq);
     // the whole tile `tl` into `dst`: instruction j of this wave fills slots [64 (j WAVES + wave), +64).
@@ -887,14 +893,18 @@ void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qm
     if ((int64_t)qtiles * C::QPB > f.mq_pad)
         throw Error{ISAX_EINVAL, "internal: query codes padded to fewer rows than the filter reads"};
     const int per_cu = WAVES >= 8 ? 1 : 4;
-    int64_t n_tiles = (a.n + C::TS - 1) / C::TS;
-    const int64_t n_sub = (n_tiles + kFilterSub - 1) / kFilterSub;
-    if (f.phase == 1) n_tiles = n_sub;
-    if (f.phase == 2) n_tiles -= n_sub;
+    static_assert(kFilterAlign % C::TS == 0, "the sample units and serving chunks start on a tile");
+    constexpr int R = kFilterAlign / C::TS;
+    const int64_t all_tiles = (a.n + C::TS - 1) / C::TS;
+    const int64_t n_samp = filter_samples_before(all_tiles, R);
+    int64_t n_tiles = all_tiles;
+    if (f.phase == 1) n_tiles = n_samp;
+    if (f.phase == 2) n_tiles -= n_samp;
     if (f.phase == 3) {
-        static_assert(kFilterAlign % C::TS == 0, "a serving chunk starts on a tile of every configuration");
-        n_tiles = (f.range_hi + C::TS - 1) / C::TS - f.range_lo / C::TS;
+        const int64_t t_lo = f.range_lo / C::TS, t_hi = (f.range_hi + C::TS - 1) / C::TS;
+        n_tiles = (t_hi - filter_samples_before(t_hi, R)) - (t_lo - filter_samples_before(t_lo, R));
     }
+    if (n_tiles <= 0) return;
     // n_streams * qtiles blocks, n_streams a multiple of 8 (one group per XCD)
     int n_streams = std::max(8, (per_cu * cus / qtiles) / 8 * 8);
     while (n_streams > 8 && n_streams / 2 >= n_tiles) n_streams /= 2;

@@ -134,17 +134,17 @@ struct StepTable;
 StepTable* step_table_create(isax_index* idx, int mode, int slots, int chunks, hipStream_t s);
 void step_table_destroy(StepTable* t);
 int step_table_chunks(const StepTable* t);  // steps per sweep (at most the requested chunks)
-// Queries hq [n][len] (host) with k hk[n] into the free rows rows[0..n).
-void step_table_admit(StepTable* t, const float* hq, const int32_t* hk, const int* rows, int n);
-// One step: chunk `chunk` of the sweep for the occupied rows among [0, hi).
-void step_table_step(StepTable* t, int chunk, int hi);
-// Rows rows[0..n) have swept the whole collection: their answers are ordered
-// and the rows become free.
-void step_table_finish(StepTable* t, const int* rows, int n);
-// Waits for the queued work; ovf (host, hi) <- rows that lost filter candidates
-// in the last step; ids / dists (host, [n][kout]) and status (0, else the row
-// must be answered alone) of the last finish.
-void step_table_sync(StepTable* t, int* ovf, int kout, int64_t* ids, float* dists, int* status);
+// Queues one step (at most two queued): queries q [n_adm][len] (host) with k
+// into the free rows adm[], chunk `chunk` for the occupied rows among [0, hi),
+// then the final ordering of the rows fin[] (which become free).
+void step_table_launch(StepTable* t, const float* q, const int32_t* k, const int* adm, int n_adm, int chunk, int hi,
+                       const int* fin, int n_fin);
+// Waits for the oldest queued step: ovf (host, its hi) <- rows that lost filter
+// candidates; ids / dists (host, [n_fin][kout]) and status (0, else the row
+// must be answered alone) of its final ordering.
+void step_table_collect(StepTable* t, int* ovf, int kout, int64_t* ids, float* dists, int* status);
+// After a failure: drains the stream, forgets queued steps, frees every row.
+void step_table_reset(StepTable* t);
 
 }  // namespace isax
 

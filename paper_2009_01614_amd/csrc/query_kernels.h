@@ -38,6 +38,7 @@ struct QueryArgs {
     int rerun;        // 1: frozen best-so-far, no best-k insertion, skip finished queries
     int skip_done;    // 1: rows whose done flag is set take no part in the filter and its refinement
                       //    (the free slots of a serving table)
+    int home_leaves;  // leaves the approximate answer covers at least (0: the default, 4)
     float* paa;       // [mq][w]
     uint8_t* sym;     // [mq][ws]
     uint64_t* qkey;   // [mq]
@@ -124,11 +125,25 @@ struct FilterArgs {
     int fcap;
     float* out_approx;        // optional [mq][n] (inspection)
     float* out_margin;        // optional [mq][n]
-    int phase;                // 0: every tile; 1: tiles t % kFilterSub == 0; 2: the other tiles;
-                              // 3: the series at sorted positions [range_lo, range_hi)
+    int phase;                // 0: every tile; 1: the sample tiles; 2: the other tiles;
+                              // 3: the other tiles among sorted positions [range_lo, range_hi)
     int64_t range_lo, range_hi;  // phase 3; range_lo a multiple of kFilterAlign
 };
+// The sample of the first phase: units of kFilterAlign consecutive sorted
+// positions, every kFilterSub-th unit (the same series for every tile size of
+// the filter's configurations).  With R = kFilterAlign / TS tiles per unit:
 constexpr int kFilterAlign = 128;  // the largest tile of any filter configuration
+// sample tiles among tiles [0, t)
+__host__ __device__ inline int64_t filter_samples_before(int64_t t, int R) {
+    const int64_t g = (int64_t)kFilterSub * R;
+    return t / g * R + (t % g < R ? t % g : R);
+}
+// tile of the v-th sample tile (phase 1) or of the v-th other tile (phases 2 and 3)
+__host__ __device__ inline int64_t filter_sample_tile(int64_t v, int R) { return v / R * kFilterSub * R + v % R; }
+__host__ __device__ inline int64_t filter_other_tile(int64_t v, int R) {
+    const int64_t g = (int64_t)(kFilterSub - 1) * R;
+    return v / g * kFilterSub * R + R + v % g;
+}
 int filter_len_pad(int len);              // rows of the reduced-precision copies are padded to this
 int filter_queries_per_block(int len);    // query codes are padded to a multiple of this
 int filter_rows_bf16(int len, int mq);    // query rows the BF16 filter computes for mq queries

@@ -596,7 +596,8 @@ __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
         }
         int64_t l0 = lo, l1 = lo + 1;
         auto count = [&](int64_t x0, int64_t x1) { return min(a.n, x1 * a.leaf_size) - x0 * a.leaf_size; };
-        const int64_t want = max((int64_t)k, min((int64_t)kHomeLeaves * a.leaf_size, (int64_t)kHomeMax - 2 * 1024));
+        const int64_t leaves = a.home_leaves > 0 ? a.home_leaves : kHomeLeaves;
+        const int64_t want = max((int64_t)k, min(leaves * a.leaf_size, (int64_t)kHomeMax - 2 * 1024));
         while (count(l0, l1) < want && count(l0, l1) < a.n) {
             // grow alternately after and before the home leaf
             if ((l1 - l0) % 2 == 1 ? l1 < a.n_leaves : l0 == 0) {

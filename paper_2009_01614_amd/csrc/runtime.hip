@@ -1295,19 +1295,25 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
 }  // namespace
 
 // =============================================================================================
-// Serving table of the step-level request loop (serve.cpp).  `slots` query rows
-// stay resident (a Batch with the filter's per-row state); a step runs the
-// filter over one chunk of the collection for every occupied row and refines
-// its candidates, so a row that joined at any chunk has covered the whole
-// collection after `chunks` steps (the sweep wraps around).  Rows join through
-// an admission batch (approximate answer and query codes, as for a batch of
-// their own) whose state is copied into the table; finished rows are copied
-// into an ordering batch for the top-k.  Free rows carry done = 1 and take no
-// part (skip_done).  The filter's bound on the query factors is a running
-// maximum over every row admitted so far, an upper bound of each row's own.
+// Serving table of the step-level request loop (serve_sched.cpp).  `slots`
+// query rows stay resident (a Batch with the filter's per-row state); a step
+// runs the filter over one chunk of the collection for every occupied row and
+// refines its candidates, so a row that joined at any chunk has covered the
+// whole collection after `chunks` steps (the sweep wraps around).  Rows join
+// through an admission batch (approximate answer and query codes, as for a
+// batch of their own) whose state is copied into the table; finished rows are
+// copied into an ordering batch for the top-k.  An admitted row first runs the
+// filter over the sample units of the collection (the batch path's first
+// phase), which tightens its bound before it joins; the sweep then covers the
+// other units only, so every series is met exactly once.  Free rows carry
+// done = 1 and take no part (skip_done).  The filter's bound on the query factors is a
+// running maximum over every row admitted so far, an upper bound of each
+// row's own.  Two steps may be queued at a time: the host staging is double
+// buffered, and a step's answers are read once its event has completed.
 namespace isax {
 constexpr int kServeCand = 16384;   // candidate slots per row (the query's list)
-constexpr int kServeFcap = 32768;   // filter candidates per row and step
+constexpr int kServeFcap = 65536;   // filter candidates per row and step
+constexpr int kServeHomeLeaves = 1; // leaves of an admitted row's approximate answer
 
 struct StepTable {
     isax_index* idx = nullptr;
@@ -1320,27 +1326,38 @@ struct StepTable {
     DevBuf own;                     // query rows and k of the table and the ordering batch, answers
     float* dq = nullptr;            // [slots][len] admitted queries
     int32_t* dk = nullptr;          // [slots] their k
-    int2* dmap = nullptr;           // [slots] row copies
-    int* dovf = nullptr;            // [slots]
-    // pinned host staging
-    float* hq = nullptr;
-    int32_t* hk = nullptr;
-    int2* hmap = nullptr;           // admission copies
-    int2* hmap2 = nullptr;          // finishing copies
-    int* hovf = nullptr;
-    int* hstatus = nullptr;
-    int64_t* hids = nullptr;
-    float* hdists = nullptr;
-    int n_fin = 0, hi_last = 0;
+    int2* dmap = nullptr;           // [2 slots] row copies: admission, then final ordering
+    int* dovf = nullptr;            // [2 slots] overflow flags: the table's rows, then the admitted rows
+    // pinned host staging, one set per queued step
+    struct Host {
+        float* q = nullptr;
+        int32_t* k = nullptr;
+        int2* map_adm = nullptr;
+        int2* map_fin = nullptr;
+        int* ovf = nullptr;
+        int* ovf_adm = nullptr;     // [n_adm] the admitted rows' first phase
+        int* adm = nullptr;         // [n_adm] their table rows
+        int* status = nullptr;
+        int64_t* ids = nullptr;
+        float* dists = nullptr;
+        hipEvent_t done = nullptr;
+        int n_fin = 0, hi = 0, n_adm = 0;
+    } h[2];
+    int64_t launched = 0, collected = 0;
     ~StepTable() {
-        (void)hipHostFree(hq);
-        (void)hipHostFree(hk);
-        (void)hipHostFree(hmap);
-        (void)hipHostFree(hmap2);
-        (void)hipHostFree(hovf);
-        (void)hipHostFree(hstatus);
-        (void)hipHostFree(hids);
-        (void)hipHostFree(hdists);
+        for (Host& x : h) {
+            (void)hipHostFree(x.q);
+            (void)hipHostFree(x.k);
+            (void)hipHostFree(x.map_adm);
+            (void)hipHostFree(x.map_fin);
+            (void)hipHostFree(x.ovf);
+            (void)hipHostFree(x.ovf_adm);
+            (void)hipHostFree(x.adm);
+            (void)hipHostFree(x.status);
+            (void)hipHostFree(x.ids);
+            (void)hipHostFree(x.dists);
+            if (x.done) (void)hipEventDestroy(x.done);
+        }
     }
 };
 
@@ -1375,18 +1392,18 @@ StepTable* step_table_create(isax_index* idx, int mode, int slots, int chunks, h
     t->s = s;
     t->chunk_len = std::max<int64_t>(kFilterAlign, (idx->n + chunks - 1) / chunks / kFilterAlign * kFilterAlign);
     t->chunks = (int)((idx->n + t->chunk_len - 1) / t->chunk_len);
-    // per-row k is set by each admission; every table row starts free (done = 1)
     std::vector<int32_t> ones(slots, 1);
     Arena ar;
     ar.add(&t->dq, (size_t)slots * idx->len);
     ar.add(&t->dk, slots);
-    ar.add(&t->dmap, slots);
-    ar.add(&t->dovf, slots);
+    ar.add(&t->dmap, 2 * (size_t)slots);
+    ar.add(&t->dovf, 2 * (size_t)slots);
     t->dev = ar.commit(s);
     ISAX_HIP(hipMemcpyAsync(t->dk, ones.data(), slots * sizeof(int32_t), hipMemcpyHostToDevice, s));
     setup_batch(t->tab, idx, t->dq, slots, t->dk, t->kmax, kServeCand, 0, nullptr, nullptr, s);
     setup_batch(t->adm, idx, t->dq, slots, t->dk, t->kmax, kServeCand, 0, nullptr, nullptr, s);
     setup_batch(t->fin, idx, t->dq, slots, t->dk, t->kmax, kServeCand, 0, nullptr, nullptr, s);
+    t->adm.a.home_leaves = kServeHomeLeaves;
     // the table and the ordering batch hold their own query rows and k (copied with the state)
     {
         t->own = DevBuf((size_t)slots * (idx->len * 4 + 4) * 2 + (size_t)slots * t->kmax * 12, s);
@@ -1406,17 +1423,22 @@ StepTable* step_table_create(isax_index* idx, int mode, int slots, int chunks, h
     }
     t->tab.a.skip_done = 1;
     setup_filter(t->ftab, idx, t->tab.a, mode, kServeFcap, s);
-    setup_filter(t->fadm, idx, t->adm.a, mode, 1, s);
+    setup_filter(t->fadm, idx, t->adm.a, mode, kServeFcap, s);
     // every table row free: done = 1
     ISAX_HIP(hipMemcpyAsync(t->tab.a.done, ones.data(), slots * sizeof(int), hipMemcpyHostToDevice, s));
-    t->hq = pinned<float>((size_t)slots * idx->len);
-    t->hk = pinned<int32_t>(slots);
-    t->hmap = pinned<int2>(slots);
-    t->hmap2 = pinned<int2>(slots);
-    t->hovf = pinned<int>(slots);
-    t->hstatus = pinned<int>(slots);
-    t->hids = pinned<int64_t>((size_t)slots * t->kmax);
-    t->hdists = pinned<float>((size_t)slots * t->kmax);
+    for (StepTable::Host& x : t->h) {
+        x.q = pinned<float>((size_t)slots * idx->len);
+        x.k = pinned<int32_t>(slots);
+        x.map_adm = pinned<int2>(slots);
+        x.map_fin = pinned<int2>(slots);
+        x.ovf = pinned<int>(slots);
+        x.ovf_adm = pinned<int>(slots);
+        x.adm = pinned<int>(slots);
+        x.status = pinned<int>(slots);
+        x.ids = pinned<int64_t>((size_t)slots * t->kmax);
+        x.dists = pinned<float>((size_t)slots * t->kmax);
+        ISAX_HIP(hipEventCreateWithFlags(&x.done, hipEventDisableTiming));
+    }
     ISAX_HIP(hipStreamSynchronize(s));
     return t.release();
 }
@@ -1429,73 +1451,100 @@ void step_table_destroy(StepTable* t) {
 
 int step_table_chunks(const StepTable* t) { return t->chunks; }
 
-// Queries hq [n][len] with k hk[n] into table rows rows[0..n): approximate
-// answer and query codes in the admission batch, then the state into the rows.
-void step_table_admit(StepTable* t, const float* hq, const int32_t* hk, const int* rows, int n) {
-    if (n <= 0) return;
-    ISAX_REQUIRE(n <= t->slots, "more admissions than table rows");
+// Queues one step: queries q [n_adm][len] with k into the free rows adm[]
+// (approximate answer and query codes in the admission batch, then the state
+// into the rows), chunk `chunk` of the sweep for the occupied rows among
+// [0, hi) (filter, refinement, overflow flags), then the final ordering of the
+// rows fin[] (their state into the ordering batch, the rows become free, the
+// top-k, the answers to the host).
+void step_table_launch(StepTable* t, const float* q, const int32_t* k, const int* adm, int n_adm, int chunk, int hi,
+                       const int* fin, int n_fin) {
+    ISAX_REQUIRE(t->launched - t->collected < 2, "at most two serving steps are queued");
+    ISAX_REQUIRE(n_adm >= 0 && n_fin >= 0 && n_adm + n_fin <= t->slots && hi <= t->slots && chunk >= 0 &&
+                     chunk < t->chunks,
+                 "bad serving step");
+    StepTable::Host& x = t->h[t->launched & 1];
     const int len = t->idx->len;
-    std::memcpy(t->hq, hq, (size_t)n * len * sizeof(float));
-    std::memcpy(t->hk, hk, (size_t)n * sizeof(int32_t));
-    for (int i = 0; i < n; ++i) t->hmap[i] = make_int2(i, rows[i]);
-    ISAX_HIP(hipMemcpyAsync(t->dq, t->hq, (size_t)n * len * sizeof(float), hipMemcpyHostToDevice, t->s));
-    ISAX_HIP(hipMemcpyAsync(t->dk, t->hk, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, t->s));
-    ISAX_HIP(hipMemcpyAsync(t->dmap, t->hmap, (size_t)n * sizeof(int2), hipMemcpyHostToDevice, t->s));
-    const QueryArgs a = rows_view(t->adm.a, n);
-    launch_qprep(a, t->s);
-    launch_homeleaf(a, t->s);
-    launch_quantise_queries(a, t->fadm.f, t->fadm.mq_pad, t->ftab.qmax, t->s);
-    launch_copy_rows(a, t->fadm.f, t->tab.a, t->ftab.f, t->dmap, n, false, t->s);
-}
-
-// One step: the filter over chunk `chunk` for table rows [0, hi), then the
-// refinement of its candidates; the overflow flags of the step.
-void step_table_step(StepTable* t, int chunk, int hi) {
-    t->hi_last = hi;
-    if (hi <= 0) return;
-    const QueryArgs a = rows_view(t->tab.a, hi);
-    FilterArgs f = t->ftab.f;
-    f.phase = 3;
-    f.range_lo = (int64_t)chunk * t->chunk_len;
-    f.range_hi = std::min<int64_t>(t->idx->n, f.range_lo + t->chunk_len);
-    launch_filter(a, f, t->ftab.qmax, t->s);
-    launch_refine_filtered(a, f, t->s);
-    launch_note_overflow(a, f, t->dovf, t->s);
-    ISAX_HIP(hipMemcpyAsync(t->hovf, t->dovf, (size_t)hi * sizeof(int), hipMemcpyDeviceToHost, t->s));
-}
-
-// Rows rows[0..n) have covered the collection: their state into the ordering
-// batch (the table rows become free), the top-k, the answers to the host.
-void step_table_finish(StepTable* t, const int* rows, int n) {
-    t->n_fin = n;
-    if (n <= 0) return;
-    ISAX_REQUIRE(n <= t->slots, "more finished rows than table rows");
-    for (int i = 0; i < n; ++i) t->hmap2[i] = make_int2(rows[i], i);
-    // the admission of this step may still read the front of the device map: the back holds
-    // this one (admitted rows were free and finishing rows are occupied, so both fit)
-    int2* dm = t->dmap + (t->slots - n);
-    ISAX_HIP(hipMemcpyAsync(dm, t->hmap2, (size_t)n * sizeof(int2), hipMemcpyHostToDevice, t->s));
-    const QueryArgs fa = rows_view(t->fin.a, n);
-    FilterArgs none{};
-    launch_copy_rows(t->tab.a, t->ftab.f, fa, none, dm, n, true, t->s);
-    launch_topk(fa, t->s);
-    ISAX_HIP(hipMemcpyAsync(t->hstatus, fa.status, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, t->s));
-    ISAX_HIP(hipMemcpyAsync(t->hids, fa.out_ids, (size_t)n * t->kmax * sizeof(int64_t), hipMemcpyDeviceToHost, t->s));
-    ISAX_HIP(hipMemcpyAsync(t->hdists, fa.out_dists, (size_t)n * t->kmax * sizeof(float), hipMemcpyDeviceToHost,
-                            t->s));
-}
-
-// Waits for the queued work.  ovf (host, hi of the last step) receives the
-// step's overflow flags; ids / dists (host, [n_fin][kout]) and status the
-// answers of the finished rows (status != 0: the row must be answered alone).
-void step_table_sync(StepTable* t, int* ovf, int kout, int64_t* ids, float* dists, int* status) {
-    ISAX_HIP(hipStreamSynchronize(t->s));
-    std::memcpy(ovf, t->hovf, (size_t)t->hi_last * sizeof(int));
-    for (int i = 0; i < t->n_fin; ++i) {
-        status[i] = t->hstatus[i];
-        std::memcpy(ids + (size_t)i * kout, t->hids + (size_t)i * t->kmax, (size_t)kout * sizeof(int64_t));
-        std::memcpy(dists + (size_t)i * kout, t->hdists + (size_t)i * t->kmax, (size_t)kout * sizeof(float));
+    if (n_adm > 0) {
+        std::memcpy(x.q, q, (size_t)n_adm * len * sizeof(float));
+        std::memcpy(x.k, k, (size_t)n_adm * sizeof(int32_t));
+        for (int i = 0; i < n_adm; ++i) x.map_adm[i] = make_int2(i, adm[i]);
+        ISAX_HIP(hipMemcpyAsync(t->dq, x.q, (size_t)n_adm * len * sizeof(float), hipMemcpyHostToDevice, t->s));
+        ISAX_HIP(hipMemcpyAsync(t->dk, x.k, (size_t)n_adm * sizeof(int32_t), hipMemcpyHostToDevice, t->s));
+        ISAX_HIP(hipMemcpyAsync(t->dmap, x.map_adm, (size_t)n_adm * sizeof(int2), hipMemcpyHostToDevice, t->s));
+        const QueryArgs a = rows_view(t->adm.a, n_adm);
+        launch_qprep(a, t->s);
+        launch_homeleaf(a, t->s);
+        launch_quantise_queries(a, t->fadm.f, t->fadm.mq_pad, t->ftab.qmax, t->s);
+        // the sample units, refined into the admitted rows' own lists
+        FilterArgs f1 = t->fadm.f;
+        f1.phase = 1;
+        launch_filter(a, f1, t->ftab.qmax, t->s);
+        launch_refine_filtered(a, f1, t->s);
+        launch_note_overflow(a, f1, t->dovf + t->slots, t->s);
+        ISAX_HIP(hipMemcpyAsync(x.ovf_adm, t->dovf + t->slots, (size_t)n_adm * sizeof(int), hipMemcpyDeviceToHost,
+                                t->s));
+        launch_copy_rows(a, t->fadm.f, t->tab.a, t->ftab.f, t->dmap, n_adm, false, t->s);
     }
+    x.n_adm = n_adm;
+    std::copy(adm, adm + n_adm, x.adm);
+    x.hi = hi;
+    if (hi > 0) {
+        const QueryArgs a = rows_view(t->tab.a, hi);
+        FilterArgs f = t->ftab.f;
+        f.phase = 3;
+        f.range_lo = (int64_t)chunk * t->chunk_len;
+        f.range_hi = std::min<int64_t>(t->idx->n, f.range_lo + t->chunk_len);
+        launch_filter(a, f, t->ftab.qmax, t->s);
+        launch_refine_filtered(a, f, t->s);
+        launch_note_overflow(a, f, t->dovf, t->s);
+        ISAX_HIP(hipMemcpyAsync(x.ovf, t->dovf, (size_t)hi * sizeof(int), hipMemcpyDeviceToHost, t->s));
+    }
+    x.n_fin = n_fin;
+    if (n_fin > 0) {
+        for (int i = 0; i < n_fin; ++i) x.map_fin[i] = make_int2(fin[i], i);
+        int2* dm = t->dmap + t->slots;
+        ISAX_HIP(hipMemcpyAsync(dm, x.map_fin, (size_t)n_fin * sizeof(int2), hipMemcpyHostToDevice, t->s));
+        const QueryArgs fa = rows_view(t->fin.a, n_fin);
+        FilterArgs none{};
+        launch_copy_rows(t->tab.a, t->ftab.f, fa, none, dm, n_fin, true, t->s);
+        launch_topk(fa, t->s);
+        ISAX_HIP(hipMemcpyAsync(x.status, fa.status, (size_t)n_fin * sizeof(int), hipMemcpyDeviceToHost, t->s));
+        ISAX_HIP(hipMemcpyAsync(x.ids, fa.out_ids, (size_t)n_fin * t->kmax * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                t->s));
+        ISAX_HIP(hipMemcpyAsync(x.dists, fa.out_dists, (size_t)n_fin * t->kmax * sizeof(float),
+                                hipMemcpyDeviceToHost, t->s));
+    }
+    ISAX_HIP(hipEventRecord(x.done, t->s));
+    ++t->launched;
+}
+
+// Waits for the oldest queued step: ovf (host, its hi) <- rows that lost filter
+// candidates in its sweep; ids / dists (host, [n_fin][kout]) and status (0,
+// else the row must be answered alone) of its final ordering.
+void step_table_collect(StepTable* t, int* ovf, int kout, int64_t* ids, float* dists, int* status) {
+    ISAX_REQUIRE(t->collected < t->launched, "no serving step is queued");
+    StepTable::Host& x = t->h[t->collected & 1];
+    ISAX_HIP(hipEventSynchronize(x.done));
+    std::memcpy(ovf, x.ovf, (size_t)x.hi * sizeof(int));
+    for (int i = 0; i < x.n_adm; ++i)
+        if (x.ovf_adm[i]) ovf[x.adm[i]] = 1;
+    for (int i = 0; i < x.n_fin; ++i) {
+        status[i] = x.status[i];
+        std::memcpy(ids + (size_t)i * kout, x.ids + (size_t)i * t->kmax, (size_t)kout * sizeof(int64_t));
+        std::memcpy(dists + (size_t)i * kout, x.dists + (size_t)i * t->kmax, (size_t)kout * sizeof(float));
+    }
+    ++t->collected;
+}
+
+// After a failure: nothing is queued any more and every row is free.
+void step_table_reset(StepTable* t) {
+    (void)hipStreamSynchronize(t->s);
+    (void)hipGetLastError();
+    t->collected = t->launched;
+    std::vector<int> ones(t->slots, 1);
+    ISAX_HIP(hipMemcpyAsync(t->tab.a.done, ones.data(), t->slots * sizeof(int), hipMemcpyHostToDevice, t->s));
+    ISAX_HIP(hipStreamSynchronize(t->s));
 }
 }  // namespace isax
 

@@ -155,17 +155,15 @@ struct HipStepRunner : isax::serve::StepRunner {
             throw Failure{e.code, e.msg};
         }
     }
-    void admit(const float* q, const int32_t* k, const int* rows, int n) override {
-        guard([&] { isax::step_table_admit(table, q, k, rows, n); });
+    void launch(const float* q, const int32_t* k, const int* adm, int n_adm, int chunk, int hi, const int* fin,
+                int n_fin) override {
+        guard([&] { isax::step_table_launch(table, q, k, adm, n_adm, chunk, hi, fin, n_fin); });
     }
-    void step(int chunk, int hi) override {
-        guard([&] { isax::step_table_step(table, chunk, hi); });
+    void collect(int* ovf, int kout, int64_t* ids, float* dists, int* status) override {
+        guard([&] { isax::step_table_collect(table, ovf, kout, ids, dists, status); });
     }
-    void finish(const int* rows, int n) override {
-        guard([&] { isax::step_table_finish(table, rows, n); });
-    }
-    void sync(int* ovf, int kout, int64_t* ids, float* dists, int* status) override {
-        guard([&] { isax::step_table_sync(table, ovf, kout, ids, dists, status); });
+    void reset() override {
+        guard([&] { isax::step_table_reset(table); });
     }
     int run_alone(const float* q, int k, int64_t* ids, float* dists, std::string& err) override {
         isax_query_options qo{};
@@ -216,7 +214,7 @@ isax_server* isax_server_create(isax_index* const* collections, int32_t n_collec
     if (opt.max_batch == 0) opt.max_batch = step ? 512 : 256;
     if (opt.streams == 0) opt.streams = 4;
     if (opt.memory_budget == 0) opt.memory_budget = int64_t(4) << 30;
-    if (opt.chunks == 0) opt.chunks = 16;
+    if (opt.chunks == 0) opt.chunks = 8;
     if (opt.max_batch < 1 || opt.max_batch > 4096 || opt.streams < 1 || opt.streams > 16 || opt.memory_budget < 0 ||
         opt.mode < ISAX_MODE_INDEX || opt.mode > ISAX_MODE_HYBRID || (opt.flags & ~ISAX_SERVE_BATCHES) != 0 ||
         opt.chunks < 1 || opt.chunks > 1024 || opt.reserved != 0) {

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <memory>
 
 namespace isax {
 namespace serve {
@@ -104,27 +105,76 @@ void batch_worker(Core& core, BatchRunner& runner, int max_batch, int64_t memory
 }
 
 // ------------------------------------------------------------------ step level
+// Two steps are in flight: step j+1 is queued before the answers of step j are
+// read, so the device does not wait for the host between steps.  A request
+// holds its row from the step that admits it to the step that finishes it (a
+// finished row is free for the next step, since the device copies it out
+// first); the lost-candidate flags of a step belong to the requests that held
+// the rows in that step.
 void step_engine(Core& core, int coll, StepRunner& runner) {
-    struct Row {
-        bool busy = false;
-        bool ovf = false;  // lost filter candidates in some step: answered alone
-        int left = 0;      // steps until the row has swept the collection
-        int occupancy = 0; // occupied rows when it joined
-        double t_start = 0;
+    struct Entry {
         Request req;
+        bool ovf = false;   // lost filter candidates in some step: answered alone
+        int left = 0;       // steps until it has swept the collection
+        int occupancy = 0;  // occupied rows when it joined
+        double t_start = 0;
+    };
+    using EntryP = std::shared_ptr<Entry>;
+    struct Launched {
+        std::vector<EntryP> held;  // the row holders of the step, [hi]
+        std::vector<EntryP> fin;   // finished in the step, in the order of its answers
+        int kout = 1;
     };
     const int S = runner.slots(), C = runner.chunks(), len = runner.len();
-    std::vector<Row> rows(S);
+    std::vector<EntryP> rows(S);
+    std::deque<Launched> flight;
     std::vector<float> hq;
     std::vector<int32_t> hk;
-    std::vector<int> rid, fin, ovf(S), status(S);
+    std::vector<int> adm, fin, ovf(S), status(S);
     std::vector<int64_t> ids, one_ids(ISAX_MAX_K);
     std::vector<float> dists, one_d(ISAX_MAX_K);
     int chunk = 0, busy = 0;
-    auto release = [&](int r) {
-        rows[r].busy = false;
-        rows[r].req.q.clear();
-        --busy;
+    auto fail_all = [&](const Failure& f) {
+        // the table's state is unknown: every request in it or in flight fails with the error
+        for (Launched& l : flight)
+            for (EntryP& e : l.fin) core.publish(e->req, f.code, f.msg, e->occupancy, e->t_start, nullptr, nullptr);
+        flight.clear();
+        for (EntryP& e : rows)
+            if (e) {
+                core.publish(e->req, f.code, f.msg, e->occupancy, e->t_start, nullptr, nullptr);
+                e.reset();
+            }
+        busy = 0;
+        try {
+            runner.reset();
+        } catch (const Failure&) {
+        }
+    };
+    auto collect = [&]() {
+        Launched l = std::move(flight.front());
+        flight.pop_front();
+        ids.assign(l.fin.size() * l.kout, -1);
+        dists.assign(l.fin.size() * l.kout, 0.f);
+        runner.collect(ovf.data(), l.kout, ids.data(), dists.data(), status.data());
+        for (size_t r = 0; r < l.held.size(); ++r)
+            if (l.held[r] && ovf[r]) l.held[r]->ovf = true;
+        for (size_t j = 0; j < l.fin.size(); ++j) {
+            Entry& e = *l.fin[j];
+            if (status[j] != 0 || e.ovf) {
+                std::string err;
+                int rc = ISAX_EDEVICE;
+                try {
+                    rc = runner.run_alone(e.req.q.data(), e.req.k, one_ids.data(), one_d.data(), err);
+                } catch (const Failure& f) {
+                    rc = f.code;
+                    err = f.msg;
+                }
+                core.publish(e.req, rc, err, e.occupancy, e.t_start, one_ids.data(), one_d.data());
+            } else {
+                core.publish(e.req, ISAX_OK, "", e.occupancy, e.t_start, ids.data() + j * l.kout,
+                             dists.data() + j * l.kout);
+            }
+        }
     };
     for (;;) {
         std::vector<Request> admitted;
@@ -140,81 +190,60 @@ void step_engine(Core& core, int coll, StepRunner& runner) {
                         ++it;
                     }
                 }
-                if (!admitted.empty() || busy > 0) break;
+                if (!admitted.empty() || busy > 0 || !flight.empty()) break;
                 if (core.stop) return;
                 core.cv_work.wait(lk);
             }
         }
-        // free rows, lowest first, for the new requests
-        const int n = (int)admitted.size();
-        const double t_adm = now();
-        rid.clear();
-        hq.resize((size_t)n * len);
-        hk.resize(n);
-        for (int i = 0, r = 0; i < n; ++i, ++r) {
-            while (rows[r].busy) ++r;
-            Row& row = rows[r];
-            row.busy = true;
-            row.ovf = false;
-            row.left = C;
-            row.t_start = t_adm;
-            row.req = std::move(admitted[i]);
-            std::memcpy(hq.data() + (size_t)i * len, row.req.q.data(), (size_t)len * sizeof(float));
-            hk[i] = row.req.k;
-            rid.push_back(r);
-        }
-        busy += n;
-        for (int r : rid) rows[r].occupancy = busy;
-        int hi = 0;
-        for (int r = 0; r < S; ++r)
-            if (rows[r].busy) hi = r + 1;
-        fin.clear();
-        int kout = 1;
-        for (int r = 0; r < hi; ++r)
-            if (rows[r].busy && rows[r].left == 1) {
-                fin.push_back(r);
-                kout = std::max(kout, rows[r].req.k);
+        if (!admitted.empty() || busy > 0) {
+            // free rows, lowest first, for the new requests
+            const int n = (int)admitted.size();
+            const double t_adm = now();
+            adm.clear();
+            hq.resize((size_t)n * len);
+            hk.resize(n);
+            for (int i = 0, r = 0; i < n; ++i, ++r) {
+                while (rows[r]) ++r;
+                EntryP e = std::make_shared<Entry>();
+                e->req = std::move(admitted[i]);
+                e->left = C;
+                e->t_start = t_adm;
+                std::memcpy(hq.data() + (size_t)i * len, e->req.q.data(), (size_t)len * sizeof(float));
+                hk[i] = e->req.k;
+                rows[r] = std::move(e);
+                adm.push_back(r);
             }
-        ids.assign(fin.size() * kout, -1);
-        dists.assign(fin.size() * kout, 0.f);
-        try {
-            runner.admit(hq.data(), hk.data(), rid.data(), n);
-            runner.step(chunk, hi);
-            runner.finish(fin.data(), (int)fin.size());
-            runner.sync(ovf.data(), kout, ids.data(), dists.data(), status.data());
-        } catch (const Failure& f) {
-            // the table's state is unknown: every occupied row fails with the error
+            busy += n;
+            for (int r : adm) rows[r]->occupancy = busy;
+            Launched l;
+            int hi = 0;
             for (int r = 0; r < S; ++r)
-                if (rows[r].busy) {
-                    core.publish(rows[r].req, f.code, f.msg, rows[r].occupancy, rows[r].t_start, nullptr, nullptr);
-                    release(r);
+                if (rows[r]) hi = r + 1;
+            l.held.assign(rows.begin(), rows.begin() + hi);
+            fin.clear();
+            for (int r = 0; r < hi; ++r)
+                if (rows[r] && --rows[r]->left == 0) {
+                    fin.push_back(r);
+                    l.kout = std::max(l.kout, rows[r]->req.k);
+                    l.fin.push_back(std::move(rows[r]));
+                    --busy;
                 }
-            continue;
-        }
-        for (int r = 0; r < hi; ++r)
-            if (rows[r].busy) {
-                rows[r].ovf |= ovf[r] != 0;
-                --rows[r].left;
+            try {
+                runner.launch(hq.data(), hk.data(), adm.data(), n, chunk, hi, fin.data(), (int)fin.size());
+            } catch (const Failure& f) {
+                for (EntryP& e : l.fin) core.publish(e->req, f.code, f.msg, e->occupancy, e->t_start, nullptr, nullptr);
+                fail_all(f);
+                continue;
             }
-        for (size_t j = 0; j < fin.size(); ++j) {
-            Row& row = rows[fin[j]];
-            if (status[j] != 0 || row.ovf) {
-                std::string err;
-                int rc = ISAX_EDEVICE;
-                try {
-                    rc = runner.run_alone(row.req.q.data(), row.req.k, one_ids.data(), one_d.data(), err);
-                } catch (const Failure& f) {
-                    rc = f.code;
-                    err = f.msg;
-                }
-                core.publish(row.req, rc, err, row.occupancy, row.t_start, one_ids.data(), one_d.data());
-            } else {
-                core.publish(row.req, ISAX_OK, "", row.occupancy, row.t_start, ids.data() + j * kout,
-                             dists.data() + j * kout);
-            }
-            release(fin[j]);
+            flight.push_back(std::move(l));
+            chunk = (chunk + 1) % C;
+            if (flight.size() < 2) continue;
         }
-        chunk = (chunk + 1) % C;
+        try {
+            collect();
+        } catch (const Failure& f) {
+            fail_all(f);
+        }
     }
 }
 

@@ -75,12 +75,17 @@ struct StepRunner {
     virtual int slots() const = 0;
     virtual int chunks() const = 0;  // steps per sweep
     virtual int len() const = 0;
-    virtual void admit(const float* q, const int32_t* k, const int* rows, int n) = 0;
-    virtual void step(int chunk, int hi) = 0;
-    virtual void finish(const int* rows, int n) = 0;
-    // Waits for the queued work: ovf [hi] of the last step, the answers [n][kout]
-    // and status of the last finish (status != 0: answer that row alone).
-    virtual void sync(int* ovf, int kout, int64_t* ids, float* dists, int* status) = 0;
+    // Queues one step (at most two are queued and not yet collected): queries
+    // q [n_adm][len] with k into the free rows adm[], chunk `chunk` of the sweep
+    // for the occupied rows among [0, hi), then the final ordering of rows
+    // fin[] (they are free for the next step).
+    virtual void launch(const float* q, const int32_t* k, const int* adm, int n_adm, int chunk, int hi,
+                        const int* fin, int n_fin) = 0;
+    // Waits for the oldest queued step: ovf [its hi], the answers [n_fin][kout]
+    // and status of its final ordering (status != 0: answer that row alone).
+    virtual void collect(int* ovf, int kout, int64_t* ids, float* dists, int* status) = 0;
+    // After a failure: nothing queued, every row free.
+    virtual void reset() = 0;
     // One query answered by itself (rows that lost candidates).
     virtual int run_alone(const float* q, int k, int64_t* ids, float* dists, std::string& err) = 0;
 };

@@ -14,6 +14,7 @@
 #include <atomic>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <random>
 #include <thread>
@@ -39,25 +40,27 @@ struct StubStep : StepRunner {
     std::vector<std::vector<float>> q;
     std::vector<int> k, busy;
     std::vector<std::vector<int>> seen;
-    std::vector<int> ovf_now, fin_rows, fin_status;
+    struct Out {  // what a queued step hands back
+        std::vector<int> ovf, status, fin_k;
+        std::vector<int64_t> base;
+    };
+    std::deque<Out> queued;
     std::mt19937 rng;
     int fail_every, calls = 0;
     StubStep(int slots, int chunks, int len, int seed, int fail_every_)
-        : S(slots), C(chunks), L(len), q(slots), k(slots, 0), busy(slots, 0), seen(slots),
-          ovf_now(slots, 0), rng(seed), fail_every(fail_every_) {}
+        : S(slots), C(chunks), L(len), q(slots), k(slots, 0), busy(slots, 0), seen(slots), rng(seed),
+          fail_every(fail_every_) {}
     int slots() const override { return S; }
     int chunks() const override { return C; }
     int len() const override { return L; }
-    void maybe_fail() {
-        if (fail_every && ++calls % fail_every == 0) {
-            // the engine publishes the error for every occupied row and frees them all
-            std::fill(busy.begin(), busy.end(), 0);
-            throw Failure{ISAX_EDEVICE, "injected device failure"};
-        }
-    }
-    void admit(const float* hq, const int32_t* hk, const int* rows, int n) override {
-        for (int i = 0; i < n; ++i) {
-            const int r = rows[i];
+    void launch(const float* hq, const int32_t* hk, const int* adm, int n_adm, int chunk, int hi, const int* fin,
+                int n_fin) override {
+        CHECK(queued.size() < 2);
+        if (fail_every && ++calls % fail_every == 0) throw Failure{ISAX_EDEVICE, "injected device failure"};
+        // in device order: admissions, the sweep of the chunk, the final ordering
+        Out o;
+        for (int i = 0; i < n_adm; ++i) {
+            const int r = adm[i];
             CHECK(r >= 0 && r < S);
             CHECK(!busy[r]);
             busy[r] = 1;
@@ -65,43 +68,44 @@ struct StubStep : StepRunner {
             k[r] = hk[i];
             seen[r].assign(C, 0);
         }
-        maybe_fail();
-    }
-    void step(int chunk, int hi) override {
         CHECK(chunk >= 0 && chunk < C);
+        o.ovf.assign(hi, 0);
         for (int r = 0; r < S; ++r) {
             CHECK(r < hi || !busy[r]);
-            ovf_now[r] = 0;
             if (r < hi && busy[r]) {
                 ++seen[r][chunk];
-                ovf_now[r] = std::uniform_int_distribution<int>(0, 199)(rng) == 0;
+                o.ovf[r] = std::uniform_int_distribution<int>(0, 199)(rng) == 0;
             }
         }
-        maybe_fail();
-    }
-    void finish(const int* rows, int n) override {
-        fin_rows.assign(rows, rows + n);
-        fin_status.assign(n, 0);
-        for (int i = 0; i < n; ++i) {
-            const int r = rows[i];
-            CHECK(busy[r]);
+        for (int i = 0; i < n_fin; ++i) {
+            const int r = fin[i];
+            CHECK(r >= 0 && r < hi && busy[r]);
             for (int c = 0; c < C; ++c) CHECK(seen[r][c] == 1);
-            fin_status[i] = std::uniform_int_distribution<int>(0, 99)(rng) == 0 ? 3 : 0;
-        }
-    }
-    void sync(int* ovf, int kout, int64_t* ids, float* dists, int* status) override {
-        for (int r = 0; r < S; ++r) ovf[r] = ovf_now[r];
-        for (size_t i = 0; i < fin_rows.size(); ++i) {
-            const int r = fin_rows[i];
-            CHECK(k[r] <= kout);
-            for (int j = 0; j < k[r]; ++j) {
-                ids[i * kout + j] = base_of(q[r].data()) + j;
-                dists[i * kout + j] = (float)j;
-            }
-            status[i] = fin_status[i];
+            o.status.push_back(std::uniform_int_distribution<int>(0, 99)(rng) == 0 ? 3 : 0);
+            o.fin_k.push_back(k[r]);
+            o.base.push_back(base_of(q[r].data()));
             busy[r] = 0;
         }
-        fin_rows.clear();
+        queued.push_back(std::move(o));
+    }
+    void collect(int* ovf, int kout, int64_t* ids, float* dists, int* status) override {
+        CHECK(!queued.empty());
+        if (queued.empty()) return;
+        Out o = std::move(queued.front());
+        queued.pop_front();
+        std::copy(o.ovf.begin(), o.ovf.end(), ovf);
+        for (size_t i = 0; i < o.status.size(); ++i) {
+            CHECK(o.fin_k[i] <= kout);
+            for (int j = 0; j < o.fin_k[i]; ++j) {
+                ids[i * kout + j] = o.base[i] + j;
+                dists[i * kout + j] = (float)j;
+            }
+            status[i] = o.status[i];
+        }
+    }
+    void reset() override {
+        queued.clear();
+        std::fill(busy.begin(), busy.end(), 0);
     }
     int run_alone(const float* hq, int kk, int64_t* ids, float* dists, std::string&) override {
         for (int j = 0; j < kk; ++j) {

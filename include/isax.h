@@ -66,8 +66,11 @@ enum {
     ISAX_QF_NO_EARLY_ABANDON = 2, /* refine every surviving series to the end */
     ISAX_QF_NO_BEST_FIRST = 4,    /* index mode: visit leaves in layout order in one pass, instead of the
                                      leaves of smallest lower bound first (MESSI's priority order, Sec. III) */
-    ISAX_QF_NO_SHORTCUT = 8       /* hybrid mode: price every query with the cost model even when the whole
+    ISAX_QF_NO_SHORTCUT = 8,      /* hybrid mode: price every query with the cost model even when the whole
                                      batch is cheap enough for the filter alone */
+    ISAX_QF_FILTER_CHEAP = 16,    /* hybrid mode: price the filter at 1/1000 of its model, or */
+    ISAX_QF_FILTER_DEAR = 32      /* at 1000 times it, so that small collections exercise each of the
+                                     planner's routes (testing) */
 };
 
 /* Distance measures (isax_query_options.metric). */

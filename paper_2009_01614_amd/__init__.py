@@ -25,7 +25,7 @@ MODES = {"index": MODE_INDEX, "scan": MODE_SCAN, "bf16": MODE_BF16, "fp8": MODE_
 METRIC_ED, METRIC_DTW = 0, 1
 METRICS = {"ed": METRIC_ED, "dtw": METRIC_DTW}
 MAX_WINDOW = 31
-QF_NO_SHARING, QF_NO_EARLY_ABANDON, QF_NO_BEST_FIRST, QF_NO_SHORTCUT = 1, 2, 4, 8
+QF_NO_SHARING, QF_NO_EARLY_ABANDON, QF_NO_BEST_FIRST, QF_NO_SHORTCUT, QF_FILTER_CHEAP, QF_FILTER_DEAR = 1, 2, 4, 8, 16, 32
 SERVE_BATCHES = 1
 MAX_K = 1024
 

@@ -845,12 +845,14 @@ __global__ void k_note_overflow(unsigned* __restrict__ fcount, int fcap, int mq,
 // Per-query state between two batches (a serving table and an admission or
 // final-ordering batch), one block per row.
 __global__ void __launch_bounds__(256) k_copy_rows(QueryArgs sa, FilterArgs sf, QueryArgs da, FilterArgs df,
-                                                   const int2* __restrict__ map, int free_src, int len_pad,
-                                                   int code_bytes) {
+                                                   const int2* __restrict__ map, int free_src, int rows_too,
+                                                   int len_pad, int code_bytes) {
     const int i = blockIdx.x;
     const int s = map[i].x, d = map[i].y;
     const int t = threadIdx.x;
-    for (int j = t; j < sa.len; j += 256) const_cast<float*>(da.Q)[(int64_t)d * da.len + j] = sa.Q[(int64_t)s * sa.len + j];
+    if (rows_too)
+        for (int j = t; j < sa.len; j += 256)
+            const_cast<float*>(da.Q)[(int64_t)d * da.len + j] = sa.Q[(int64_t)s * sa.len + j];
     const unsigned cnt = min(sa.cand_count[s], (unsigned)sa.cap);
     for (unsigned j = t; j < min(cnt, (unsigned)da.cap); j += 256) da.cand[(int64_t)d * da.cap + j] = sa.cand[(int64_t)s * sa.cap + j];
     for (int j = t; j < da.kmax; j += 256)
@@ -862,7 +864,8 @@ __global__ void __launch_bounds__(256) k_copy_rows(QueryArgs sa, FilterArgs sf, 
         for (int j = t; j < len_pad * code_bytes; j += 256) dst[j] = src[j];
     }
     if (t == 0) {
-        const_cast<int32_t*>(da.kq)[d] = sa.kq[s];
+        if (rows_too) const_cast<int32_t*>(da.kq)[d] = sa.kq[s];
+        da.qkey[d] = sa.qkey[s];
         da.qinfo[d] = sa.qinfo[s];
         da.tau0[d] = sa.tau0[s];
         // candidates past the destination's capacity are reported as an overflow by its top-k
@@ -1002,10 +1005,11 @@ void launch_note_overflow(const QueryArgs& a, const FilterArgs& f, int* ovf, hip
 }
 
 void launch_copy_rows(const QueryArgs& sa, const FilterArgs& sf, const QueryArgs& da, const FilterArgs& df,
-                      const int2* map, int n, bool free_src, hipStream_t s) {
+                      const int2* map, int n, bool free_src, hipStream_t s, bool rows_too) {
     if (n <= 0) return;
-    ProfScope ps("serve_copy_rows", s);
-    k_copy_rows<<<n, 256, 0, s>>>(sa, sf, da, df, map, free_src ? 1 : 0, filter_len_pad(sa.len), sf.kind == 0 ? 2 : 1);
+    ProfScope ps("copy_rows", s);
+    k_copy_rows<<<n, 256, 0, s>>>(sa, sf, da, df, map, free_src ? 1 : 0, rows_too ? 1 : 0, filter_len_pad(sa.len),
+                                  sf.kind == 0 ? 2 : 1);
     ISAX_HIP(hipGetLastError());
 }
 

@@ -39,6 +39,7 @@ struct QueryArgs {
     int skip_done;    // 1: rows whose done flag is set take no part in the filter and its refinement
                       //    (the free slots of a serving table)
     int home_leaves;  // leaves the approximate answer covers at least (0: the default, 4)
+    int leaf_stride;  // leaf pass: every leaf_stride-th block of leaves only (0 or 1: every leaf)
     float* paa;       // [mq][w]
     uint8_t* sym;     // [mq][ws]
     uint64_t* qkey;   // [mq]
@@ -93,6 +94,9 @@ void launch_qprep(const QueryArgs& a, hipStream_t s);
 void launch_homeleaf(const QueryArgs& a, hipStream_t s);
 void launch_index_scan(const QueryArgs& a, hipStream_t s);
 void launch_leaf_order(const QueryArgs& a, hipStream_t s);  // histogram of leaf bounds -> theta
+// dst.tau0[map[i].y] = min(itself, the k-th best of src row map[i].x): a bound
+// found by one batch handed to the rows of another.
+void launch_carry_bound(const QueryArgs& src, const QueryArgs& dst, const int2* map, int n, hipStream_t s);
 // list_rest[q] = list entries at or above theta still within the best-so-far
 // (queries not done, whose list holds every leaf within the first bound).
 void launch_list_recount(const QueryArgs& a, int64_t grid_x, hipStream_t s);
@@ -152,12 +156,13 @@ void launch_filter(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax
 void launch_refine_filtered(const QueryArgs& a, const FilterArgs& f, hipStream_t s);
 // Serving tables: ovf[q] = fcount[q] > fcap, then fcount[q] = 0, for q < a.mq.
 void launch_note_overflow(const QueryArgs& a, const FilterArgs& f, int* ovf, hipStream_t s);
-// Per-query state of rows map[i].x of (sa, sf) into rows map[i].y of (da, df): query row, k,
-// norms, bounds, best-k list, candidate list, approximate-answer range, statistics, status,
-// the filter's query codes and factors.  done of the destination row is set to 0 and, when
-// free_src, that of the source row to 1.
+// Per-query state of rows map[i].x of (sa, sf) into rows map[i].y of (da, df): key, norms,
+// bounds, best-k list, candidate list, approximate-answer range, statistics, status, the
+// filter's query codes and factors (where both have them), and with rows_too the query row
+// and k.  done of the destination row is set to 0 and, when free_src, that of the source
+// row to 1.
 void launch_copy_rows(const QueryArgs& sa, const FilterArgs& sf, const QueryArgs& da, const FilterArgs& df,
-                      const int2* map, int n, bool free_src, hipStream_t s);
+                      const int2* map, int n, bool free_src, hipStream_t s, bool rows_too = true);
 void launch_filter_tighten(const QueryArgs& a, const FilterArgs& f, hipStream_t s);
 
 }  // namespace isax

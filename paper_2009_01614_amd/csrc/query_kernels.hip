@@ -754,7 +754,11 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
     const int nq = min(QB, a.mq - q0);
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const int64_t base_leaf = (int64_t)blockIdx.x * 256 * R;
+    // nodes of 64 leaves: node nd of this block (nd = 4 r + wave) is node (16 blockIdx.x + nd) * stride;
+    // with stride 1 the block takes 1024 consecutive leaves, with a larger one an even sample of nodes
+    const int64_t stride = a.leaf_stride > 1 ? a.leaf_stride : 1;
+    const int64_t base_leaf = (int64_t)blockIdx.x * 256 * R;  // (stride 1: the first leaf of the block)
+    auto node_of = [&](int nd) -> int64_t { return ((int64_t)blockIdx.x * 4 * R + nd) * stride; };
     for (int i = 0; i < nq; ++i) {
         const int q = q0 + i;
         for (int s = threadIdx.x; s < a.ns; s += 256) {
@@ -769,7 +773,8 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
     }
     if (threadIdx.x < nq) {
         const int q = q0 + threadIdx.x;
-        s_thr[threadIdx.x] = read_tau(a, q, a.kq[q]) * a.tau_scale;
+        // a query set aside (skip_done) keeps no node and no leaf
+        s_thr[threadIdx.x] = a.skip_done && a.done[q] ? -1.f : read_tau(a, q, a.kq[q]) * a.tau_scale;
         s_home[threadIdx.x][0] = a.home[2 * q];
         s_home[threadIdx.x][1] = a.home[2 * q + 1];
         s_valid[threadIdx.x] = 0u;
@@ -779,7 +784,7 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
     // node bounds, one (query, node) pair per thread
     if (threadIdx.x < QB * 4 * R) {
         const int i = threadIdx.x / (4 * R), nd = threadIdx.x % (4 * R);
-        const int64_t node = base_leaf / kNodeLeaves + nd;
+        const int64_t node = node_of(nd);
         bool in = false;
         if (i < nq && node < a.n_nodes)
             in = env_bound(a, a.node_lo + node * a.ws, a.node_hi + node * a.ws, pu[i], pl[i], lo_e[i], hi_e[i]) *
@@ -793,7 +798,7 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
     int slot[QB][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int64_t leaf = base_leaf + r * 256 + threadIdx.x;
+        const int64_t leaf = node_of(r * 4 + (threadIdx.x >> 6)) * kNodeLeaves + lane;
         uint4 vl = make_uint4(0u, 0u, 0u, 0u), vh = vl;
         if constexpr (W16) {
             bool any_in = false;  // the same in every lane of the wave
@@ -849,7 +854,8 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
             const int64_t p = (int64_t)s_base[i] + slot[i][r];
             if (p < a.leaf_cap)
                 a.leaf_list[(int64_t)(q0 + i) * a.leaf_cap + p] =
-                    make_uint2((unsigned)(base_leaf + r * 256 + threadIdx.x), __float_as_uint(lbs[i][r]));
+                    make_uint2((unsigned)(node_of(r * 4 + (threadIdx.x >> 6)) * kNodeLeaves + lane),
+                               __float_as_uint(lbs[i][r]));
         }
     }
     for (int i = 0; i < nq; ++i) {
@@ -1604,11 +1610,24 @@ void launch_list_recount(const QueryArgs& a, int64_t grid_x, hipStream_t s) {
     ISAX_HIP(hipGetLastError());
 }
 
+__global__ void k_carry_bound(QueryArgs src, QueryArgs dst, const int2* __restrict__ map, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int s = map[i].x, d = map[i].y;
+    dst.tau0[d] = fminf(dst.tau0[d], read_tau(src, s, src.kq[s]));
+}
+
+void launch_carry_bound(const QueryArgs& src, const QueryArgs& dst, const int2* map, int n, hipStream_t s) {
+    if (n <= 0) return;
+    k_carry_bound<<<(n + 255) / 256, 256, 0, s>>>(src, dst, map, n);
+    ISAX_HIP(hipGetLastError());
+}
+
 void launch_leaf_order(const QueryArgs& a, hipStream_t s) {
     ProfScope ps("leaf_order", s);
     ISAX_HIP(hipMemsetAsync(a.leaf_hist, 0, (size_t)a.mq * kLeafBins * sizeof(unsigned), s));
     ISAX_HIP(hipMemsetAsync(a.leaf_count, 0, (size_t)a.mq * sizeof(unsigned), s));
-    const int64_t per_block = 256 * kHistLeafRounds;
+    const int64_t per_block = 256 * kHistLeafRounds * std::max(1, a.leaf_stride);
     const dim3 grid((unsigned)((a.n_leaves + per_block - 1) / per_block),
                     (unsigned)((a.mq + kHistQueries - 1) / kHistQueries));
     if (a.w == 16 && a.ws == 16) k_leaf_hist<true><<<grid, 256, 0, s>>>(a);

@@ -501,6 +501,13 @@ struct Batch {
     std::vector<int> skip;
     std::unique_ptr<Batch> sub;
     DevBuf sub_mem;
+    // the per-query state holds an approximate answer already (qprep and the
+    // approximate answer are not run again)
+    bool prepared = false;
+    const int32_t* kq_host = nullptr;  // k per query (host), where the caller knows it
+    // hybrid batches: leaves within the first bound per query, -1 where the
+    // leaf pass did not run (used by the statistics instead of leaf_count)
+    std::vector<int64_t> li;
 };
 
 // Slack of comparisons with a DTW best-so-far: the FP32 recurrence sums at
@@ -626,7 +633,7 @@ void fill_stats(const Batch& b, isax_query_stats* out, hipStream_t s) {
     ISAX_HIP(hipMemcpyAsync(st.data(), b.a.stats, st.size() * 8, hipMemcpyDeviceToHost, s));
     ISAX_HIP(hipMemcpyAsync(qi.data(), b.a.qinfo, qi.size() * sizeof(float4), hipMemcpyDeviceToHost, s));
     ISAX_HIP(hipStreamSynchronize(s));
-    const std::vector<int64_t> li = b.hist_valid ? leaves_initial(b, s) : std::vector<int64_t>(mq, -1);
+    const std::vector<int64_t> li = !b.li.empty() ? b.li : b.hist_valid ? leaves_initial(b, s) : std::vector<int64_t>(mq, -1);
     for (int i = 0; i < mq; ++i) {
         const unsigned long long* r = &st[(size_t)i * ST_N];
         out[i].leaves_scanned = (int64_t)r[ST_LEAVES];
@@ -739,12 +746,24 @@ constexpr double kFilterPerQuery = 10e-6;
 // about 1.5 ms per call at 10M x 256; a batch the filter answers in less than
 // kHybridFixed takes the BF16 path at once.
 constexpr double kHybridFixed = 3e-3;
+// Index work per leaf grows with k beyond the words and refinement the model
+// counts (longer best-k lists, wider windows): measured about 1.7x at k = 10.
+inline double k_prior(int k) { return 1.0 + 0.7 * std::log10((double)std::max(k, 1)); }
+// The pre-screen bounds every kPreStride-th node (64 leaves) of the leaf pass.
+constexpr int kPreStride = 16;
+// Near queries measured at 1.7-2x their optimistic pre-screen price (100M x 256,
+// sigma 0.01 and 0.1, k = 1 and 10): the pre-screen scales it by this much.
+constexpr double kPreFactor = 1.5;
 
 // The planner: `fixed` queries go to the filter; of the others, the j of
 // largest cost join them, j minimising filter_cost(all of them) + the cost of
 // the queries left on the iSAX path.  Returns the filter's set.
 double filter_cost(const isax_index* idx, int f);
-std::vector<char> plan_far(const isax_index* idx, const std::vector<double>& cost, const std::vector<char>& fixed) {
+// Keeping any query on the index path also costs its own passes and
+// synchronisations (leaf pass, rounds, the second plan): about this much.
+constexpr double kIndexFixed = 1.5e-3;
+std::vector<char> plan_far(const isax_index* idx, const std::vector<double>& cost, const std::vector<char>& fixed,
+                           double fscale = 1.0) {
     const int mq = (int)cost.size();
     std::vector<int> order;
     int n0 = 0;
@@ -758,11 +777,12 @@ std::vector<char> plan_far(const isax_index* idx, const std::vector<double>& cos
         }
     }
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
-    double best = filter_cost(idx, n0) + rest;
+    const int n = (int)order.size();
+    double best = fscale * filter_cost(idx, n0) + rest + (n > 0 ? kIndexFixed : 0.0);
     int bj = 0;
-    for (int j = 1; j <= (int)order.size(); ++j) {
+    for (int j = 1; j <= n; ++j) {
         rest -= cost[order[j - 1]];
-        const double c = filter_cost(idx, n0 + j) + rest;
+        const double c = fscale * filter_cost(idx, n0 + j) + rest + (j < n ? kIndexFixed : 0.0);
         if (c < best) {
             best = c;
             bj = j;
@@ -809,46 +829,108 @@ Arena sub_arena(int32_t** pos, float** Qf, int32_t** kqf, int64_t** oid, float**
 void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     QueryArgs& a = b.a;
     const int mq = a.mq;
-    if (limit == 0 && !(a.flags & ISAX_QF_NO_SHORTCUT) && filter_cost(idx, mq) < kHybridFixed) {
+    const double fscale = (a.flags & ISAX_QF_FILTER_CHEAP) ? 1e-3 : (a.flags & ISAX_QF_FILTER_DEAR) ? 1e3 : 1.0;
+    if (limit == 0 && !(a.flags & ISAX_QF_NO_SHORTCUT) && fscale * filter_cost(idx, mq) < kHybridFixed) {
         run_batch(idx, b, ISAX_MODE_BF16, s);
         return;
     }
     launch_qprep(a, s);
     launch_homeleaf(a, s);
-    leaf_pass(b, kLeafListMax, s);
-    const std::vector<int64_t> cnt = leaves_initial(b, s);
     const bool best_first = !(a.flags & ISAX_QF_NO_BEST_FIRST);
+    const double leaf_words = (double)a.leaf_size * a.ws / kIdxBps;
+    const double leaf_refine = (double)a.leaf_size * a.len * 4.0 / kIdxBps;
+    std::vector<double> cost(mq), kp(mq);
+    for (int q = 0; q < mq; ++q) kp[q] = k_prior(b.kq_host ? b.kq_host[q] : a.kmax);
+    std::vector<char> pre(mq, 0);  // sent to the filter before the leaf pass
+    std::vector<int> flags_a(mq), flags_b(mq);  // done flags of the launches below (kept alive until a sync)
+    if (limit == 0 && best_first) {
+        // Pre-screen on a sample of the leaves (every kPreStride-th node of 64
+        // leaves, no lists): each query's count within its first bound,
+        // scaled up, priced optimistically (its first kFirstLeaves leaves at
+        // kFarShare, the others at kNearShare).  Queries too dear for the index
+        // even then go to the filter without the full leaf pass.
+        a.leaf_stride = kPreStride;
+        a.leaf_cap = 0;
+        launch_leaf_order(a, s);
+        a.leaf_stride = 1;
+        int64_t sampled = 0;
+        for (int64_t nd = 0; nd * kNodeLeaves < a.n_leaves; nd += kPreStride)
+            sampled += std::min<int64_t>(kNodeLeaves, a.n_leaves - nd * kNodeLeaves);
+        const double scale = (double)a.n_leaves / (double)std::max<int64_t>(sampled, 1);
+        std::vector<unsigned> c(mq);
+        ISAX_HIP(hipMemcpyAsync(c.data(), a.leaf_count, mq * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+        ISAX_HIP(hipStreamSynchronize(s));
+        for (int q = 0; q < mq; ++q) {
+            const double est = c[q] * scale, n1 = std::min<double>(est, kFirstLeaves);
+            cost[q] = kPreFactor * kp[q] *
+                      ((leaf_words + kFarShare * leaf_refine) * n1 + (leaf_words + kNearShare * leaf_refine) * (est - n1));
+        }
+        pre = plan_far(idx, cost, pre, fscale);
+        double total = 0.0;
+        int n_pre = 0;
+        for (int q = 0; q < mq; ++q) {
+            n_pre += pre[q];
+            total += pre[q] ? 0.0 : cost[q];
+        }
+        if (n_pre == mq) {
+            // every query to the filter: the batch itself runs the BF16 path from its approximate answer
+            b.li.assign(mq, -1);
+            b.prepared = true;
+            run_batch(idx, b, ISAX_MODE_BF16, s);
+            return;
+        }
+        if (n_pre == 0 && total < 0.5 * fscale * filter_cost(idx, mq)) {
+            // the index is far cheaper than any filter pass: the plain index path
+            leaf_pass(b, kLeafListMax, s);
+            const std::vector<int64_t> cnt = leaves_initial(b, s);
+            b.li = cnt;
+            index_rounds(idx, b, s, cnt, {});
+            finish_batch(idx, b, ISAX_MODE_INDEX, s);
+            return;
+        }
+    }
+    // the approximate answer of every query (the leaf pass changes no per-query
+    // state), kept for the filter's sub-batch: its rows take it instead of
+    // computing it again
+    Batch shadow;
+    setup_batch(shadow, idx, a.Q, mq, a.kq, a.kmax, a.cap, a.flags, nullptr, nullptr, s);
+    DevBuf maps((size_t)mq * 2 * sizeof(int2), s);
+    int2* ident = maps.as<int2>();
+    int2* fmap = ident + mq;
+    // host sources of the copies below stay alive until the batch's last sync
+    std::vector<int2> id(mq), fm;
+    for (int q = 0; q < mq; ++q) id[q] = make_int2(q, q);
+    ISAX_HIP(hipMemcpyAsync(ident, id.data(), mq * sizeof(int2), hipMemcpyHostToDevice, s));
+    {
+        const FilterArgs none{};
+        launch_copy_rows(a, none, shadow.a, none, ident, mq, false, s, false);
+    }
+    // the leaf pass for the queries that stay (done = 1 sets a query aside)
+    for (int q = 0; q < mq; ++q) flags_a[q] = pre[q];
+    ISAX_HIP(hipMemcpyAsync(a.done, flags_a.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
+    a.skip_done = 1;
+    leaf_pass(b, kLeafListMax, s);
+    a.skip_done = 0;
+    std::vector<int64_t> cnt = leaves_initial(b, s);
+    b.li = cnt;
+    for (int q = 0; q < mq; ++q)
+        if (pre[q]) b.li[q] = -1;
     std::vector<char> listed(mq);
     for (int q = 0; q < mq; ++q) listed[q] = best_first && cnt[q] <= a.leaf_cap;
     std::vector<int64_t> est = cnt;
-    std::vector<int> flags_a(mq), flags_b(mq);  // done flags of the launches below (kept alive until the sync)
-    // iSAX cost per remaining leaf: the words of its series, and the refinement
-    // of a share of them
-    const double leaf_words = (double)a.leaf_size * a.ws / kIdxBps;
-    const double leaf_refine = (double)a.leaf_size * a.len * 4.0 / kIdxBps;
-    std::vector<double> cost(mq);
-    std::vector<char> pre(mq, 0);  // sent to the filter before round 1
-    if (limit == 0) {
-        // queries too dear for the index even at the small refinement share of
-        // a near query after round 1 skip round 1; round 1 itself (the leaves
-        // of the histogram's bins up to theta) is priced at kFarShare
-        std::vector<unsigned> h((size_t)mq * kLeafBins);
-        ISAX_HIP(hipMemcpyAsync(h.data(), a.leaf_hist, h.size() * 4, hipMemcpyDeviceToHost, s));
-        ISAX_HIP(hipStreamSynchronize(s));
-        for (int q = 0; q < mq; ++q) {
-            int64_t n1 = 0;
-            for (int j = 0; j < kLeafBins && n1 < kFirstLeaves; ++j) n1 += h[(size_t)q * kLeafBins + j];
-            n1 = std::min(n1, cnt[q]);
-            cost[q] = (leaf_words + kFarShare * leaf_refine) * (double)n1 +
-                      (leaf_words + kNearShare * leaf_refine) * (double)(cnt[q] - n1);
-        }
-        pre = plan_far(idx, cost, pre);
-    }
     int64_t g1 = 0;
     for (int q = 0; q < mq; ++q) {
         flags_a[q] = !listed[q] || pre[q];
         if (!flags_a[q]) g1 = std::max(g1, (cnt[q] + 255) / 256);
     }
+    if (limit == 0)
+        for (int q = 0; q < mq; ++q)
+            if (!pre[q]) {
+                // not listed: priced from its count at the far share until it is known better
+                const int64_t n1 = std::min<int64_t>(cnt[q], kFirstLeaves);
+                cost[q] = kp[q] * ((leaf_words + kFarShare * leaf_refine) * (double)n1 +
+                                   (leaf_words + kNearShare * leaf_refine) * (double)(cnt[q] - n1));
+            }
     if (g1 > 0) {
         // round 1 over the lists
         ISAX_HIP(hipMemcpyAsync(a.done, flags_a.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
@@ -866,24 +948,28 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
                 est[q] = r[q];
                 const unsigned long long* sq = &st[(size_t)q * ST_N];
                 const double share = (double)sq[ST_REFINED] / (double)std::max<unsigned long long>(sq[ST_SERIES_LB], 1);
-                cost[q] = (leaf_words + std::min(1.0, share) * leaf_refine) * (double)est[q];
+                cost[q] = kp[q] * (leaf_words + std::min(1.0, share) * leaf_refine) * (double)est[q];
             }
     }
     b.skip.assign(mq, 0);
     if (limit > 0) {
         for (int q = 0; q < mq; ++q) b.skip[q] = est[q] > limit;
     } else {
-        const std::vector<char> far = plan_far(idx, cost, pre);
+        const std::vector<char> far = plan_far(idx, cost, pre, fscale);
         for (int q = 0; q < mq; ++q) b.skip[q] = far[q];
     }
     for (int q = 0; q < mq; ++q)
         if (b.skip[q]) b.far.push_back(q);
     const int mf = (int)b.far.size();
     if (mf == mq) {
-        // every query to the filter: the batch itself runs the BF16 path (qprep
-        // resets its per-query state; the leaf counts stay for the statistics)
+        // every query to the filter: the batch itself runs the BF16 path from its
+        // approximate answer (round 1's results dropped, its bound kept)
         b.far.clear();
         b.skip.clear();
+        const FilterArgs none{};
+        launch_carry_bound(a, shadow.a, ident, mq, s);  // round 1's bound, before the state is restored
+        launch_copy_rows(shadow.a, none, a, none, ident, mq, false, s, false);
+        b.prepared = true;
         run_batch(idx, b, ISAX_MODE_BF16, s);
         return;
     }
@@ -891,49 +977,53 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     int64_t* oid = nullptr;
     float* od = nullptr;
     if (mf > 0) {
+        // the filter's sub-batch: the rows' approximate answers, with the bound the
+        // index path has found for them since
         float* Qf = nullptr;
         int32_t* kqf = nullptr;
         b.sub_mem = sub_arena(&pos, &Qf, &kqf, &oid, &od, mf, a.len, a.kmax).commit(s);
+        fm.resize(mf);
+        for (int i = 0; i < mf; ++i) fm[i] = make_int2(b.far[i], i);
         ISAX_HIP(hipMemcpyAsync(pos, b.far.data(), mf * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        launch_gather_queries(a.Q, a.kq, pos, mf, a.len, Qf, kqf, s);
+        ISAX_HIP(hipMemcpyAsync(fmap, fm.data(), mf * sizeof(int2), hipMemcpyHostToDevice, s));
         b.sub.reset(new Batch);
         setup_batch(*b.sub, idx, Qf, mf, kqf, a.kmax, a.cap, a.flags, oid, od, s);
         b.sub->fcap0 = b.fcap0;
+        const FilterArgs none{};
+        launch_copy_rows(shadow.a, none, b.sub->a, none, fmap, mf, false, s, true);
+        launch_carry_bound(a, b.sub->a, fmap, mf, s);
+        b.sub->prepared = true;
     }
-    if (mf < mq) {
-        if (best_first) {
-            // round 2 over the lists of the listed queries that stay
-            int64_t g2 = 0, n_full = 0;
-            for (int q = 0; q < mq; ++q) {
-                flags_a[q] = b.skip[q] || !listed[q];
-                flags_b[q] = b.skip[q] || listed[q];
-                if (!flags_a[q]) g2 = std::max(g2, (cnt[q] + 255) / 256);
-                n_full += !flags_b[q];
-            }
-            if (g2 > 0) {
-                ISAX_HIP(hipMemcpyAsync(a.done, flags_a.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
-                a.grid_leaves = g2;
-                a.round = 2;
-                launch_index_scan(a, s);
-            }
-            if (n_full > 0) {
-                // both rounds over every leaf for the queries whose list did not fit
-                ISAX_HIP(hipMemcpyAsync(a.done, flags_b.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
-                a.grid_leaves = (a.n_leaves + 255) / 256;
-                a.round = 1;
-                launch_index_scan(a, s);
-                a.round = 2;
-                launch_index_scan(a, s);
-            }
-            if (profiling_on()) profile_add_bytes("index_scan", scan_bytes(b, idx, s, cnt, b.skip));
+    if (best_first) {
+        // round 2 over the lists of the listed queries that stay
+        int64_t g2 = 0, n_full = 0;
+        for (int q = 0; q < mq; ++q) {
+            flags_a[q] = b.skip[q] || !listed[q];
+            flags_b[q] = b.skip[q] || listed[q];
+            if (!flags_a[q]) g2 = std::max(g2, (cnt[q] + 255) / 256);
+            n_full += !flags_b[q];
         }
-        // the iSAX kernels and the final ordering pass over a query whose done flag is set
-        ISAX_HIP(hipMemcpyAsync(a.done, b.skip.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
-        if (!best_first) index_rounds(idx, b, s, cnt, b.skip);
-        finish_batch(idx, b, ISAX_MODE_INDEX, s);
-    } else {
-        ISAX_HIP(hipMemcpyAsync(a.done, b.skip.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
+        if (g2 > 0) {
+            ISAX_HIP(hipMemcpyAsync(a.done, flags_a.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
+            a.grid_leaves = g2;
+            a.round = 2;
+            launch_index_scan(a, s);
+        }
+        if (n_full > 0) {
+            // both rounds over every leaf for the queries whose list did not fit
+            ISAX_HIP(hipMemcpyAsync(a.done, flags_b.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
+            a.grid_leaves = (a.n_leaves + 255) / 256;
+            a.round = 1;
+            launch_index_scan(a, s);
+            a.round = 2;
+            launch_index_scan(a, s);
+        }
+        if (profiling_on()) profile_add_bytes("index_scan", scan_bytes(b, idx, s, cnt, b.skip));
     }
+    // the iSAX kernels and the final ordering pass over a query whose done flag is set
+    ISAX_HIP(hipMemcpyAsync(a.done, b.skip.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
+    if (!best_first) index_rounds(idx, b, s, cnt, b.skip);
+    finish_batch(idx, b, ISAX_MODE_INDEX, s);
     if (mf > 0) {
         run_batch(idx, *b.sub, ISAX_MODE_BF16, s);
         launch_scatter_answers(oid, od, pos, mf, a.kmax, a.out_ids, a.out_dists, s);
@@ -947,7 +1037,7 @@ void run_batch(isax_index* idx, Batch& b, int mode, hipStream_t s, int64_t hybri
         run_hybrid_batch(idx, b, s, hybrid_limit);
         return;
     }
-    launch_qprep(a, s);
+    if (!b.prepared) launch_qprep(a, s);  // (prepared batches run the filter path, which clears the flag)
     const bool dtw = a.metric == ISAX_METRIC_DTW;
     if (dtw && mode == ISAX_MODE_SCAN) {
         // the plain scan under DTW: the home leaves seed the bound, then every
@@ -1047,7 +1137,7 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     ISAX_REQUIRE(o.hybrid_leaves >= 0, "hybrid_leaves must be >= 0");
     ISAX_REQUIRE(o.candidate_capacity >= 0 && o.batch >= 0, "candidate_capacity and batch must be >= 0");
     ISAX_REQUIRE((o.flags & ~(ISAX_QF_NO_SHARING | ISAX_QF_NO_EARLY_ABANDON | ISAX_QF_NO_BEST_FIRST |
-                              ISAX_QF_NO_SHORTCUT)) == 0,
+                              ISAX_QF_NO_SHORTCUT | ISAX_QF_FILTER_CHEAP | ISAX_QF_FILTER_DEAR)) == 0,
                  "unknown flag");
     ISAX_REQUIRE((o.mode != ISAX_MODE_BF16 && o.mode != ISAX_MODE_HYBRID) || idx->x_bf16,
                  "index was built without the BF16 copy");
@@ -1115,13 +1205,12 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     }
     DevBuf kdev;
     const int32_t* kq = o.k_per_query;
+    std::vector<int32_t> hk(m, k);  // k per query on the host too (the hybrid planner prices by k)
     if (kq) {
-        std::vector<int32_t> hk(m);
         ISAX_HIP(hipMemcpyAsync(hk.data(), kq, m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         ISAX_HIP(hipStreamSynchronize(s));
         for (int32_t v : hk) ISAX_REQUIRE(v >= 1 && v <= k, "k_per_query values must be in 1..k");
     } else {
-        std::vector<int32_t> hk(m, k);
         kdev = DevBuf(m * sizeof(int32_t), s);
         ISAX_HIP(hipMemcpyAsync(kdev.p, hk.data(), m * sizeof(int32_t), hipMemcpyHostToDevice, s));
         ISAX_HIP(hipStreamSynchronize(s));
@@ -1143,6 +1232,7 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
             setup_batch(b, idx, Q + q0 * idx->len, mq, kq + q0, k, cap, o.flags, st_ids + q0 * k,
                         st_dists + q0 * k, s, o.metric, o.window);
             b.fcap0 = (int)fcap;
+            b.kq_host = hk.data() + q0;
             run_batch(idx, b, o.mode, s, hybrid_limit);
             if (o.stats) fill_stats(b, st_host.data() + q0, s);
         }
@@ -1249,7 +1339,10 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     QueryArgs& a = b.a;
     FilterScratch fs;
     setup_filter(fs, idx, a, mode, b.fcap0 > 0 ? b.fcap0 : kFilterCap, s);
-    launch_homeleaf(a, s);
+    // a prepared batch holds its approximate answer for this first pass only: every
+    // re-run (overflowed lists) computes it again
+    if (!b.prepared) launch_homeleaf(a, s);
+    b.prepared = false;
     launch_quantise_queries(a, fs.f, fs.mq_pad, fs.qmax, s);
     const int64_t n_tiles = (idx->n + 31) / 32;
     std::vector<int> phases;

@@ -195,3 +195,22 @@ def test_hybrid_other_lengths_and_sorted_rows(isax, length, w):
             path = np.array([s["path"] for s in st])
             assert np.all(path[li <= limit] == isax.MODE_INDEX)
         idx.close()
+
+
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_hybrid_cost_model_routes(isax, coll, k):
+    # the planner's own routes at 100K series, without a limit and without the batch
+    # shortcut: its plain choice; the filter priced at 1000x (the plain index path after
+    # the sampled pre-screen) and at 1/1000 (the pre-screen sends the queries to the filter,
+    # which start from their approximate answers).  Every route gives the oracle's answer.
+    idx, Q, X = coll["idx"], coll["Q"], coll["X"]
+    ref_ids, ref_d2 = (coll["ids"], coll["d2"]) if k <= 10 else kr.knn_exact_c(_cpu(X), _cpu(Q), k)
+    ib, db = idx.query(Q, k=k, mode="bf16")
+    paths = {}
+    for extra in (0, isax.QF_FILTER_DEAR, isax.QF_FILTER_CHEAP):
+        ids, d, st = idx.query(Q, k=k, mode="hybrid", flags=isax.QF_NO_SHORTCUT | extra, stats=True)
+        _check(ids, d, ref_ids, ref_d2, k)
+        paths[extra] = {s["path"] for s in st}
+        assert torch.equal(ids, ib) and torch.equal(d.view(torch.int32), db.view(torch.int32))
+    assert paths[isax.QF_FILTER_DEAR] == {isax.MODE_INDEX}
+    assert paths[isax.QF_FILTER_CHEAP] == {isax.MODE_BF16}

@@ -562,7 +562,10 @@ def next_report(args, dev):
     queries, k = 1 and 10, index and plain-scan modes; DTW cells/s against the
     ALU bound.  Host-resident raw data: the same collection in pinned host
     memory (summaries, layout and the BF16 copy in HBM), 1000 queries, index and
-    BF16 modes.  Embeddings: n x 128 and n x 384 clustered vectors, 1000 queries.
+    BF16 modes.  Embeddings: n x 128 and n x 384 clustered vectors, 1000 queries;
+    16 segments with the standard-normal edges, and dim / 8 segments with the
+    collection's own (empirical) edges; then the same vectors at unit norm, dim / 8
+    segments, standard-normal against empirical edges (index mode).
     """
     import numpy as np
     import torch
@@ -657,7 +660,39 @@ def next_report(args, dev):
             assert torch.equal(ids, ref), f"embeddings {mode} disagrees"
             out["embeddings"][f"d{dim}_{mode}_k10_qps"] = round(1000 / dt, 1)
             log(f"embeddings d={dim} {mode}: {out['embeddings'][f'd{dim}_{mode}_k10_qps']} q/s")
+        _, _, st = ie.query(QE[:100].contiguous(), k=10, mode="index", stats=True)
+        out["embeddings"][f"d{dim}_w16_normal_refined_per_query"] = round(sum(x["series_refined"] for x in st) / 100)
         ie.close()
+        # dim / 8 segments with the collection's own region edges
+        w = dim // 8
+        ie = isax.Index(E, w, 8, precision=1, edges="empirical")
+        for mode in ("index", "hybrid"):
+            ie.query(QE[:64].contiguous(), k=10, mode=mode)
+            (ids, _), dt, _ = _timed_query(isax, ie, QE, k=10, mode=mode)
+            assert torch.equal(ids, ref), f"embeddings {mode} (w={w}, empirical edges) disagrees"
+            out["embeddings"][f"d{dim}_w{w}_empirical_{mode}_k10_qps"] = round(1000 / dt, 1)
+            log(f"embeddings d={dim} w={w} empirical {mode}: {round(1000 / dt, 1)} q/s")
+        _, _, st = ie.query(QE[:100].contiguous(), k=10, mode="index", stats=True)
+        out["embeddings"][f"d{dim}_w{w}_empirical_refined_per_query"] = round(
+            sum(x["series_refined"] for x in st) / 100)
+        ie.close()
+        # the same vectors scaled to unit norm (their segment means sit near 0, far narrower
+        # than N(0, 1)): dim / 8 segments, standard-normal against empirical edges
+        E /= E.norm(dim=1, keepdim=True)
+        QE /= QE.norm(dim=1, keepdim=True)
+        ref = None
+        for edges in ("normal", "empirical"):
+            ie = isax.Index(E, w, 8, precision=1, edges=edges)
+            ie.query(QE[:64].contiguous(), k=10, mode="index")
+            (ids, _), dt, _ = _timed_query(isax, ie, QE, k=10, mode="index")
+            ref = ids if ref is None else ref
+            assert torch.equal(ids, ref), f"unit embeddings ({edges} edges) disagree"
+            _, _, st = ie.query(QE[:100].contiguous(), k=10, mode="index", stats=True)
+            out["embeddings"][f"unit_d{dim}_w{w}_{edges}_index_k10_qps"] = round(1000 / dt, 1)
+            out["embeddings"][f"unit_d{dim}_w{w}_{edges}_refined_per_query"] = round(
+                sum(x["series_refined"] for x in st) / 100)
+            log(f"unit embeddings d={dim} w={w} {edges}: {round(1000 / dt, 1)} q/s")
+            ie.close()
         del E
         torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)

@@ -89,6 +89,18 @@ enum {
 
 typedef struct isax_index isax_index; /* opaque, owned by the library */
 
+/* Region edges of the iSAX symbols (isax_build_options.edges). */
+enum {
+    ISAX_EDGES_NORMAL = 0,   /* Phi^-1(j / 2^c): equiprobable regions for N(0,1) segment means (z-normalised
+                                series) */
+    ISAX_EDGES_EMPIRICAL = 1 /* the collection's own quantiles, for data that is not z-normalised (embedding
+                                vectors, Sec. V): the FP32 segment means of every segment of
+                                S = min(n, ceil(65536 / segments)) series at ids floor(t n / S), t < S, and
+                                edge j = the ceil(j V / 2^c)-th smallest of those V = S * segments values (the
+                                inverted-CDF quantile at j / 2^c).  Nested across c like the normal edges;
+                                every bound stays a lower bound (it holds for any ordered edges). */
+};
+
 typedef struct isax_build_options {
     int32_t leaf_size; /* series per leaf (consecutive runs of the sorted order); 0 = 256; 16..1024 */
     int32_t key_bits;  /* leading bits of the interleaved key that are sorted; 0 = min(64, w*c); 8..64, multiple of 8 */
@@ -96,7 +108,7 @@ typedef struct isax_build_options {
                           bit 2: also keep the FP32 rows in leaf order (n x len x 4 bytes more), read by
                           refinement instead of the borrowed data: the series of a leaf are then
                           consecutive in memory. Answers are the same either way. */
-    int32_t reserved;  /* must be 0 */
+    int32_t edges;     /* ISAX_EDGES_*: how the 2^c - 1 region edges are chosen */
     void* stream;      /* hipStream_t the build runs on; NULL = null stream */
 } isax_build_options;
 
@@ -213,8 +225,10 @@ int isax_query_noalloc(isax_index* idx, const float* queries, int64_t m, int32_t
 
 /* ---------------------------------------------------------- inspection */
 
-/* The 2^c - 1 region edges used for c-bit symbols, FP32, ascending (host out). */
+/* The 2^c - 1 region edges used for c-bit symbols, FP32, ascending (host out): Phi^-1(j / 2^c). */
 int isax_breakpoints(int32_t card_bits, float* out);
+/* The 2^c - 1 region edges of an index (host out, FP32, ascending), normal or empirical. */
+int isax_index_breakpoints(const isax_index* idx, float* out);
 
 /*
  * iSAX words of n series without building an index (Sec. II, iSAX
@@ -233,7 +247,7 @@ typedef struct isax_index_info {
     float delta;         /* bound on |FP32 PAA - exact PAA| of any series */
     int64_t device_bytes;/* bytes the index owns on the device */
     int32_t has_sorted_rows; /* 1 if the index keeps the FP32 rows in leaf order (precision bit 2) */
-    int32_t reserved;
+    int32_t edges;           /* ISAX_EDGES_* of the build */
 } isax_index_info;
 
 int isax_index_get_info(const isax_index* idx, isax_index_info* out);

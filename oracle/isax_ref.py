@@ -83,14 +83,38 @@ def breakpoints_f32(c: int) -> np.ndarray:
     return breakpoints(c).astype(np.float32)
 
 
+EDGE_SAMPLE = 65536  # segment means the empirical edges are taken from (about)
+
+
+def empirical_breakpoints(X: np.ndarray, w: int, c: int) -> np.ndarray:
+    """Region edges from the collection's own segment means (data that is not
+    z-normalised, e.g. the embedding vectors of Sec. V), FP32, ascending.
+
+    Sample: the FP32 segment means (paa32_tree) of every segment of
+    S = min(n, ceil(EDGE_SAMPLE / w)) series, series floor(t n / S) for t < S;
+    V = S w values.  Edge j (j = 1..2^c-1) is the ceil(j V / 2^c)-th smallest
+    of them: the smallest value whose empirical CDF reaches j / 2^c.
+    """
+    X = np.asarray(X, dtype=np.float32)
+    n = X.shape[0]
+    S = min(n, -(-EDGE_SAMPLE // w))
+    rows = (np.arange(S, dtype=np.int64) * n) // S
+    v = paa32_tree(X[rows], w).ravel()
+    v = np.sort(v[np.isfinite(v)])
+    V = v.shape[0]
+    j = np.arange(1, 2 ** c, dtype=np.int64)
+    return v[-(-(j * V) // 2 ** c) - 1].astype(np.float32)
+
+
 def symbols(paa: np.ndarray, beta: np.ndarray) -> np.ndarray:
     """Region index s = #{j : beta_j <= paa} (half-open regions, s=0 lowest)."""
     return np.searchsorted(beta, paa, side="right").astype(np.uint8)
 
 
-def isax_words(X: np.ndarray, w: int, c: int) -> np.ndarray:
-    """uint8 [n, w]: the c-bit iSAX symbol of every segment of every series."""
-    return symbols(paa32_tree(X, w), breakpoints_f32(c))
+def isax_words(X: np.ndarray, w: int, c: int, beta: np.ndarray | None = None) -> np.ndarray:
+    """uint8 [n, w]: the c-bit iSAX symbol of every segment of every series
+    (region edges beta, FP32; default the standard-normal ones)."""
+    return symbols(paa32_tree(X, w), breakpoints_f32(c) if beta is None else beta)
 
 
 def word_string(word, c: int) -> str:

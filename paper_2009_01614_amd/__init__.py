@@ -27,6 +27,7 @@ METRICS = {"ed": METRIC_ED, "dtw": METRIC_DTW}
 MAX_WINDOW = 31
 QF_NO_SHARING, QF_NO_EARLY_ABANDON, QF_NO_BEST_FIRST, QF_NO_SHORTCUT, QF_FILTER_CHEAP, QF_FILTER_DEAR = 1, 2, 4, 8, 16, 32
 SERVE_BATCHES = 1
+EDGES = {"normal": 0, "empirical": 1}
 MAX_K = 1024
 
 
@@ -38,7 +39,7 @@ class IsaxError(RuntimeError):
 
 class BuildOptions(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("key_bits", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("edges", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class QueryStats(ctypes.Structure):
@@ -63,7 +64,7 @@ class IndexInfo(ctypes.Structure):
                 ("card_bits", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("key_bits", ctypes.c_int32),
                 ("has_bf16", ctypes.c_int32), ("has_fp8", ctypes.c_int32), ("n_leaves", ctypes.c_int64),
                 ("max_abs", ctypes.c_float), ("delta", ctypes.c_float), ("device_bytes", ctypes.c_int64),
-                ("has_sorted_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("has_sorted_rows", ctypes.c_int32), ("edges", ctypes.c_int32)]
 
 
 class ProfileEntry(ctypes.Structure):
@@ -97,6 +98,7 @@ SIGNATURES = {
     "isax_breakpoints": (ctypes.c_int, [_I32, _F32P]),
     "isax_summarize": (ctypes.c_int, [_VP, _I64, _I32, _I32, _I32, _VP, _F32P, _VP]),
     "isax_index_get_info": (ctypes.c_int, [_VP, ctypes.POINTER(IndexInfo)]),
+    "isax_index_breakpoints": (ctypes.c_int, [_VP, _F32P]),
     "isax_index_export": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "isax_lower_bounds": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "isax_filter_scores": (ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _VP]),
@@ -199,11 +201,14 @@ class Index:
     """
 
     def __init__(self, data: torch.Tensor, segments: int = 16, card_bits: int = 8, leaf_size: int = 0,
-                 key_bits: int = 0, precision: int = 0, stream=None):
+                 key_bits: int = 0, precision: int = 0, stream=None, edges="normal"):
+        """edges: "normal" (standard-normal quantiles) or "empirical" (the collection's own)."""
         _dev_f32(data, "data", allow_pinned=True)
         self.data = data
         self.n, self.len = data.shape
-        opt = BuildOptions(leaf_size, key_bits, precision, 0, _stream(stream))
+        self.card_bits = card_bits
+        opt = BuildOptions(leaf_size, key_bits, precision, EDGES[edges] if isinstance(edges, str) else int(edges),
+                           _stream(stream))
         h = lib().isax_build_ex(data.data_ptr(), self.n, self.len, segments, card_bits, ctypes.byref(opt))
         if not h:
             raise IsaxError(ISAX_EINVAL, last_error())
@@ -223,6 +228,13 @@ class Index:
             self.close()
         except Exception:
             pass
+
+    def breakpoints(self):
+        """The index's 2^c - 1 region edges (numpy FP32)."""
+        import numpy as np
+        out = np.zeros((1 << self.card_bits) - 1, np.float32)
+        _check(lib().isax_index_breakpoints(self._h, out.ctypes.data_as(_F32P)))
+        return out
 
     def info(self) -> dict:
         inf = IndexInfo()

@@ -139,6 +139,39 @@ __global__ void k_summarise_generic(const float* __restrict__ data, int64_t n, i
 }
 
 // ---------------------------------------------------------------------------------------------
+// FP32 PAA of every segment of n_series evenly spaced series (series
+// floor(t n / n_series), t = 0..n_series-1) into out[t][w], in the summation
+// order of the summarise kernels (zero-padded to a power of two, a balanced
+// tree of adjacent pairs, then / m): the sample the empirical region edges
+// are taken from.
+__global__ void k_paa_sample(const float* __restrict__ data, int64_t n, int len, int w, int m, int n_series,
+                             float* __restrict__ out) {
+    int P = 1;
+    while (P < m) P <<= 1;
+    const int64_t items = (int64_t)n_series * w;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < items;
+         it += (int64_t)gridDim.x * blockDim.x) {
+        const int t = (int)(it / w), j = (int)(it - (int64_t)t * w);
+        const int64_t i = (int64_t)t * n / n_series;
+        const float* x = data + i * len + (int64_t)j * m;
+        float stack[14];
+        int level[14];
+        int top = 0;
+        for (int q = 0; q < P; ++q) {
+            stack[top] = q < m ? x[q] : 0.f;
+            level[top] = 0;
+            ++top;
+            while (top >= 2 && level[top - 1] == level[top - 2]) {
+                stack[top - 2] = stack[top - 2] + stack[top - 1];
+                level[top - 2] += 1;
+                --top;
+            }
+        }
+        out[it] = stack[0] / (float)m;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Interleaved key: bit (63 - (r*w + j)) holds bit (c-1-r) of segment j; only
 // the first key_bits positions are kept.  The first w bits are the root subtree.
 // 16 segments: the bit of round r of the four bytes of a word is gathered with
@@ -639,6 +672,12 @@ void launch_quantise(const float* data, const int32_t* ids, int64_t n, int len, 
     const bool vec = len % 4 == 0 && (reinterpret_cast<uintptr_t>(data) & 15) == 0;
     if (vec) k_quantise<true><<<grid_blocks(n, 4), 256, 0, s>>>(data, ids, n, len, len_pad, kind, xb, xf, meta);
     else k_quantise<false><<<grid_blocks(n, 4), 256, 0, s>>>(data, ids, n, len, len_pad, kind, xb, xf, meta);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_paa_sample(const float* data, int64_t n, int len, int w, int n_series, float* out, hipStream_t s) {
+    const int64_t items = (int64_t)n_series * w;
+    k_paa_sample<<<grid_blocks(items, 256, 4096), 256, 0, s>>>(data, n, len, w, len / w, n_series, out);
     ISAX_HIP(hipGetLastError());
 }
 

@@ -161,6 +161,8 @@ struct isax_index {
     float max_abs = 0.f;
     float delta = 0.f;
     float* beta = nullptr;          // [ns-1] region edges
+    std::vector<float> beta_host;   // the same on the host
+    int edges = ISAX_EDGES_NORMAL;  // how the edges were chosen
     uint8_t* words_sorted = nullptr;// [n][ws]
     int32_t* ids_sorted = nullptr;  // [n]
     uint8_t* env_lo = nullptr;      // [n_leaves][ws]

@@ -391,8 +391,33 @@ void validate_series_shape(const float* data, int64_t n, int32_t len, int32_t w,
     ISAX_REQUIRE((reinterpret_cast<uintptr_t>(data) & 3) == 0, "data must be 4-byte aligned");
 }
 
-float* upload_beta(int c, hipStream_t s, DevBuf* tmp, isax_index* idx) {
-    const std::vector<float> b = breakpoints_f32(c);
+// Empirical region edges (isax_build_options.edges): the FP32 PAA of every
+// segment of S = ceil(kEdgeSample / w) evenly spaced series (at most n), and
+// edge j = the ceil(j V / 2^c)-th smallest of those V = S w values (the
+// inverted-CDF quantile at j / 2^c).  Nested across c like the normal ones.
+constexpr int kEdgeSample = 65536;
+std::vector<float> empirical_edges(const float* data, int64_t n, int len, int w, int c, hipStream_t s) {
+    const int S = (int)std::min<int64_t>(n, (kEdgeSample + w - 1) / w);
+    DevBuf buf((size_t)S * w * sizeof(float), s);
+    launch_paa_sample(data, n, len, w, S, buf.as<float>(), s);
+    std::vector<float> v((size_t)S * w);
+    ISAX_HIP(hipMemcpyAsync(v.data(), buf.p, v.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    ISAX_HIP(hipStreamSynchronize(s));
+    // a non-finite value is rejected by the summarise pass; keep it out of the sort
+    v.erase(std::remove_if(v.begin(), v.end(), [](float x) { return !(std::fabs(x) <= 3.4028235e38f); }), v.end());
+    std::sort(v.begin(), v.end());
+    const int64_t V = (int64_t)v.size();
+    std::vector<float> b((size_t)(1 << c) - 1, 0.f);
+    for (int j = 1; j < (1 << c) && V > 0; ++j) {
+        const int64_t r = (j * V + (1 << c) - 1) / (1 << c) - 1;  // ceil(j V / 2^c) - 1
+        b[j - 1] = v[(size_t)std::max<int64_t>(0, r)];
+    }
+    return b;
+}
+
+float* upload_beta(int c, hipStream_t s, DevBuf* tmp, isax_index* idx, const std::vector<float>* edges = nullptr) {
+    const std::vector<float> b = edges ? *edges : breakpoints_f32(c);
+    if (idx) idx->beta_host = b;
     float* d = idx ? own<float>(idx, b.size()) : nullptr;
     if (!idx) {
         *tmp = DevBuf(b.size() * sizeof(float), s);
@@ -412,7 +437,7 @@ isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int
     ISAX_REQUIRE(key_bits >= 8 && key_bits <= 64 && key_bits % 8 == 0, "key_bits must be a multiple of 8 in 8..64");
     ISAX_REQUIRE(o.precision >= 0 && o.precision <= 7,
                  "precision must be a bitmask of 1 (BF16), 2 (FP8) and 4 (FP32 rows in leaf order)");
-    ISAX_REQUIRE(o.reserved == 0, "reserved must be 0");
+    ISAX_REQUIRE(o.edges == ISAX_EDGES_NORMAL || o.edges == ISAX_EDGES_EMPIRICAL, "edges must be 0 or 1");
     require_device_accessible(data, "data");
     hipStream_t s = static_cast<hipStream_t>(o.stream);
 
@@ -430,7 +455,13 @@ isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int
     idx->leaf_size = leaf;
     idx->key_bits = key_bits;
     idx->n_leaves = (n + leaf - 1) / leaf;
-    idx->beta = upload_beta(c, s, nullptr, idx.get());
+    idx->edges = o.edges;
+    if (o.edges == ISAX_EDGES_EMPIRICAL) {
+        const std::vector<float> e = empirical_edges(data, n, len, w, c, s);
+        idx->beta = upload_beta(c, s, nullptr, idx.get(), &e);
+    } else {
+        idx->beta = upload_beta(c, s, nullptr, idx.get());
+    }
 
     const int ws = idx->ws;
     DevBuf words(n * ws, s), flags(16, s);
@@ -1752,6 +1783,14 @@ int isax_summarize(const float* data, int64_t n, int32_t len, int32_t segments, 
     });
 }
 
+int isax_index_breakpoints(const isax_index* idx, float* out) {
+    return guarded([&] {
+        ISAX_REQUIRE(idx && out, "index and out must not be NULL");
+        std::memcpy(out, idx->beta_host.data(), idx->beta_host.size() * sizeof(float));
+        return ISAX_OK;
+    });
+}
+
 int isax_index_get_info(const isax_index* idx, isax_index_info* out) {
     return guarded([&] {
         ISAX_REQUIRE(idx && out, "index and out must not be NULL");
@@ -1764,6 +1803,7 @@ int isax_index_get_info(const isax_index* idx, isax_index_info* out) {
         out->has_bf16 = idx->x_bf16 != nullptr;
         out->has_fp8 = idx->x_fp8 != nullptr;
         out->has_sorted_rows = idx->xs != nullptr;
+        out->edges = idx->edges;
         out->n_leaves = idx->n_leaves;
         out->max_abs = idx->max_abs;
         out->delta = idx->delta;

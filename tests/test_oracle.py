@@ -112,6 +112,89 @@ def test_c8_table_span():
     assert abs(np.diff(beta).min() - 0.00979) < 1e-5
 
 
+# ----------------------------------------------------------------------------- empirical edges
+def _embeddings(n, d, seed):
+    rng = np.random.default_rng(seed)
+    centres = rng.standard_normal((40, d)) * 3.0
+    return (centres[rng.integers(0, 40, n)] + 0.7 * rng.standard_normal((n, d))).astype(np.float32)
+
+
+def test_empirical_edges_are_inverted_cdf_quantiles():
+    # edge j is the library's inverted-CDF quantile of the sampled segment means at j / 2^c
+    X = _embeddings(3000, 64, 21)
+    for c in (1, 3, 8):
+        got = ir.empirical_breakpoints(X, 8, c)
+        v = ir.paa32_tree(X, 8).ravel()   # n < 65536 / 8: every series is sampled
+        want = np.quantile(v, np.arange(1, 2 ** c) / 2 ** c, method="inverted_cdf")
+        assert got.dtype == np.float32 and np.array_equal(got, want.astype(np.float32))
+
+
+def test_empirical_edges_rank_property_brute_force():
+    # #{v < e_j} < ceil(j V / 2^c) <= #{v <= e_j}, counted one value at a time
+    X = _embeddings(500, 24, 22)
+    v = [float(a) for a in ir.paa32_tree(X, 6).ravel()]
+    V = len(v)
+    for c in (2, 4):
+        e = ir.empirical_breakpoints(X, 6, c)
+        assert np.all(np.diff(e) >= 0)
+        for j in range(1, 2 ** c):
+            rank = -(-j * V // 2 ** c)
+            below = sum(1 for a in v if a < e[j - 1])
+            upto = sum(1 for a in v if a <= e[j - 1])
+            assert below < rank <= upto
+
+
+def test_empirical_edges_sample_rule_and_nesting():
+    # series i holds the constant i, so the sampled values name the sampled series:
+    # S = ceil(65536 / w) series, series floor(t n / S); nesting across cardinalities
+    n, w = 50_000, 8
+    X = np.repeat(np.arange(n, dtype=np.float32)[:, None], 32, axis=1)
+    S = 8192
+    picked = sorted({t * n // S for t in range(S)})
+    assert len(picked) == S
+    e8 = ir.empirical_breakpoints(X, w, 8)
+    assert set(e8.astype(np.int64)) <= set(picked)
+    for j in range(1, 256):                       # each series contributes w equal values
+        assert e8[j - 1] == picked[-(-j * S // 256) - 1]
+    for b in range(1, 8):
+        step = 2 ** (8 - b)
+        assert np.array_equal(ir.empirical_breakpoints(X, w, b), e8[step - 1::step])
+
+
+def test_empirical_edges_approach_normal_quantiles_and_skip_nan():
+    # piecewise-constant N(0,1) segments: the sampled means are the normal draws themselves,
+    # so the edges approach Phi^-1(j / 16) (DKW: |F_V - Phi| < 0.01 with V = 65536)
+    rng = np.random.default_rng(23)
+    seg = rng.standard_normal((8192, 8)).astype(np.float32)
+    X = np.repeat(seg, 16, axis=1)
+    e = ir.empirical_breakpoints(X, 8, 4)
+    assert np.array_equal(ir.paa32_tree(X, 8), seg)
+    phi = np.array([0.5 * (1 + math.erf(float(b) / math.sqrt(2))) for b in e])
+    assert np.abs(phi - np.arange(1, 16) / 16).max() < 0.01
+    # a series with a non-finite value: its segment means are dropped before the ranks
+    Y = X.copy()
+    Y[5, 3] = np.nan
+    keep = np.isfinite(ir.paa32_tree(Y, 8).ravel())
+    assert keep.sum() == Y.size // 16 - 1
+    v = np.sort(ir.paa32_tree(Y, 8).ravel()[keep])
+    j = np.arange(1, 16)
+    assert np.array_equal(ir.empirical_breakpoints(Y, 8, 4), v[-(-(j * v.size) // 16) - 1])
+
+
+def test_isax_words_with_explicit_edges():
+    X = _embeddings(200, 32, 24)
+    assert np.array_equal(ir.isax_words(X, 8, 4, ir.breakpoints_f32(4)), ir.isax_words(X, 8, 4))
+    e = ir.empirical_breakpoints(X, 8, 4)
+    got = ir.isax_words(X, 8, 4, e)
+    p = ir.paa32_tree(X, 8)
+    for i in range(0, 200, 37):
+        for j in range(8):
+            assert got[i, j] == sum(1 for b in e if b <= p[i, j])
+    # the empirical edges spread the symbols: each of the 16 regions holds about 1/16
+    h = np.bincount(got.ravel(), minlength=16) / got.size
+    assert h.min() > 0.04 and h.max() < 0.09
+
+
 # ----------------------------------------------------------------------------- symbols
 def test_symbols_brute_force_and_half_open():
     beta = ir.breakpoints_f32(3)

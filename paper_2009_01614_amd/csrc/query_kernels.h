@@ -40,6 +40,8 @@ struct QueryArgs {
                       //    (the free slots of a serving table)
     int home_leaves;  // leaves the approximate answer covers at least (0: the default, 4)
     int leaf_stride;  // leaf pass: every leaf_stride-th block of leaves only (0 or 1: every leaf)
+    const int32_t* qsel;  // leaf pass: the queries it bounds leaves for, [nsel] (null: all mq)
+    int nsel;
     float* paa;       // [mq][w]
     uint8_t* sym;     // [mq][ws]
     uint64_t* qkey;   // [mq]

@@ -750,8 +750,12 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
     __shared__ int64_t s_home[QB][2];
     __shared__ unsigned s_valid[QB], s_kept[QB], s_base[QB];
     __shared__ unsigned char s_node_in[QB][4 * R];
+    __shared__ int s_q[QB];
+    // the block's queries: QB consecutive rows, or QB consecutive entries of the selection
     const int q0 = blockIdx.y * QB;
-    const int nq = min(QB, a.mq - q0);
+    const int nq = min(QB, (a.qsel ? a.nsel : a.mq) - q0);
+    if (threadIdx.x < nq) s_q[threadIdx.x] = a.qsel ? a.qsel[q0 + threadIdx.x] : q0 + threadIdx.x;
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     // nodes of 64 leaves: node nd of this block (nd = 4 r + wave) is node (16 blockIdx.x + nd) * stride;
@@ -760,7 +764,7 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
     const int64_t base_leaf = (int64_t)blockIdx.x * 256 * R;  // (stride 1: the first leaf of the block)
     auto node_of = [&](int nd) -> int64_t { return ((int64_t)blockIdx.x * 4 * R + nd) * stride; };
     for (int i = 0; i < nq; ++i) {
-        const int q = q0 + i;
+        const int q = s_q[i];
         for (int s = threadIdx.x; s < a.ns; s += 256) {
             lo_e[i][s] = a.edges[(int64_t)q * 2 * a.ns + s];
             hi_e[i][s] = a.edges[(int64_t)q * 2 * a.ns + a.ns + s];
@@ -772,7 +776,7 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
         if (threadIdx.x < kLeafBins) hist[i][threadIdx.x] = 0u;
     }
     if (threadIdx.x < nq) {
-        const int q = q0 + threadIdx.x;
+        const int q = s_q[threadIdx.x];
         // a query set aside (skip_done) keeps no node and no leaf
         s_thr[threadIdx.x] = a.skip_done && a.done[q] ? -1.f : read_tau(a, q, a.kq[q]) * a.tau_scale;
         s_home[threadIdx.x][0] = a.home[2 * q];
@@ -844,7 +848,7 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
     __syncthreads();
     // one atomic per query and block for the list position, then the entries
     if (threadIdx.x < nq && s_kept[threadIdx.x])
-        s_base[threadIdx.x] = atomicAdd(a.leaf_count + q0 + threadIdx.x, s_kept[threadIdx.x]);
+        s_base[threadIdx.x] = atomicAdd(a.leaf_count + s_q[threadIdx.x], s_kept[threadIdx.x]);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < QB; ++i) {
@@ -853,18 +857,18 @@ __global__ void __launch_bounds__(256) k_leaf_hist(QueryArgs a) {
             if (slot[i][r] < 0) continue;
             const int64_t p = (int64_t)s_base[i] + slot[i][r];
             if (p < a.leaf_cap)
-                a.leaf_list[(int64_t)(q0 + i) * a.leaf_cap + p] =
+                a.leaf_list[(int64_t)s_q[i] * a.leaf_cap + p] =
                     make_uint2((unsigned)(node_of(r * 4 + (threadIdx.x >> 6)) * kNodeLeaves + lane),
                                __float_as_uint(lbs[i][r]));
         }
     }
     for (int i = 0; i < nq; ++i) {
-        const int q = q0 + i;
+        const int q = s_q[i];
         if (threadIdx.x < kLeafBins && hist[i][threadIdx.x])
             atomicAdd(a.leaf_hist + (int64_t)q * kLeafBins + threadIdx.x, hist[i][threadIdx.x]);
     }
     if (threadIdx.x < nq && s_valid[threadIdx.x])
-        atomicAdd(a.stats + (int64_t)(q0 + threadIdx.x) * ST_N + ST_LEAVES, (unsigned long long)s_valid[threadIdx.x]);
+        atomicAdd(a.stats + (int64_t)s_q[threadIdx.x] * ST_N + ST_LEAVES, (unsigned long long)s_valid[threadIdx.x]);
 }
 
 // After round 1: the leaves that round 2 would still take, counted from the
@@ -1628,10 +1632,12 @@ void launch_leaf_order(const QueryArgs& a, hipStream_t s) {
     ISAX_HIP(hipMemsetAsync(a.leaf_hist, 0, (size_t)a.mq * kLeafBins * sizeof(unsigned), s));
     ISAX_HIP(hipMemsetAsync(a.leaf_count, 0, (size_t)a.mq * sizeof(unsigned), s));
     const int64_t per_block = 256 * kHistLeafRounds * std::max(1, a.leaf_stride);
-    const dim3 grid((unsigned)((a.n_leaves + per_block - 1) / per_block),
-                    (unsigned)((a.mq + kHistQueries - 1) / kHistQueries));
-    if (a.w == 16 && a.ws == 16) k_leaf_hist<true><<<grid, 256, 0, s>>>(a);
-    else k_leaf_hist<false><<<grid, 256, 0, s>>>(a);
+    const int nq = a.qsel ? a.nsel : a.mq;
+    if (nq > 0) {
+        const dim3 grid((unsigned)((a.n_leaves + per_block - 1) / per_block), (unsigned)((nq + kHistQueries - 1) / kHistQueries));
+        if (a.w == 16 && a.ws == 16) k_leaf_hist<true><<<grid, 256, 0, s>>>(a);
+        else k_leaf_hist<false><<<grid, 256, 0, s>>>(a);
+    }
     k_leaf_theta<<<(a.mq + 255) / 256, 256, 0, s>>>(a);
     ISAX_HIP(hipGetLastError());
 }

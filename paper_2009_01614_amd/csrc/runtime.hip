@@ -654,7 +654,8 @@ void leaf_pass(Batch& b, int64_t cap, hipStream_t s) {
     b.hist_valid = true;
     // leaf envelopes once per block of queries
     if (profiling_on())
-        profile_add_bytes("leaf_order", 2.0 * a.ws * a.n_leaves * ((a.mq + kHistQueries - 1) / kHistQueries));
+        profile_add_bytes("leaf_order",
+                          2.0 * a.ws * a.n_leaves * (((a.qsel ? a.nsel : a.mq) + kHistQueries - 1) / kHistQueries));
 }
 
 void fill_stats(const Batch& b, isax_query_stats* out, hipStream_t s) {
@@ -925,23 +926,32 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     // computing it again
     Batch shadow;
     setup_batch(shadow, idx, a.Q, mq, a.kq, a.kmax, a.cap, a.flags, nullptr, nullptr, s);
-    DevBuf maps((size_t)mq * 2 * sizeof(int2), s);
+    DevBuf maps((size_t)mq * 2 * sizeof(int2) + (size_t)mq * sizeof(int32_t), s);
     int2* ident = maps.as<int2>();
     int2* fmap = ident + mq;
+    int32_t* qsel = reinterpret_cast<int32_t*>(fmap + mq);
     // host sources of the copies below stay alive until the batch's last sync
     std::vector<int2> id(mq), fm;
-    for (int q = 0; q < mq; ++q) id[q] = make_int2(q, q);
+    std::vector<int32_t> sel;
+    for (int q = 0; q < mq; ++q) {
+        id[q] = make_int2(q, q);
+        if (!pre[q]) sel.push_back(q);
+    }
     ISAX_HIP(hipMemcpyAsync(ident, id.data(), mq * sizeof(int2), hipMemcpyHostToDevice, s));
+    if ((int)sel.size() < mq)
+        ISAX_HIP(hipMemcpyAsync(qsel, sel.data(), sel.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     {
         const FilterArgs none{};
         launch_copy_rows(a, none, shadow.a, none, ident, mq, false, s, false);
     }
-    // the leaf pass for the queries that stay (done = 1 sets a query aside)
-    for (int q = 0; q < mq; ++q) flags_a[q] = pre[q];
-    ISAX_HIP(hipMemcpyAsync(a.done, flags_a.data(), mq * sizeof(int), hipMemcpyHostToDevice, s));
-    a.skip_done = 1;
+    // the leaf pass for the queries that stay (the others keep empty lists)
+    if ((int)sel.size() < mq) {
+        a.qsel = qsel;
+        a.nsel = (int)sel.size();
+    }
     leaf_pass(b, kLeafListMax, s);
-    a.skip_done = 0;
+    a.qsel = nullptr;
+    a.nsel = 0;
     std::vector<int64_t> cnt = leaves_initial(b, s);
     b.li = cnt;
     for (int q = 0; q < mq; ++q)

@@ -12,5 +12,6 @@ Modules
              (knn_ref.c, built by build_c()) used for large sampled checks
              and for the CPU baseline timing
   margin_ref FP64 check of the BF16 / FP8 dot-product filter margin
+  spectral_ref  DCT-based reduced copy of the filter and its lower bound
 """
-from . import isax_ref, knn_ref, margin_ref  # noqa: F401
+from . import isax_ref, knn_ref, margin_ref, spectral_ref  # noqa: F401

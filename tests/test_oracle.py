@@ -15,6 +15,7 @@ from scipy.spatial.distance import cdist
 from oracle import isax_ref as ir
 from oracle import knn_ref as kr
 from oracle import margin_ref as mr
+from oracle import spectral_ref as sr
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -340,6 +341,86 @@ def test_mindist_pure_python_tiny():
             d = max(0.0, ext[s] - p[j], p[j] - ext[s + 1])
             tot += d * d
         assert abs(got[i] - 8 * tot) <= 1e-12 * max(1, tot)
+
+
+# ----------------------------------------------------------------------------- spectral copy
+def test_dct_matrix_cosine_definition_and_orthonormal():
+    # scipy's DCT against the cosine definition, term by term (pure Python), and T T^T = I
+    L = 12
+    T = sr.dct_matrix(L)
+    for i in range(L):
+        c = math.sqrt((1.0 if i == 0 else 2.0) / L)
+        for j in range(L):
+            k = i * (2 * j + 1) % (4 * L)   # cos has period 4L in units of pi / (2L)
+            assert abs(T[i, j] - c * math.cos(math.pi * k / (2 * L))) <= 1e-15
+    for L in (16, 200, 256, 512):
+        T = sr.dct_matrix(L)
+        assert np.abs(T @ T.T - np.eye(L)).max() <= 1e-13
+
+
+def test_spectral_ext_pure_python_tiny():
+    X = walks(5, 8, 40)
+    got = sr.spectral_ext(X, 3)
+    for i in range(5):
+        y = [math.fsum((math.sqrt((1.0 if k == 0 else 2.0) / 8) * math.cos(math.pi * (k * (2 * j + 1) % 32) / 16)) *
+                       float(X[i, j]) for j in range(8)) for k in range(8)]
+        want = [y[0], y[1], math.sqrt(math.fsum(v * v for v in y[2:]))]
+        assert np.allclose(got[i], want, rtol=0, atol=1e-13)
+
+
+def test_spectral_ext_energy_bound_and_monotone_in_width():
+    X = walks(300, 256, 41)
+    Q = walks(20, 256, 42)
+    d2 = np.stack([kr.sq_dists(X, q) for q in Q])
+    assert np.allclose(np.linalg.norm(sr.spectral_ext(X, 128), axis=1), np.linalg.norm(X.astype(np.float64), axis=1),
+                       rtol=1e-13, atol=0)
+    prev = None
+    for D in (2, 16, 64, 127, 128, 192, 256):
+        lb = sr.spectral_lb_sq(Q, X, D)
+        assert np.all(lb <= d2 * (1 + 1e-12) + 1e-9), D        # a lower bound on every pair
+        if prev is not None:
+            assert np.all(lb >= prev * (1 - 1e-12) - 1e-9), D  # never weaker with more coefficients
+        prev = lb
+    # D = L keeps every coefficient but the sign of the last: exact where the signs agree
+    Y, Z = sr.spectral_ext(Q, 256), sr.spectral_ext(X, 256)
+    from scipy.fft import dct
+    same = np.sign(dct(Q.astype(np.float64), norm="ortho", axis=1)[:, -1:]) == \
+        np.sign(dct(X.astype(np.float64), norm="ortho", axis=1)[:, -1])[None, :]
+    assert np.allclose(np.where(same, prev, d2), d2, rtol=1e-10, atol=1e-9)
+
+
+def test_spectral_ext_tight_case():
+    # q = x + v with v in the span of the first D - 1 basis vectors: equal tails, so LB = ED^2
+    X = walks(50, 256, 43)
+    T = sr.dct_matrix(256)
+    rng = np.random.default_rng(44)
+    V = rng.standard_normal((50, 127)) @ T[:127]
+    Q = X.astype(np.float64) + V
+    lb = np.array([sr.spectral_lb_sq(Q[i:i + 1], X[i:i + 1], 128)[0, 0] for i in range(50)])
+    assert np.allclose(lb, (V ** 2).sum(axis=1), rtol=1e-10, atol=0)
+
+
+def test_spectral_filter_scores_bound_every_pair():
+    # the filter's approximate distance minus its error bound never exceeds ED^2 (FP64),
+    # and the bound is far tighter on random walks than the BF16 margin on the full rows is wide
+    X = walks(2000, 256, 45)
+    rng = np.random.default_rng(46)
+    src = rng.integers(0, 2000, 30)
+    Q = X[src] + np.array([0.01, 0.1, 1.0])[np.arange(30) % 3, None] * rng.standard_normal((30, 256))
+    Q = ((Q - Q.mean(1, keepdims=True)) / Q.std(1, keepdims=True)).astype(np.float32)
+    approx, err = sr.spectral_filter_scores(Q, X, 128)
+    d2 = np.stack([kr.sq_dists(X, q) for q in Q])
+    assert np.all(approx - err <= d2 + 1e-9)
+    lb = sr.spectral_lb_sq(Q, X, 128)
+    assert np.all(np.abs(lb - approx) <= err + 1e-9)
+    assert err.mean() < 4.0
+    # a planted mistake: dropping the tail coordinate breaks the bound somewhere
+    e_q, e_x = sr.spectral_ext(Q, 128), sr.spectral_ext(X, 128)
+    no_tail = (e_q[:, None, :127] - e_x[None, :, :127]) ** 2
+    assert np.all(no_tail.sum(axis=2) <= d2 + 1e-9)
+    wrong = (Q.astype(np.float64) ** 2).sum(1)[:, None] + (X.astype(np.float64) ** 2).sum(1)[None, :] - \
+        2.0 * (e_q[:, :127] @ e_x[:, :127].T)
+    assert np.any(wrong > d2 + 1e-6)
 
 
 # ----------------------------------------------------------------------------- k-NN

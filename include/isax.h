@@ -69,8 +69,10 @@ enum {
     ISAX_QF_NO_SHORTCUT = 8,      /* hybrid mode: price every query with the cost model even when the whole
                                      batch is cheap enough for the filter alone */
     ISAX_QF_FILTER_CHEAP = 16,    /* hybrid mode: price the filter at 1/1000 of its model, or */
-    ISAX_QF_FILTER_DEAR = 32      /* at 1000 times it, so that small collections exercise each of the
+    ISAX_QF_FILTER_DEAR = 32,     /* at 1000 times it, so that small collections exercise each of the
                                      planner's routes (testing) */
+    ISAX_QF_FULL_ROWS = 64        /* BF16 filter: read the full-length BF16 copy even when the index also
+                                     holds the spectral copy (precision bit 3) */
 };
 
 /* Distance measures (isax_query_options.metric). */
@@ -107,9 +109,23 @@ typedef struct isax_build_options {
     int32_t precision; /* bit 0: also keep a BF16 copy, bit 1: also keep an FP8 E4M3 copy (needed by those modes);
                           bit 2: also keep the FP32 rows in leaf order (n x len x 4 bytes more), read by
                           refinement instead of the borrowed data: the series of a leaf are then
-                          consecutive in memory. Answers are the same either way. */
+                          consecutive in memory. Answers are the same either way.
+                          bit 3: also keep the spectral copy, a reduced representation for the BF16
+                          filter (lower-bound pruning on a reduced representation before real
+                          distances, Sec. II-III): with y = T x, T the orthonormal DCT-II of length
+                          len, the series is summarised by ext(x) = (y_0 .. y_{D-2}, |(y_{D-1} ..
+                          y_{len-1})|), D = spectral_dim coordinates in BF16 (n x D x 2 bytes), computed
+                          in FP64.  |ext(x)| = |x| and q.x <= ext(q).ext(x), so the filter's margin
+                          rule holds with ext in place of the rows: the BF16 filter (modes BF16 and
+                          HYBRID, and the server's filter modes) then reads this copy, D / len of the
+                          matrix work, and refines more candidates where the dropped coefficients
+                          carry energy.  Answers are the same. */
     int32_t edges;     /* ISAX_EDGES_*: how the 2^c - 1 region edges are chosen */
     void* stream;      /* hipStream_t the build runs on; NULL = null stream */
+    int32_t spectral_dim; /* D of the spectral copy: 0 = three quarters of the padded length (len rounded up
+                             to a multiple of 64), rounded down to a multiple of 64, within 64..256 (192
+                             for len 256); else a multiple of 64 in 64..256, below len */
+    int32_t reserved;     /* must be 0 */
 } isax_build_options;
 
 typedef struct isax_query_stats { /* per query, filled when requested */
@@ -248,6 +264,8 @@ typedef struct isax_index_info {
     int64_t device_bytes;/* bytes the index owns on the device */
     int32_t has_sorted_rows; /* 1 if the index keeps the FP32 rows in leaf order (precision bit 2) */
     int32_t edges;           /* ISAX_EDGES_* of the build */
+    int32_t spectral_dim;    /* D of the spectral copy (precision bit 3), 0 if none */
+    int32_t reserved;
 } isax_index_info;
 
 int isax_index_get_info(const isax_index* idx, isax_index_info* out);
@@ -273,7 +291,9 @@ int isax_lower_bounds(isax_index* idx, const float* queries, int64_t m, float* o
  * Scores of the reduced-precision filter (mode ISAX_MODE_BF16 or _FP8), for
  * testing its margin: out_approx (device, m x n) = |q|^2 + |x|^2 - 2 q~.x~
  * accumulated on the matrix cores, out_margin (device, m x n) = the bound M
- * with |ED^2 - approx| <= M.  m <= 1024.
+ * with |ED^2 - approx| <= M.  m <= 1024.  Where the index holds the spectral
+ * copy, BF16 scores are those of that copy (q~, x~ the BF16 copies of ext(q),
+ * ext(x)): then |ext-distance^2 - approx| <= M, and approx - M <= ED^2.
  */
 int isax_filter_scores(isax_index* idx, const float* queries, int64_t m, int32_t mode,
                        float* out_approx, float* out_margin);

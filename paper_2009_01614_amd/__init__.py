@@ -26,6 +26,9 @@ METRIC_ED, METRIC_DTW = 0, 1
 METRICS = {"ed": METRIC_ED, "dtw": METRIC_DTW}
 MAX_WINDOW = 31
 QF_NO_SHARING, QF_NO_EARLY_ABANDON, QF_NO_BEST_FIRST, QF_NO_SHORTCUT, QF_FILTER_CHEAP, QF_FILTER_DEAR = 1, 2, 4, 8, 16, 32
+QF_FULL_ROWS = 64
+# isax_build_options.precision bits
+PREC_BF16, PREC_FP8, PREC_SORTED_ROWS, PREC_SPECTRAL = 1, 2, 4, 8
 SERVE_BATCHES = 1
 EDGES = {"normal": 0, "empirical": 1}
 MAX_K = 1024
@@ -39,7 +42,8 @@ class IsaxError(RuntimeError):
 
 class BuildOptions(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("key_bits", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("edges", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("edges", ctypes.c_int32), ("stream", ctypes.c_void_p), ("spectral_dim", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class QueryStats(ctypes.Structure):
@@ -64,7 +68,8 @@ class IndexInfo(ctypes.Structure):
                 ("card_bits", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("key_bits", ctypes.c_int32),
                 ("has_bf16", ctypes.c_int32), ("has_fp8", ctypes.c_int32), ("n_leaves", ctypes.c_int64),
                 ("max_abs", ctypes.c_float), ("delta", ctypes.c_float), ("device_bytes", ctypes.c_int64),
-                ("has_sorted_rows", ctypes.c_int32), ("edges", ctypes.c_int32)]
+                ("has_sorted_rows", ctypes.c_int32), ("edges", ctypes.c_int32), ("spectral_dim", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ProfileEntry(ctypes.Structure):
@@ -201,14 +206,15 @@ class Index:
     """
 
     def __init__(self, data: torch.Tensor, segments: int = 16, card_bits: int = 8, leaf_size: int = 0,
-                 key_bits: int = 0, precision: int = 0, stream=None, edges="normal"):
-        """edges: "normal" (standard-normal quantiles) or "empirical" (the collection's own)."""
+                 key_bits: int = 0, precision: int = 0, stream=None, edges="normal", spectral_dim: int = 0):
+        """edges: "normal" (standard-normal quantiles) or "empirical" (the collection's own).
+        precision: bits PREC_*; spectral_dim: D of the spectral copy (PREC_SPECTRAL), 0 = the default."""
         _dev_f32(data, "data", allow_pinned=True)
         self.data = data
         self.n, self.len = data.shape
         self.card_bits = card_bits
         opt = BuildOptions(leaf_size, key_bits, precision, EDGES[edges] if isinstance(edges, str) else int(edges),
-                           _stream(stream))
+                           _stream(stream), spectral_dim, 0)
         h = lib().isax_build_ex(data.data_ptr(), self.n, self.len, segments, card_bits, ctypes.byref(opt))
         if not h:
             raise IsaxError(ISAX_EINVAL, last_error())

@@ -19,6 +19,10 @@ void launch_leaf_layout(const uint64_t* keys_sorted, const uint8_t* words_sorted
 // meta[p] = {|x|^2, |e_x|, |x~|, scale}.
 void launch_quantise(const float* data, const int32_t* ids, int64_t n, int len, int len_pad, int kind, uint16_t* xb,
                      uint8_t* xf, float4* meta, hipStream_t s);
+// Spectral copy (D coefficients per series, row p = series ids[p]) from the
+// transform tt [len][D] (FP64, column D - 1 zero); meta[p] = {|x|^2, |e|, |x~|, 1}.
+void launch_spectral(const float* data, const int32_t* ids, int64_t n, int len, int D, const double* tt, uint16_t* xs,
+                     float4* meta, hipStream_t s);
 // FP32 PAA (the summarise kernels' order) of every segment of n_series evenly
 // spaced series into out [n_series][w].
 void launch_paa_sample(const float* data, int64_t n, int len, int w, int n_series, float* out, hipStream_t s);

@@ -565,6 +565,92 @@ __global__ void __launch_bounds__(256) k_quantise(const float* __restrict__ data
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Spectral copy: for the series at sorted position p, y = T x in FP64 (T the
+// orthonormal DCT-II, given transposed as tt [len][D] with a zero column D - 1),
+// ext(x) = (y_0 .. y_{D-2}, t) with t = sqrt(|x|^2 - |y_head|^2) the norm of the
+// dropped coefficients, and its BF16 codes.  A block takes tiles of 64 series,
+// staged through LDS kSpecChunk points at a time (rows of kSpecChunk + 1
+// floats: lanes read distinct banks); wave g computes coefficients
+// [g DQ, (g + 1) DQ) of every series of the tile, one series per lane, the
+// coefficients of T coming through scalar loads.
+// meta[p] = {|x|^2, |ext(x) - x~| (up), |x~| (up), 1}: the FP64 transform (T
+// within 2^-50 relative, sums of at most 512 terms) puts the head within
+// 1e-12 |x| of the exact one and the tail norm, from a difference of squares,
+// within 1.5e-6 |x|; 2^-18 |x| is added to |ext(x) - x~| for both.
+constexpr int kSpecChunk = 128;
+template <int DQ>
+__global__ void __launch_bounds__(256) k_spectral(const float* __restrict__ data, const int32_t* __restrict__ ids,
+                                                  int64_t n, int len, const double* __restrict__ tt,
+                                                  uint16_t* __restrict__ xs, float4* __restrict__ meta) {
+    constexpr int D = 4 * DQ, JC = kSpecChunk;
+    __shared__ float sx[64][JC + 1];
+    __shared__ double s_head[4][64], s_err[4][64], s_code[4][64];
+    const int lane = threadIdx.x & 63;
+    const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t n_tiles = (n + 63) / 64;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t p0 = tile * 64;
+        double acc[DQ];
+#pragma unroll
+        for (int r = 0; r < DQ; ++r) acc[r] = 0.0;
+        double xn = 0.0;
+        const double* tg = tt + g * DQ;
+        for (int j0 = 0; j0 < len; j0 += JC) {
+            const int jn = min(JC, len - j0);
+            __syncthreads();  // the previous chunk's points are no longer read
+            for (int e = threadIdx.x; e < 64 * JC; e += 256) {
+                const int r = e / JC, j = e % JC;
+                const int64_t p = p0 + r;
+                sx[r][j] = p < n && j < jn ? data[(int64_t)ids[p] * len + j0 + j] : 0.f;
+            }
+            __syncthreads();
+            for (int j = 0; j < jn; ++j) {
+                const double v = (double)sx[lane][j];
+                xn = fma(v, v, xn);
+                const double* tj = tg + (int64_t)(j0 + j) * D;
+#pragma unroll
+                for (int r = 0; r < DQ; ++r) acc[r] = fma(tj[r], v, acc[r]);
+            }
+        }
+        double hs = 0.0;
+#pragma unroll
+        for (int r = 0; r < DQ; ++r) hs = fma(acc[r], acc[r], hs);
+        s_head[g][lane] = hs;
+        __syncthreads();
+        const double tail = sqrt(fmax(0.0, xn - (((s_head[0][lane] + s_head[1][lane]) + s_head[2][lane]) + s_head[3][lane])));
+        if (g == 3) acc[DQ - 1] = tail;
+        const int64_t p = p0 + lane;
+        double e2 = 0.0, c2 = 0.0;
+        unsigned packed[DQ / 2];
+#pragma unroll
+        for (int r = 0; r < DQ; ++r) {
+            const uint16_t b = bf16_rne((float)acc[r]);
+            const double bv = (double)bf16_val(b);
+            e2 = fma(acc[r] - bv, acc[r] - bv, e2);
+            c2 = fma(bv, bv, c2);
+            if (r & 1) packed[r / 2] |= (unsigned)b << 16;
+            else packed[r / 2] = b;
+        }
+        if (p < n) {
+            uint4* dst = reinterpret_cast<uint4*>(xs + p * D + g * DQ);
+#pragma unroll
+            for (int c = 0; c < DQ / 8; ++c)
+                dst[c] = make_uint4(packed[4 * c], packed[4 * c + 1], packed[4 * c + 2], packed[4 * c + 3]);
+        }
+        s_err[g][lane] = e2;
+        s_code[g][lane] = c2;
+        __syncthreads();
+        if (g == 0 && p < n) {
+            const double E = ((s_err[0][lane] + s_err[1][lane]) + s_err[2][lane]) + s_err[3][lane];
+            const double C = ((s_code[0][lane] + s_code[1][lane]) + s_code[2][lane]) + s_code[3][lane];
+            const double nx = sqrt(xn);
+            meta[p] = make_float4((float)xn, up_norm((float)(E * (1.0 + 0x1p-40))) + (float)(0x1p-18 * nx) * 1.001f,
+                                  up_norm((float)(C * (1.0 + 0x1p-40))), 1.f);
+        }
+    }
+}
+
 }  // namespace
 
 // =============================================================================================
@@ -672,6 +758,22 @@ void launch_quantise(const float* data, const int32_t* ids, int64_t n, int len, 
     const bool vec = len % 4 == 0 && (reinterpret_cast<uintptr_t>(data) & 15) == 0;
     if (vec) k_quantise<true><<<grid_blocks(n, 4), 256, 0, s>>>(data, ids, n, len, len_pad, kind, xb, xf, meta);
     else k_quantise<false><<<grid_blocks(n, 4), 256, 0, s>>>(data, ids, n, len, len_pad, kind, xb, xf, meta);
+    ISAX_HIP(hipGetLastError());
+}
+
+void launch_spectral(const float* data, const int32_t* ids, int64_t n, int len, int D, const double* tt, uint16_t* xs,
+                     float4* meta, hipStream_t s) {
+    ProfScope ps("spectral", s);
+    if (len > 512 || D >= len || D < 64 || D > 256 || D % 64)
+        throw Error{ISAX_EINVAL, "the spectral copy needs len <= 512 and D in 64..256 (a multiple of 64) below len"};
+    const int64_t tiles = (n + 63) / 64;
+    const int grid = (int)std::min<int64_t>(tiles, 8192);
+    switch (D) {
+        case 64: k_spectral<16><<<grid, 256, 0, s>>>(data, ids, n, len, tt, xs, meta); break;
+        case 128: k_spectral<32><<<grid, 256, 0, s>>>(data, ids, n, len, tt, xs, meta); break;
+        case 192: k_spectral<48><<<grid, 256, 0, s>>>(data, ids, n, len, tt, xs, meta); break;
+        default: k_spectral<64><<<grid, 256, 0, s>>>(data, ids, n, len, tt, xs, meta); break;
+    }
     ISAX_HIP(hipGetLastError());
 }
 

@@ -55,7 +55,7 @@ __device__ inline float read_tau(const QueryArgs& a, int q, int k) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Query codes (row-padded to len_pad with zeros) and per-query factors; batch
+// Query codes (row-padded to dim with zeros) and per-query factors; batch
 // maxima of |q|, |e_q| + gamma |q~| and |q|^2 go to qmax[0..2].
 __device__ inline uint16_t bf16_rne(float x) {
     unsigned u = __float_as_uint(x);
@@ -130,6 +130,65 @@ __global__ void __launch_bounds__(64) k_quantise_queries(QueryArgs a, FilterArgs
             atomicMax(qmax + 0, __float_as_uint(nq));
             atomicMax(qmax + 1, __float_as_uint(cq));
             atomicMax(qmax + 2, __float_as_uint(up(qn)));
+        }
+    }
+}
+
+// Spectral codes of the queries: ext(q) = (y_0 .. y_{D-2}, |(y_{D-1} ..)|), y = T q,
+// computed in FP64 like the collection's copy (f.spec holds T transposed with a
+// zero column D - 1), then the same BF16 codes and factors as above.  ext(q)
+// is within 2^-18 |q| of the exact one (the tail norm comes from a difference
+// of squares, |q|^2 - |y_head|^2, whose FP64 error is below 2e-12 |q|^2); that
+// is added to |e_q|.  |ext(q)| = |q|, so |q| and |q|^2 keep their roles.
+__global__ void __launch_bounds__(64) k_quantise_queries_spec(QueryArgs a, FilterArgs f, unsigned* qmax) {
+    constexpr int RMAX = 4;  // D <= 256 coefficients over 64 lanes
+    const int q = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int D = f.dim;
+    const bool real = q < a.mq;
+    const float* x = a.Q + (int64_t)q * a.len;
+    double y[RMAX] = {0.0, 0.0, 0.0, 0.0};
+    double qn = 0.0;
+    for (int j = 0; j < a.len; ++j) {
+        const double v = real ? (double)x[j] : 0.0;
+        qn = fma(v, v, qn);
+        const double* tj = f.spec + (int64_t)j * D;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r)
+            if (lane + 64 * r < D) y[r] = fma(tj[lane + 64 * r], v, y[r]);
+    }
+    double head = 0.0;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) head = fma(y[r], y[r], head);
+    for (int o = 32; o > 0; o >>= 1) head += __shfl_xor(head, o, 64);
+    const double tail = sqrt(fmax(0.0, qn - head));
+    double en = 0.0, tn = 0.0;
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+        const int i = lane + 64 * r;
+        if (i >= D) continue;
+        const double v = i == D - 1 ? tail : y[r];
+        const uint16_t b = bf16_rne((float)v);
+        static_cast<uint16_t*>(f.qq)[(int64_t)q * D + i] = b;
+        const double vt = (double)__uint_as_float((unsigned)b << 16);
+        en = fma(v - vt, v - vt, en);
+        tn = fma(vt, vt, tn);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        en += __shfl_xor(en, o, 64);
+        tn += __shfl_xor(tn, o, 64);
+    }
+    if (lane == 0) {
+        const double nq = sqrt(qn);
+        const float fq = up((float)nq);
+        const float eq = up((float)(sqrt(en) * (1.0 + 0x1p-40) + 0x1p-18 * nq));
+        const float cq = up(eq + f.gamma * up((float)(sqrt(tn) * (1.0 + 0x1p-40))));
+        const float qn32 = (float)qn;
+        f.qmeta[q] = make_float4(qn32, fq, cq, 1.f);
+        if (real) {
+            atomicMax(qmax + 0, __float_as_uint(fq));
+            atomicMax(qmax + 1, __float_as_uint(cq));
+            atomicMax(qmax + 2, __float_as_uint(up(qn32)));
         }
     }
 }
@@ -211,7 +270,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
     // per-row thresholds H = tau (1 + eps) - |q|^2 (refreshed periodically; BF16 keeps H / 2)
     // and FP8 row scales
     auto refresh_H = [&]() {
-        for (int i = threadIdx.x; i < C::QPB; i += C::THREADS) {
+        // (rare: its addresses are recomputed here, through an empty asm, rather than kept in
+        // registers across the tile loop)
+        int i0 = threadIdx.x;
+        asm volatile("" : "+v"(i0));
+        for (int i = i0; i < C::QPB; i += C::THREADS) {
             const int q = qt * C::QPB + i;
             float H = -kInf;
             if (q < a.mq && !((a.rerun || a.skip_done) && a.done[q]))
@@ -521,7 +584,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter_bf16(QueryArgs a, FilterA
             fa[t][s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const i32x4*>(src + s * 16));
     }
     auto refresh_H = [&]() {
-        for (int i = threadIdx.x; i < C::QPB; i += C::THREADS) {
+        // (rare: its addresses are recomputed here, through an empty asm, rather than kept in
+        // registers across the tile loop)
+        int i0 = threadIdx.x;
+        asm volatile("" : "+v"(i0));
+        for (int i = i0; i < C::QPB; i += C::THREADS) {
             const int q = qt * C::QPB + i;
             float H = -kInf;
             if (q < a.mq && !((a.rerun || a.skip_done) && a.done[q]))
@@ -941,13 +1008,19 @@ int filter_len_pad(int len) { return (len + 63) / 64 * 64; }
 
 void launch_quantise_queries(const QueryArgs& a, const FilterArgs& f, int mq_pad, unsigned* qmax, hipStream_t s) {
     ProfScope ps("quantise_queries", s);
-    k_quantise_queries<<<mq_pad, 64, 0, s>>>(a, f, filter_len_pad(a.len), qmax);
+    if (f.spec) {
+        if (f.kind != 0 || f.dim < 64 || f.dim > 256 || f.dim % 64)
+            throw Error{ISAX_EINVAL, "internal: spectral codes need BF16 and 64..256 coefficients"};
+        k_quantise_queries_spec<<<mq_pad, 64, 0, s>>>(a, f, qmax);
+    } else {
+        k_quantise_queries<<<mq_pad, 64, 0, s>>>(a, f, f.dim, qmax);
+    }
     ISAX_HIP(hipGetLastError());
 }
 
 void launch_filter(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax, hipStream_t s) {
     ProfScope ps(f.kind == 0 ? "filter_bf16" : "filter_fp8", s);
-    const int lp = filter_len_pad(a.len);
+    const int lp = f.dim;
     if (f.kind == 0) {
         switch (lp) {
             case 64: launch_filter_t<0, 4, 2, 8>(a, f, qmax, s); break;
@@ -985,8 +1058,8 @@ void launch_refine_filtered(const QueryArgs& a, const FilterArgs& f, hipStream_t
 
 // Query rows the BF16 filter computes for a batch of mq queries: its block
 // class (the dispatch of launch_filter) times the blocks.
-int filter_rows_bf16(int len, int mq) {
-    const int lp = filter_len_pad(len);
+int filter_rows_bf16(int dim, int mq) {
+    const int lp = dim;
     int qpb = lp <= 256 ? 512 : 256;  // <MT = 2, 8 waves> below 320, <1, 8> from 320
     if ((lp == 128 || lp == 256) && mq <= 256) qpb = mq <= 64 ? 64 : mq <= 128 ? 128 : 256;
     return (mq + qpb - 1) / qpb * qpb;
@@ -1008,7 +1081,7 @@ void launch_copy_rows(const QueryArgs& sa, const FilterArgs& sf, const QueryArgs
                       const int2* map, int n, bool free_src, hipStream_t s, bool rows_too) {
     if (n <= 0) return;
     ProfScope ps("copy_rows", s);
-    k_copy_rows<<<n, 256, 0, s>>>(sa, sf, da, df, map, free_src ? 1 : 0, rows_too ? 1 : 0, filter_len_pad(sa.len),
+    k_copy_rows<<<n, 256, 0, s>>>(sa, sf, da, df, map, free_src ? 1 : 0, rows_too ? 1 : 0, sf.dim,
                                   sf.kind == 0 ? 2 : 1);
     ISAX_HIP(hipGetLastError());
 }

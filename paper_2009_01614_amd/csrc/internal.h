@@ -177,6 +177,11 @@ struct isax_index {
     float4* meta_bf16 = nullptr;    // [n] {|x|^2, |e_x| (up), |x~| (up), 1}
     uint8_t* x_fp8 = nullptr;       // [n][len] E4M3 codes
     float4* meta_fp8 = nullptr;     // [n] {|x|^2, |e_x| (up), |x~| (up), scale}
+    // spectral copy: BF16 of ext(x) = (D - 1 leading DCT-II coefficients, norm of the rest)
+    int spec_dim = 0;               // D (0: none)
+    uint16_t* x_spec = nullptr;     // [n][D] BF16 bits, leaf order
+    float4* meta_spec = nullptr;    // [n] {|x|^2, |ext(x) - x~| (up), |x~| (up), 1}
+    double* spec_t = nullptr;       // [len][D] the transform, column D - 1 zero (FP64)
     int64_t device_bytes = 0;
     std::vector<void*> owned;
     ~isax_index();

@@ -119,9 +119,11 @@ void launch_scatter_answers(const int64_t* ids, const float* dists, const int32_
 // Reduced-precision filter (filter_kernels.hip).
 struct FilterArgs {
     int kind;                 // 0 BF16, 1 FP8
-    const void* xq;           // collection codes [n][len] (uint16 BF16 bits or uint8 E4M3)
+    int dim;                  // codes per row: the padded length, or D of the spectral copy
+    const double* spec;       // spectral copy: the transform [len][dim] (FP64), else null
+    const void* xq;           // collection codes [n][dim] (uint16 BF16 bits or uint8 E4M3)
     const float4* xmeta;      // [n] {|x|^2, |e_x|, |x~|, scale}
-    void* qq;                 // query codes [mq_pad][len_pad]
+    void* qq;                 // query codes [mq_pad][dim]
     int mq_pad;               // rows of qq and qmeta
     float4* qmeta;            // [mq_pad] {|q|^2, |e_q|, |q~|, scale}
     float gamma;              // accumulation error factor
@@ -152,7 +154,7 @@ __host__ __device__ inline int64_t filter_other_tile(int64_t v, int R) {
 }
 int filter_len_pad(int len);              // rows of the reduced-precision copies are padded to this
 int filter_queries_per_block(int len);    // query codes are padded to a multiple of this
-int filter_rows_bf16(int len, int mq);    // query rows the BF16 filter computes for mq queries
+int filter_rows_bf16(int dim, int mq);    // query rows the BF16 filter computes for mq queries (dim codes per row)
 void launch_quantise_queries(const QueryArgs& a, const FilterArgs& f, int mq_pad, unsigned* qmax, hipStream_t s);
 void launch_filter(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax, hipStream_t s);
 void launch_refine_filtered(const QueryArgs& a, const FilterArgs& f, hipStream_t s);

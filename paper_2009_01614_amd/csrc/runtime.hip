@@ -427,6 +427,33 @@ float* upload_beta(int c, hipStream_t s, DevBuf* tmp, isax_index* idx, const std
     return d;
 }
 
+// The spectral copy's transform, transposed: entry (j, i) = T_ij of the
+// orthonormal DCT-II of length len, T_ij = sqrt((i ? 2 : 1) / len)
+// cos(pi i (2j + 1) / (2 len)), for coefficients i < D - 1; column D - 1 (the
+// slot of the tail norm) is zero.  The angle is reduced modulo its period
+// 4 len (in units of pi / (2 len)) before the cosine.
+std::vector<double> spectral_table(int len, int D) {
+    std::vector<double> t((size_t)len * D, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < D - 1; ++i) {
+        const double c = std::sqrt((i == 0 ? 1.0 : 2.0) / len);
+        for (int j = 0; j < len; ++j) {
+            const int64_t k = (int64_t)i * (2 * j + 1) % (4 * len);
+            t[(size_t)j * D + i] = c * std::cos(pi * (double)k / (2.0 * len));
+        }
+    }
+    return t;
+}
+
+// D of the spectral copy for an option value (0: three quarters of the padded
+// length rounded down to a multiple of 64, within 64..256).  At 100M x 256
+// random walks, D = 128 left 27K candidates per far query (sigma = 1) and
+// its filter pass was slower than the full rows'; D = 192 left 3.6K and
+// took 0.88 of the full pass.
+int spectral_dim_for(int len, int opt) {
+    return opt ? opt : std::min(256, std::max(64, filter_len_pad(len) * 3 / 4 / 64 * 64));
+}
+
 isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int32_t c, const isax_build_options* opt) {
     validate_series_shape(data, n, len, w, c);
     isax_build_options o{};
@@ -435,8 +462,14 @@ isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int
     ISAX_REQUIRE(leaf >= 16 && leaf <= kMaxLeaf, "leaf_size must be in 16..1024");
     const int key_bits = o.key_bits ? o.key_bits : default_key_bits(w, c);
     ISAX_REQUIRE(key_bits >= 8 && key_bits <= 64 && key_bits % 8 == 0, "key_bits must be a multiple of 8 in 8..64");
-    ISAX_REQUIRE(o.precision >= 0 && o.precision <= 7,
-                 "precision must be a bitmask of 1 (BF16), 2 (FP8) and 4 (FP32 rows in leaf order)");
+    ISAX_REQUIRE(o.precision >= 0 && o.precision <= 15,
+                 "precision must be a bitmask of 1 (BF16), 2 (FP8), 4 (FP32 rows in leaf order) and 8 (spectral)");
+    ISAX_REQUIRE(o.reserved == 0, "reserved must be 0");
+    const int spec_dim = (o.precision & 8) ? spectral_dim_for(len, o.spectral_dim) : 0;
+    ISAX_REQUIRE(!(o.precision & 8) || (len <= 512 && spec_dim % 64 == 0 && spec_dim >= 64 && spec_dim <= 256 &&
+                                        spec_dim < len),
+                 "the spectral copy needs len <= 512 and spectral_dim a multiple of 64 in 64..256, below len");
+    ISAX_REQUIRE((o.precision & 8) || o.spectral_dim == 0, "spectral_dim needs precision bit 8");
     ISAX_REQUIRE(o.edges == ISAX_EDGES_NORMAL || o.edges == ISAX_EDGES_EMPIRICAL, "edges must be 0 or 1");
     require_device_accessible(data, "data");
     hipStream_t s = static_cast<hipStream_t>(o.stream);
@@ -507,6 +540,16 @@ isax_index* build_impl(const float* data, int64_t n, int32_t len, int32_t w, int
         idx->x_fp8 = own<uint8_t>(idx.get(), (size_t)n * lp);
         idx->meta_fp8 = own<float4>(idx.get(), n);
         launch_quantise(data, idx->ids_sorted, n, len, lp, 1, nullptr, idx->x_fp8, idx->meta_fp8, s);
+    }
+    if (o.precision & 8) {
+        const std::vector<double> t = spectral_table(len, spec_dim);
+        idx->spec_dim = spec_dim;
+        idx->spec_t = own<double>(idx.get(), t.size());
+        ISAX_HIP(hipMemcpyAsync(idx->spec_t, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        idx->x_spec = own<uint16_t>(idx.get(), (size_t)n * spec_dim);
+        idx->meta_spec = own<float4>(idx.get(), n);
+        launch_spectral(data, idx->ids_sorted, n, len, spec_dim, idx->spec_t, idx->x_spec, idx->meta_spec, s);
+        ISAX_HIP(hipStreamSynchronize(s));  // t is read by the copy above
     }
     words = DevBuf();
     keys = DevBuf();
@@ -787,15 +830,21 @@ constexpr int kPreStride = 16;
 // sigma 0.01 and 0.1, k = 1 and 10): the pre-screen scales it by this much.
 constexpr double kPreFactor = 1.5;
 
+// Codes per row the BF16 filter reads: D of the spectral copy when the index
+// holds one (unless the query asks for the full rows), else the padded length.
+int bf16_dim(const isax_index* idx, int flags) {
+    return idx->x_spec && !(flags & ISAX_QF_FULL_ROWS) ? idx->spec_dim : filter_len_pad(idx->len);
+}
+
 // The planner: `fixed` queries go to the filter; of the others, the j of
 // largest cost join them, j minimising filter_cost(all of them) + the cost of
 // the queries left on the iSAX path.  Returns the filter's set.
-double filter_cost(const isax_index* idx, int f);
+double filter_cost(const isax_index* idx, int f, int dim);
 // Keeping any query on the index path also costs its own passes and
 // synchronisations (leaf pass, rounds, the second plan): about this much.
 constexpr double kIndexFixed = 1.5e-3;
 std::vector<char> plan_far(const isax_index* idx, const std::vector<double>& cost, const std::vector<char>& fixed,
-                           double fscale = 1.0) {
+                           double fscale, int dim) {
     const int mq = (int)cost.size();
     std::vector<int> order;
     int n0 = 0;
@@ -810,11 +859,11 @@ std::vector<char> plan_far(const isax_index* idx, const std::vector<double>& cos
     }
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
     const int n = (int)order.size();
-    double best = fscale * filter_cost(idx, n0) + rest + (n > 0 ? kIndexFixed : 0.0);
+    double best = fscale * filter_cost(idx, n0, dim) + rest + (n > 0 ? kIndexFixed : 0.0);
     int bj = 0;
     for (int j = 1; j <= n; ++j) {
         rest -= cost[order[j - 1]];
-        const double c = fscale * filter_cost(idx, n0 + j) + rest + (j < n ? kIndexFixed : 0.0);
+        const double c = fscale * filter_cost(idx, n0 + j, dim) + rest + (j < n ? kIndexFixed : 0.0);
         if (c < best) {
             best = c;
             bj = j;
@@ -825,12 +874,12 @@ std::vector<char> plan_far(const isax_index* idx, const std::vector<double>& cos
     return far;
 }
 
-double filter_cost(const isax_index* idx, int f) {
+double filter_cost(const isax_index* idx, int f, int dim) {
     if (f == 0) return 0.0;
-    const double stream = (double)idx->n * (filter_len_pad(idx->len) * 2 + 16) / kFilterStreamBps;
-    const int rows = filter_rows_bf16(idx->len, f);
+    const double stream = (double)idx->n * (dim * 2 + 16) / kFilterStreamBps;
+    const int rows = filter_rows_bf16(dim, f);
     const double rate = rows % 512 == 0 ? kFilterFlopsWide : rows == 256 ? kFilterFlopsMid : kFilterFlopsNarrow;
-    const double mfma = 2.0 * idx->len * (double)idx->n * rows / rate;
+    const double mfma = 2.0 * dim * (double)idx->n * rows / rate;
     return std::max(stream, mfma) + f * kFilterPerQuery;
 }
 
@@ -862,7 +911,8 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     QueryArgs& a = b.a;
     const int mq = a.mq;
     const double fscale = (a.flags & ISAX_QF_FILTER_CHEAP) ? 1e-3 : (a.flags & ISAX_QF_FILTER_DEAR) ? 1e3 : 1.0;
-    if (limit == 0 && !(a.flags & ISAX_QF_NO_SHORTCUT) && fscale * filter_cost(idx, mq) < kHybridFixed) {
+    const int fdim = bf16_dim(idx, a.flags);
+    if (limit == 0 && !(a.flags & ISAX_QF_NO_SHORTCUT) && fscale * filter_cost(idx, mq, fdim) < kHybridFixed) {
         run_batch(idx, b, ISAX_MODE_BF16, s);
         return;
     }
@@ -897,7 +947,7 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
             cost[q] = kPreFactor * kp[q] *
                       ((leaf_words + kFarShare * leaf_refine) * n1 + (leaf_words + kNearShare * leaf_refine) * (est - n1));
         }
-        pre = plan_far(idx, cost, pre, fscale);
+        pre = plan_far(idx, cost, pre, fscale, fdim);
         double total = 0.0;
         int n_pre = 0;
         for (int q = 0; q < mq; ++q) {
@@ -911,7 +961,7 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
             run_batch(idx, b, ISAX_MODE_BF16, s);
             return;
         }
-        if (n_pre == 0 && total < 0.5 * fscale * filter_cost(idx, mq)) {
+        if (n_pre == 0 && total < 0.5 * fscale * filter_cost(idx, mq, fdim)) {
             // the index is far cheaper than any filter pass: the plain index path
             leaf_pass(b, kLeafListMax, s);
             const std::vector<int64_t> cnt = leaves_initial(b, s);
@@ -996,7 +1046,7 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
     if (limit > 0) {
         for (int q = 0; q < mq; ++q) b.skip[q] = est[q] > limit;
     } else {
-        const std::vector<char> far = plan_far(idx, cost, pre, fscale);
+        const std::vector<char> far = plan_far(idx, cost, pre, fscale, fdim);
         for (int q = 0; q < mq; ++q) b.skip[q] = far[q];
     }
     for (int q = 0; q < mq; ++q)
@@ -1178,10 +1228,14 @@ int query_impl(isax_index* idx, const float* Q, int64_t m, int32_t k, int64_t* o
     ISAX_REQUIRE(o.hybrid_leaves >= 0, "hybrid_leaves must be >= 0");
     ISAX_REQUIRE(o.candidate_capacity >= 0 && o.batch >= 0, "candidate_capacity and batch must be >= 0");
     ISAX_REQUIRE((o.flags & ~(ISAX_QF_NO_SHARING | ISAX_QF_NO_EARLY_ABANDON | ISAX_QF_NO_BEST_FIRST |
-                              ISAX_QF_NO_SHORTCUT | ISAX_QF_FILTER_CHEAP | ISAX_QF_FILTER_DEAR)) == 0,
+                              ISAX_QF_NO_SHORTCUT | ISAX_QF_FILTER_CHEAP | ISAX_QF_FILTER_DEAR |
+                              ISAX_QF_FULL_ROWS)) == 0,
                  "unknown flag");
-    ISAX_REQUIRE((o.mode != ISAX_MODE_BF16 && o.mode != ISAX_MODE_HYBRID) || idx->x_bf16,
-                 "index was built without the BF16 copy");
+    ISAX_REQUIRE((o.mode != ISAX_MODE_BF16 && o.mode != ISAX_MODE_HYBRID) || idx->x_bf16 || idx->x_spec,
+                 "index was built without a BF16 copy (precision bit 1 or 8)");
+    ISAX_REQUIRE(!(o.flags & ISAX_QF_FULL_ROWS) || (o.mode != ISAX_MODE_BF16 && o.mode != ISAX_MODE_HYBRID) ||
+                     idx->x_bf16,
+                 "ISAX_QF_FULL_ROWS needs the full-length BF16 copy (precision bit 1)");
     ISAX_REQUIRE(o.mode != ISAX_MODE_FP8 || idx->x_fp8, "index was built without the FP8 copy");
     ISAX_REQUIRE(o.metric == ISAX_METRIC_ED || o.metric == ISAX_METRIC_DTW, "unknown metric");
     if (o.metric == ISAX_METRIC_ED) {
@@ -1309,12 +1363,11 @@ int guarded(F&& f) {
 // Reduced-precision filter batch (kernels in filter_kernels.hip)
 namespace {
 
-// gamma: FP32 accumulation error of len_pad exact products, any order and
+// gamma: FP32 accumulation error of dim exact products, any order and
 // rounding (2u per add).  kappa: relative slack on |q|^2 + |x|^2 covering the
 // FP32 norms and the epilogue, never below 2^-14.
-void filter_constants(int len, float* gamma, float* kappa) {
-    const int lp = filter_len_pad(len);
-    *gamma = (float)(lp * std::ldexp(1.0, -23));
+void filter_constants(int len, int dim, float* gamma, float* kappa) {
+    *gamma = (float)(dim * std::ldexp(1.0, -23));
     double k = std::ldexp(1.0, -14);
     while (k < 8.0 * len * std::ldexp(1.0, -24)) k *= 2;
     *kappa = (float)k;
@@ -1337,12 +1390,11 @@ void alloc_filter_cands(FilterScratch& fs, int mq, int64_t fcap, hipStream_t s) 
 }
 
 // The filter's per-query arrays (query codes, factors, counts) in one block.
-Arena filter_arena(FilterScratch& fs, unsigned char** qq, const isax_index* idx, int mq, int kind) {
-    const int lp = filter_len_pad(idx->len);
+Arena filter_arena(FilterScratch& fs, unsigned char** qq, const isax_index* idx, int mq, int kind, int dim) {
     const int qpb = filter_queries_per_block(idx->len);
     fs.mq_pad = (mq + qpb - 1) / qpb * qpb;
     Arena ar;
-    ar.add(qq, (size_t)fs.mq_pad * lp * (kind == 0 ? 2 : 1));
+    ar.add(qq, (size_t)fs.mq_pad * dim * (kind == 0 ? 2 : 1));
     ar.add(&fs.f.qmeta, fs.mq_pad);
     ar.add(&fs.qmax, 4);
     ar.add(&fs.f.fcount, mq);
@@ -1354,12 +1406,21 @@ void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, 
                   hipStream_t s) {
     FilterArgs& f = fs.f;
     f.kind = mode == ISAX_MODE_BF16 ? 0 : 1;
-    f.xq = f.kind == 0 ? static_cast<const void*>(idx->x_bf16) : static_cast<const void*>(idx->x_fp8);
-    f.xmeta = f.kind == 0 ? idx->meta_bf16 : idx->meta_fp8;
-    filter_constants(idx->len, &f.gamma, &f.kappa);
+    if (f.kind == 0 && idx->x_spec && !(a.flags & ISAX_QF_FULL_ROWS)) {
+        f.dim = idx->spec_dim;
+        f.spec = idx->spec_t;
+        f.xq = idx->x_spec;
+        f.xmeta = idx->meta_spec;
+    } else {
+        ISAX_REQUIRE(f.kind == 1 || idx->x_bf16, "index was built without the full-length BF16 copy");
+        f.dim = filter_len_pad(idx->len);
+        f.xq = f.kind == 0 ? static_cast<const void*>(idx->x_bf16) : static_cast<const void*>(idx->x_fp8);
+        f.xmeta = f.kind == 0 ? idx->meta_bf16 : idx->meta_fp8;
+    }
+    filter_constants(idx->len, f.dim, &f.gamma, &f.kappa);
     f.phase = 0;
     unsigned char* qq = nullptr;
-    fs.mem = filter_arena(fs, &qq, idx, a.mq, f.kind).commit(s);
+    fs.mem = filter_arena(fs, &qq, idx, a.mq, f.kind, f.dim).commit(s);
     f.qq = qq;
     f.mq_pad = fs.mq_pad;
     alloc_filter_cands(fs, a.mq, fcap, s);
@@ -1390,7 +1451,7 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     if (n_tiles >= 16 * kSub) phases = {1, 2};
     else phases = {0};
     const int qpb = filter_queries_per_block(idx->len);
-    const double bytes_all = (double)idx->n * (filter_len_pad(idx->len) * (fs.f.kind == 0 ? 2 : 1) + 16) *
+    const double bytes_all = (double)idx->n * (fs.f.dim * (fs.f.kind == 0 ? 2 : 1) + 16) *
                              ((fs.mq_pad + qpb - 1) / qpb);
     std::vector<unsigned> cnt(a.mq);
     for (int attempt = 0;; ++attempt) {
@@ -1516,7 +1577,7 @@ QueryArgs rows_view(const QueryArgs& a, int m) {
 
 StepTable* step_table_create(isax_index* idx, int mode, int slots, int chunks, hipStream_t s) {
     ISAX_REQUIRE(mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8, "step-level serving runs the BF16 or FP8 filter");
-    ISAX_REQUIRE(mode != ISAX_MODE_BF16 || idx->x_bf16, "index was built without the BF16 copy");
+    ISAX_REQUIRE(mode != ISAX_MODE_BF16 || idx->x_bf16 || idx->x_spec, "index was built without a BF16 copy");
     ISAX_REQUIRE(mode != ISAX_MODE_FP8 || idx->x_fp8, "index was built without the FP8 copy");
     ISAX_REQUIRE(slots >= 1 && slots <= 4096 && chunks >= 1 && chunks <= 1024, "bad serving table size");
     std::unique_ptr<StepTable> t(new StepTable);
@@ -1699,7 +1760,7 @@ size_t batch_scratch_bound(const isax_index* idx, int mq, int kmax, int cap, int
     auto filter = [&](int kind) {
         FilterScratch fs;
         unsigned char* qq = nullptr;
-        return blk(filter_arena(fs, &qq, idx, mq, kind).off) + blk((size_t)mq * fcap * 4);
+        return blk(filter_arena(fs, &qq, idx, mq, kind, filter_len_pad(idx->len)).off) + blk((size_t)mq * fcap * 4);
     };
     size_t tot = batch;
     if (mode == ISAX_MODE_INDEX && !(flags & ISAX_QF_NO_BEST_FIRST)) tot += lists;
@@ -1814,6 +1875,8 @@ int isax_index_get_info(const isax_index* idx, isax_index_info* out) {
         out->has_fp8 = idx->x_fp8 != nullptr;
         out->has_sorted_rows = idx->xs != nullptr;
         out->edges = idx->edges;
+        out->spectral_dim = idx->spec_dim;
+        out->reserved = 0;
         out->n_leaves = idx->n_leaves;
         out->max_abs = idx->max_abs;
         out->delta = idx->delta;
@@ -1874,7 +1937,7 @@ int isax_filter_scores(isax_index* idx, const float* queries, int64_t m, int32_t
     return guarded([&] {
         ISAX_REQUIRE(idx != nullptr, "index is NULL");
         ISAX_REQUIRE(mode == ISAX_MODE_BF16 || mode == ISAX_MODE_FP8, "mode must be ISAX_MODE_BF16 or ISAX_MODE_FP8");
-        ISAX_REQUIRE(mode != ISAX_MODE_BF16 || idx->x_bf16, "index was built without the BF16 copy");
+        ISAX_REQUIRE(mode != ISAX_MODE_BF16 || idx->x_bf16 || idx->x_spec, "index was built without a BF16 copy");
         ISAX_REQUIRE(mode != ISAX_MODE_FP8 || idx->x_fp8, "index was built without the FP8 copy");
         ISAX_REQUIRE(m >= 0 && m <= 1024, "m must be in 0..1024");
         if (m == 0) return ISAX_OK;

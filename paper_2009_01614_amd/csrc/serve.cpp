@@ -231,7 +231,7 @@ isax_server* isax_server_create(isax_index* const* collections, int32_t n_collec
             isax::set_error(ISAX_EINVAL, "collections must be non-NULL indexes on one device");
             return nullptr;
         }
-        if (((opt.mode == ISAX_MODE_BF16 || opt.mode == ISAX_MODE_HYBRID) && !idx->x_bf16) ||
+        if (((opt.mode == ISAX_MODE_BF16 || opt.mode == ISAX_MODE_HYBRID) && !idx->x_bf16 && !idx->x_spec) ||
             (opt.mode == ISAX_MODE_FP8 && !idx->x_fp8)) {
             isax::set_error(ISAX_EINVAL, "a collection lacks the reduced-precision copy the mode needs");
             return nullptr;

@@ -53,7 +53,11 @@ def main():
     ap.add_argument("--m", type=int, default=1000)
     ap.add_argument("--k", type=int, default=1)
     ap.add_argument("--mode", default="hybrid", choices=["index", "scan", "bf16", "fp8", "hybrid"])
-    ap.add_argument("--modes", default="index,scan,bf16,fp8", help="modes measured once each besides the timed one")
+    ap.add_argument("--modes", default="index,scan,bf16,bf16_full,fp8",
+                    help="modes measured once each besides the timed one (bf16_full: BF16 filter on the full rows)")
+    ap.add_argument("--no-spectral", action="store_true",
+                    help="build no spectral copy: the BF16 filter (and hybrid) then read the full-length rows")
+    ap.add_argument("--spectral-dim", type=int, default=0, help="coefficients of the spectral copy (0: the default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-series", type=int, default=10_000_000)
     ap.add_argument("--cpu-sample-queries", type=int, default=128)
@@ -111,18 +115,23 @@ def main():
     torch.cuda.synchronize()
 
     # ---------------------------------------------------------------- build
+    # the BF16 filter (and hybrid mode) read the spectral copy unless --no-spectral; bf16_full reads the rows
+    bf16_bits = isax.PREC_BF16 if args.no_spectral else isax.PREC_SPECTRAL
+    bits = {"bf16": bf16_bits, "fp8": isax.PREC_FP8, "hybrid": bf16_bits, "bf16_full": isax.PREC_BF16}
     precision = 0
     for md in set(args.modes.split(",")) | {args.mode}:
-        precision |= {"bf16": 1, "fp8": 2, "hybrid": 1}.get(md, 0)
-    precision |= {"bf16": 1, "fp8": 2, "hybrid": 1}.get(args.serve_mode, 0) if not args.no_serving else 0
+        precision |= bits.get(md, 0)
+    precision |= bits.get(args.serve_mode, 0) if not args.no_serving else 0
+    sdim = args.spectral_dim if precision & isax.PREC_SPECTRAL else 0
     log("building the index (twice; the second is timed)")
-    idx = isax.Index(X, 16, 8, precision=precision)
+    idx = isax.Index(X, 16, 8, precision=precision, spectral_dim=sdim)
     del idx
     torch.cuda.synchronize()
     isax.profile_enable(True)
     isax.profile_reset()
     t0 = time.perf_counter()
-    idx = isax.Index(X, 16, 8, precision=precision)
+    idx = isax.Index(X, 16, 8, precision=precision, spectral_dim=sdim)
+    spec_dim = idx.info()["spectral_dim"]
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     build_prof = isax.profile_read()
@@ -161,11 +170,14 @@ def main():
     avg_ms = dom["total_ms"] / max(dom["launches"], 1)
     if dom_name.startswith("filter_"):
         dt_ = dom_name.split("_")[1]
-        per_launch_flop = 2.0 * L * n * m_filter / max(dom["launches"] / args.steps, 1)
+        # 2 flops per coefficient of the copy the filter reads, per (query, series) pair
+        fdim = spec_dim if (dt_ == "bf16" and spec_dim) else L
+        per_launch_flop = 2.0 * fdim * n * m_filter / max(dom["launches"] / args.steps, 1)
         achieved = per_launch_flop / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 1), "peak": PEAK_TFLOPS[dt_], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_TFLOPS[dt_], 4), "traffic": None, "kernel": "k_filter",
-                "avg_launch_ms": round(avg_ms, 3), "algorithmic_flop_per_launch": per_launch_flop}
+                "avg_launch_ms": round(avg_ms, 3), "algorithmic_flop_per_launch": per_launch_flop,
+                "flop_per_pair": 2 * fdim}
     elif dom_name == "brute_scan":
         per_launch_flop = 3.0 * L * n * m / max(dom["launches"] / args.steps, 1)
         achieved = per_launch_flop / (avg_ms * 1e-3) / 1e12
@@ -206,7 +218,10 @@ def main():
             continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ids_m, _ = idx.query(Q, k=k, mode=md, stream=stream)
+        if md == "bf16_full":
+            ids_m, _ = idx.query(Q, k=k, mode="bf16", stream=stream, flags=isax.QF_FULL_ROWS)
+        else:
+            ids_m, _ = idx.query(Q, k=k, mode=md, stream=stream)
         torch.cuda.synchronize()
         modes_qps[md] = round(m / (time.perf_counter() - t0), 1)
         assert torch.equal(ids_m, ids), f"mode {md} disagrees with {args.mode}"
@@ -307,7 +322,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{n} x {L} z-normalised FP32 random walks, 16 segments, 8-bit iSAX; {m} noisy-copy "
                                f"queries (sigma 0.01/0.1/1), exact k={k}",
-                   "mode": args.mode, "refine_dtype": "f32", "source_hit_rate": hit, "hybrid_split": split},
+                   "mode": args.mode, "refine_dtype": "f32", "source_hit_rate": hit, "hybrid_split": split,
+                   "filter_copy": f"spectral, {spec_dim} of {L} coefficients" if spec_dim else "full rows"},
         "build_s": round(build_s, 4), "build_isax_only_s": round(build_plain_s, 4),
         "build_kernels_ms": {kk: round(v["total_ms"], 3) for kk, v in build_prof.items()},
         "modes_qps": modes_qps, "serving": serving, "kernels": kernels,
@@ -508,22 +524,30 @@ def sigma_report(args, dev):
     log(f"generating {n} x {L}")
     X = workload.random_walks(n, L, seed=20090163, device=dev)
     Q, src, sig = workload.noisy_queries(X, m, seed=20091163)
-    idx = isax.Index(X, 16, 8, precision=1)
+    prec = isax.PREC_BF16 | (0 if args.no_spectral else isax.PREC_SPECTRAL)
+    idx = isax.Index(X, 16, 8, precision=prec, spectral_dim=args.spectral_dim if not args.no_spectral else 0)
     out = {"metric": "exact k-NN queries/s and pruning by query noise level",
-           "config": {"workload": f"{n} x {L} random walks, {m} noisy queries split by sigma"}, "by_sigma": {}}
+           "config": {"workload": f"{n} x {L} random walks, {m} noisy queries split by sigma",
+                      "spectral_dim": idx.info()["spectral_dim"],
+                      "timing": "best of 3 calls per cell, one batch of the third of the queries"}, "by_sigma": {}}
+    modes = ("bf16", "index", "hybrid") + (() if args.no_spectral else ("bf16_full",))
     for sg in (0.01, 0.1, 1.0):
         sel = torch.from_numpy(np.where(sig == sg)[0]).to(dev)
         Qs = Q[sel].contiguous()
         rec = {"queries": int(Qs.shape[0])}
         for k in (1, 10, 100):
-            for mode in ("bf16", "index", "hybrid"):
-                idx.query(Qs[:8].contiguous(), k=k, mode=mode)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                res = idx.query(Qs, k=k, mode=mode)
-                torch.cuda.synchronize()
-                rec[f"{mode}_k{k}_qps"] = round(Qs.shape[0] / (time.perf_counter() - t0), 1)
-                if mode != "bf16":
+            for mode in modes:
+                kw = {"mode": "bf16", "flags": isax.QF_FULL_ROWS} if mode == "bf16_full" else {"mode": mode}
+                idx.query(Qs[:8].contiguous(), k=k, **kw)
+                best = float("inf")
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    res = idx.query(Qs, k=k, **kw)
+                    torch.cuda.synchronize()
+                    best = min(best, time.perf_counter() - t0)
+                rec[f"{mode}_k{k}_qps"] = round(Qs.shape[0] / best, 1)
+                if mode in ("index", "hybrid"):
                     res = idx.query(Qs, k=k, mode=mode, stats=True)  # untimed
                 if mode == "hybrid":
                     rec[f"hybrid_k{k}_index_share"] = round(

@@ -300,7 +300,12 @@ int isax_filter_scores(isax_index* idx, const float* queries, int64_t m, int32_t
 
 /* ------------------------------------------------------- kernel timing */
 /* When enabled, every library kernel launch is bracketed by HIP events on its
- * own stream; isax_profile_read() returns per-kernel totals (host out). */
+ * own stream; isax_profile_read() returns per-kernel totals (host out).  One
+ * entry is a count, not a kernel: "filter_full_rows_switch" (in
+ * algorithmic_bytes) counts the filter passes that moved from the spectral
+ * copy to the full rows after their second sample (both copies present: the
+ * sample's candidates, extrapolated to the rest of the collection, would cost
+ * more to refine than the spectral copy saves). */
 typedef struct isax_profile_entry {
     char name[48];
     int64_t launches;

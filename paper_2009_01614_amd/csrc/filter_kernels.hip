@@ -140,22 +140,27 @@ __global__ void __launch_bounds__(64) k_quantise_queries(QueryArgs a, FilterArgs
 // is within 2^-18 |q| of the exact one (the tail norm comes from a difference
 // of squares, |q|^2 - |y_head|^2, whose FP64 error is below 2e-12 |q|^2); that
 // is added to |e_q|.  |ext(q)| = |q|, so |q| and |q|^2 keep their roles.
+template <int RR>  // D = 64 RR coefficients, RR per lane
 __global__ void __launch_bounds__(64) k_quantise_queries_spec(QueryArgs a, FilterArgs f, unsigned* qmax) {
-    constexpr int RMAX = 4;  // D <= 256 coefficients over 64 lanes
+    constexpr int RMAX = RR, D = 64 * RR;
+    __shared__ float sq[512];  // the query row (len <= 512), read once with coalesced loads
     const int q = blockIdx.x;
     const int lane = threadIdx.x;
-    const int D = f.dim;
     const bool real = q < a.mq;
     const float* x = a.Q + (int64_t)q * a.len;
-    double y[RMAX] = {0.0, 0.0, 0.0, 0.0};
-    double qn = 0.0;
-    for (int j = 0; j < a.len; ++j) {
-        const double v = real ? (double)x[j] : 0.0;
-        qn = fma(v, v, qn);
-        const double* tj = f.spec + (int64_t)j * D;
+    for (int t = lane; t < a.len; t += 64) sq[t] = real ? x[t] : 0.f;
+    __syncthreads();
+    double y[RMAX];
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r)
-            if (lane + 64 * r < D) y[r] = fma(tj[lane + 64 * r], v, y[r]);
+    for (int r = 0; r < RMAX; ++r) y[r] = 0.0;
+    double qn = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < a.len; ++j) {
+        const double v = (double)sq[j];
+        qn = fma(v, v, qn);
+        const double* tj = f.spec + (int64_t)j * D + lane;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) y[r] = fma(tj[64 * r], v, y[r]);
     }
     double head = 0.0;
 #pragma unroll
@@ -166,7 +171,6 @@ __global__ void __launch_bounds__(64) k_quantise_queries_spec(QueryArgs a, Filte
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
         const int i = lane + 64 * r;
-        if (i >= D) continue;
         const double v = i == D - 1 ? tail : y[r];
         const uint16_t b = bf16_rne((float)v);
         static_cast<uint16_t*>(f.qq)[(int64_t)q * D + i] = b;
@@ -304,12 +308,20 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
     const int n_samp = (int)filter_samples_before(n_tiles, R);
     const int64_t t_lo = f.range_lo / C::TS, t_hi = (f.range_hi + C::TS - 1) / C::TS;
     const int g_lo = (int)(t_lo - filter_samples_before(t_lo, R)), g_hi = (int)(t_hi - filter_samples_before(t_hi, R));
-    const int n_vt = f.phase == 0 ? n_tiles : f.phase == 1 ? n_samp : f.phase == 2 ? n_tiles - n_samp : g_hi - g_lo;
+    const int n_sec = (int)filter_seconds_before(n_tiles, R);
+    const int n_vt = f.phase == 0   ? n_tiles
+                     : f.phase == 1 ? n_samp
+                     : f.phase == 2 ? n_tiles - n_samp
+                     : f.phase == 3 ? g_hi - g_lo
+                     : f.phase == 4 ? n_sec
+                                    : n_tiles - n_samp - n_sec;
     auto tile_of = [&](int v) -> int64_t {
         return f.phase == 0   ? v
                : f.phase == 1 ? filter_sample_tile(v, R)
                : f.phase == 2 ? filter_other_tile(v, R)
-                              : filter_other_tile(g_lo + v, R);
+               : f.phase == 3 ? filter_other_tile(g_lo + v, R)
+               : f.phase == 4 ? filter_second_tile(v, R)
+                              : filter_rest_tile(v, R);
     };
     const unsigned char* X = static_cast<const unsigned char*>(f.xq);
     // one column tile's rows (part) at a time: the next tile's part p is loaded
@@ -619,12 +631,20 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter_bf16(QueryArgs a, FilterA
     const int n_samp = (int)filter_samples_before(n_tiles, R);
     const int64_t t_lo = f.range_lo / C::TS, t_hi = (f.range_hi + C::TS - 1) / C::TS;
     const int g_lo = (int)(t_lo - filter_samples_before(t_lo, R)), g_hi = (int)(t_hi - filter_samples_before(t_hi, R));
-    const int n_vt = f.phase == 0 ? n_tiles : f.phase == 1 ? n_samp : f.phase == 2 ? n_tiles - n_samp : g_hi - g_lo;
+    const int n_sec = (int)filter_seconds_before(n_tiles, R);
+    const int n_vt = f.phase == 0   ? n_tiles
+                     : f.phase == 1 ? n_samp
+                     : f.phase == 2 ? n_tiles - n_samp
+                     : f.phase == 3 ? g_hi - g_lo
+                     : f.phase == 4 ? n_sec
+                                    : n_tiles - n_samp - n_sec;
     auto tile_of = [&](int v) -> int64_t {
         return f.phase == 0   ? v
                : f.phase == 1 ? filter_sample_tile(v, R)
                : f.phase == 2 ? filter_other_tile(v, R)
-                              : filter_other_tile(g_lo + v, R);
+               : f.phase == 3 ? filter_other_tile(g_lo + v, R)
+               : f.phase == 4 ? filter_second_tile(v, R)
+                              : filter_rest_tile(v, R);
     };
     const unsigned char* X = static_cast<const unsigned char*>(f.xq);
     // the whole tile `tl` into `dst`: instruction j of this wave fills slots [64 (j WAVES + wave), +64).
@@ -968,8 +988,11 @@ void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qm
     const int64_t all_tiles = (a.n + C::TS - 1) / C::TS;
     const int64_t n_samp = filter_samples_before(all_tiles, R);
     int64_t n_tiles = all_tiles;
+    const int64_t n_sec = filter_seconds_before(all_tiles, R);
     if (f.phase == 1) n_tiles = n_samp;
     if (f.phase == 2) n_tiles -= n_samp;
+    if (f.phase == 4) n_tiles = n_sec;
+    if (f.phase == 5) n_tiles -= n_samp + n_sec;
     if (f.phase == 3) {
         const int64_t t_lo = f.range_lo / C::TS, t_hi = (f.range_hi + C::TS - 1) / C::TS;
         n_tiles = (t_hi - filter_samples_before(t_hi, R)) - (t_lo - filter_samples_before(t_lo, R));
@@ -1011,7 +1034,12 @@ void launch_quantise_queries(const QueryArgs& a, const FilterArgs& f, int mq_pad
     if (f.spec) {
         if (f.kind != 0 || f.dim < 64 || f.dim > 256 || f.dim % 64)
             throw Error{ISAX_EINVAL, "internal: spectral codes need BF16 and 64..256 coefficients"};
-        k_quantise_queries_spec<<<mq_pad, 64, 0, s>>>(a, f, qmax);
+        switch (f.dim / 64) {
+            case 1: k_quantise_queries_spec<1><<<mq_pad, 64, 0, s>>>(a, f, qmax); break;
+            case 2: k_quantise_queries_spec<2><<<mq_pad, 64, 0, s>>>(a, f, qmax); break;
+            case 3: k_quantise_queries_spec<3><<<mq_pad, 64, 0, s>>>(a, f, qmax); break;
+            default: k_quantise_queries_spec<4><<<mq_pad, 64, 0, s>>>(a, f, qmax); break;
+        }
     } else {
         k_quantise_queries<<<mq_pad, 64, 0, s>>>(a, f, f.dim, qmax);
     }
@@ -1025,7 +1053,7 @@ void launch_filter(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax
         switch (lp) {
             case 64: launch_filter_t<0, 4, 2, 8>(a, f, qmax, s); break;
             case 128: launch_filter_sized<0, 8, 2>(a, f, qmax, s); break;
-            case 192: launch_filter_t<0, 12, 2, 8>(a, f, qmax, s); break;
+            case 192: launch_filter_sized<0, 12, 2>(a, f, qmax, s); break;
             case 256: launch_filter_sized<0, 16, 2>(a, f, qmax, s); break;
             case 320: launch_filter_t<0, 20, 1, 8>(a, f, qmax, s); break;
             case 384: launch_filter_t<0, 24, 1, 8>(a, f, qmax, s); break;
@@ -1061,7 +1089,7 @@ void launch_refine_filtered(const QueryArgs& a, const FilterArgs& f, hipStream_t
 int filter_rows_bf16(int dim, int mq) {
     const int lp = dim;
     int qpb = lp <= 256 ? 512 : 256;  // <MT = 2, 8 waves> below 320, <1, 8> from 320
-    if ((lp == 128 || lp == 256) && mq <= 256) qpb = mq <= 64 ? 64 : mq <= 128 ? 128 : 256;
+    if ((lp == 128 || lp == 192 || lp == 256) && mq <= 256) qpb = mq <= 64 ? 64 : mq <= 128 ? 128 : 256;
     return (mq + qpb - 1) / qpb * qpb;
 }
 

@@ -134,7 +134,8 @@ struct FilterArgs {
     float* out_approx;        // optional [mq][n] (inspection)
     float* out_margin;        // optional [mq][n]
     int phase;                // 0: every tile; 1: the sample tiles; 2: the other tiles;
-                              // 3: the other tiles among sorted positions [range_lo, range_hi)
+                              // 3: the other tiles among sorted positions [range_lo, range_hi);
+                              // 4 and 5: phase 2 split into a second sample and the rest
     int64_t range_lo, range_hi;  // phase 3; range_lo a multiple of kFilterAlign
 };
 // The sample of the first phase: units of kFilterAlign consecutive sorted
@@ -151,6 +152,22 @@ __host__ __device__ inline int64_t filter_sample_tile(int64_t v, int R) { return
 __host__ __device__ inline int64_t filter_other_tile(int64_t v, int R) {
     const int64_t g = (int64_t)(kFilterSub - 1) * R;
     return v / g * kFilterSub * R + R + v % g;
+}
+// Phases 4 and 5 split the other units (phase 2) in two: phase 4 takes the unit
+// kFilterSub / 2 past each sample unit (a second even sample of the
+// collection), phase 5 the rest.  Tiles of phase 4 among tiles [0, t):
+__host__ __device__ inline int64_t filter_seconds_before(int64_t t, int R) {
+    const int64_t g = (int64_t)kFilterSub * R, o = (int64_t)(kFilterSub / 2) * R, r = t % g;
+    return t / g * R + (r <= o ? 0 : (r - o < R ? r - o : R));
+}
+__host__ __device__ inline int64_t filter_second_tile(int64_t v, int R) {
+    return v / R * kFilterSub * R + (int64_t)(kFilterSub / 2) * R + v % R;
+}
+__host__ __device__ inline int64_t filter_rest_tile(int64_t v, int R) {
+    const int64_t g = (int64_t)(kFilterSub - 2) * R, w = v % g;
+    int64_t u = w / R + 1;
+    if (u >= kFilterSub / 2) ++u;
+    return v / g * kFilterSub * R + u * R + w % R;
 }
 int filter_len_pad(int len);              // rows of the reduced-precision copies are padded to this
 int filter_queries_per_block(int len);    // query codes are padded to a multiple of this

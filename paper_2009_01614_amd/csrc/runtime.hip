@@ -816,6 +816,12 @@ constexpr double kFilterFlopsWide = 1.4e15;
 constexpr double kFilterFlopsMid = 1.05e15;
 constexpr double kFilterFlopsNarrow = 0.8e15;
 constexpr double kFilterPerQuery = 10e-6;
+// The spectral copy (fewer coefficients than the padded length) streams at
+// about kSpectralStreamBps and computes at kSpectralRate of the rates above
+// (fitted to 100M x 256 with 192 coefficients: 8.8 ms for 1-100 queries, 13.3
+// for 256, 19.0 for 512, 35.8 for 1000).
+constexpr double kSpectralStreamBps = 4.5e12;
+constexpr double kSpectralRate = 0.74;
 // The hybrid's own work before and around the split (leaf pass, round 1, a
 // second approximate answer for the filter's queries, more synchronisation):
 // about 1.5 ms per call at 10M x 256; a batch the filter answers in less than
@@ -827,8 +833,12 @@ inline double k_prior(int k) { return 1.0 + 0.7 * std::log10((double)std::max(k,
 // The pre-screen bounds every kPreStride-th node (64 leaves) of the leaf pass.
 constexpr int kPreStride = 16;
 // Near queries measured at 1.7-2x their optimistic pre-screen price (100M x 256,
-// sigma 0.01 and 0.1, k = 1 and 10): the pre-screen scales it by this much.
+// sigma 0.01 and 0.1, k = 10): the pre-screen scales it by this much for k > 1.
+// At k = 1 the bound of a near query tightens at once in round 1 (sigma = 0.1:
+// about 11 us per query against pre-screen prices of 50-120 us for those whose
+// approximate answer was loose), so its price is left as it is.
 constexpr double kPreFactor = 1.5;
+inline double pre_factor(int k) { return k > 1 ? kPreFactor : 1.0; }
 
 // Codes per row the BF16 filter reads: D of the spectral copy when the index
 // holds one (unless the query asks for the full rows), else the padded length.
@@ -840,6 +850,7 @@ int bf16_dim(const isax_index* idx, int flags) {
 // largest cost join them, j minimising filter_cost(all of them) + the cost of
 // the queries left on the iSAX path.  Returns the filter's set.
 double filter_cost(const isax_index* idx, int f, int dim);
+double filter_pass_cost(const isax_index* idx, int f, int dim);
 // Keeping any query on the index path also costs its own passes and
 // synchronisations (leaf pass, rounds, the second plan): about this much.
 constexpr double kIndexFixed = 1.5e-3;
@@ -874,13 +885,20 @@ std::vector<char> plan_far(const isax_index* idx, const std::vector<double>& cos
     return far;
 }
 
-double filter_cost(const isax_index* idx, int f, int dim) {
+// The pass over the copy (streaming or matrix work, whichever binds) ...
+double filter_pass_cost(const isax_index* idx, int f, int dim) {
     if (f == 0) return 0.0;
-    const double stream = (double)idx->n * (dim * 2 + 16) / kFilterStreamBps;
+    const bool spec = dim < filter_len_pad(idx->len);
+    const double stream = (double)idx->n * (dim * 2 + 16) / (spec ? kSpectralStreamBps : kFilterStreamBps);
     const int rows = filter_rows_bf16(dim, f);
-    const double rate = rows % 512 == 0 ? kFilterFlopsWide : rows == 256 ? kFilterFlopsMid : kFilterFlopsNarrow;
+    const double rate = (rows % 512 == 0 ? kFilterFlopsWide : rows == 256 ? kFilterFlopsMid : kFilterFlopsNarrow) *
+                        (spec ? kSpectralRate : 1.0);
     const double mfma = 2.0 * dim * (double)idx->n * rows / rate;
-    return std::max(stream, mfma) + f * kFilterPerQuery;
+    return std::max(stream, mfma);
+}
+// ... and the refinement and ordering of its queries.
+double filter_cost(const isax_index* idx, int f, int dim) {
+    return f == 0 ? 0.0 : filter_pass_cost(idx, f, dim) + f * kFilterPerQuery;
 }
 
 // The rows of a hybrid batch's filter sub-batch: positions, gathered queries
@@ -944,7 +962,7 @@ void run_hybrid_batch(isax_index* idx, Batch& b, hipStream_t s, int64_t limit) {
         ISAX_HIP(hipStreamSynchronize(s));
         for (int q = 0; q < mq; ++q) {
             const double est = c[q] * scale, n1 = std::min<double>(est, kFirstLeaves);
-            cost[q] = kPreFactor * kp[q] *
+            cost[q] = pre_factor(b.kq_host ? b.kq_host[q] : a.kmax) * kp[q] *
                       ((leaf_words + kFarShare * leaf_refine) * n1 + (leaf_words + kNearShare * leaf_refine) * (est - n1));
         }
         pre = plan_far(idx, cost, pre, fscale, fdim);
@@ -1403,10 +1421,10 @@ Arena filter_arena(FilterScratch& fs, unsigned char** qq, const isax_index* idx,
 
 // `fcap`: filter candidates kept per query before the buffer grows.
 void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, int mode, int64_t fcap,
-                  hipStream_t s) {
+                  hipStream_t s, bool full_rows = false) {
     FilterArgs& f = fs.f;
     f.kind = mode == ISAX_MODE_BF16 ? 0 : 1;
-    if (f.kind == 0 && idx->x_spec && !(a.flags & ISAX_QF_FULL_ROWS)) {
+    if (f.kind == 0 && idx->x_spec && !(a.flags & ISAX_QF_FULL_ROWS) && !full_rows) {
         f.dim = idx->spec_dim;
         f.spec = idx->spec_t;
         f.xq = idx->x_spec;
@@ -1437,6 +1455,19 @@ void setup_filter(FilterScratch& fs, const isax_index* idx, const QueryArgs& a, 
 // and the phases run again.
 constexpr int kSub = kFilterSub;
 
+// The spectral copy trades matrix work for candidates: where the dropped
+// coefficients matter (queries far from every series, large k) it lets
+// through many more series than the full rows do.  When the index also holds
+// the full rows, the other units run as a second even sample (phase 4, on the
+// spectral copy, after the first sample's candidates have tightened the
+// bound) and the rest (phase 5): the second sample's candidate count times the
+// units left (kSub - 2 of them per sample unit) is priced at kRefineBps of
+// row reads against what the spectral copy saves on the matrix work, and when
+// the refinement would cost more the rest (and any re-run) reads the full
+// rows.  The saving is taken as half the share of coefficients dropped
+// (measured at 100M x 256: 192 of 256 coefficients took 0.88 of the full pass).
+constexpr double kRefineBps = 2e12;
+
 void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     QueryArgs& a = b.a;
     FilterScratch fs;
@@ -1451,8 +1482,12 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
     if (n_tiles >= 16 * kSub) phases = {1, 2};
     else phases = {0};
     const int qpb = filter_queries_per_block(idx->len);
-    const double bytes_all = (double)idx->n * (fs.f.dim * (fs.f.kind == 0 ? 2 : 1) + 16) *
-                             ((fs.mq_pad + qpb - 1) / qpb);
+    auto bytes_all = [&]() {
+        return (double)idx->n * (fs.f.dim * (fs.f.kind == 0 ? 2 : 1) + 16) * ((fs.mq_pad + qpb - 1) / qpb);
+    };
+    // (not under the no-allocation entry point, whose scratch holds one filter's arrays)
+    bool may_switch = fs.f.spec && idx->x_bf16 && phases.size() == 2 && !fixed_scratch();
+    if (may_switch) phases = {1, 4, 5};
     std::vector<unsigned> cnt(a.mq);
     for (int attempt = 0;; ++attempt) {
         bool over = false;
@@ -1463,7 +1498,7 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
             launch_filter(a, fs.f, fs.qmax, s);
             if (profiling_on())
                 profile_add_bytes(fs.f.kind == 0 ? "filter_bf16" : "filter_fp8",
-                                  ph == 0 ? bytes_all : ph == 1 ? bytes_all / kSub : bytes_all * (kSub - 1) / kSub);
+                                  bytes_all() * (ph == 0 ? kSub : ph == 2 ? kSub - 1 : ph == 5 ? kSub - 2 : 1) / kSub);
             ISAX_HIP(hipMemcpyAsync(cnt.data(), fs.f.fcount, a.mq * sizeof(unsigned), hipMemcpyDeviceToHost, s));
             ISAX_HIP(hipStreamSynchronize(s));
             for (unsigned c : cnt) maxc = std::max(maxc, c);
@@ -1472,6 +1507,21 @@ void run_filter_batch(isax_index* idx, Batch& b, int mode, hipStream_t s) {
                 break;
             }
             launch_refine_filtered(a, fs.f, s);
+            if (ph == 4 && may_switch) {
+                may_switch = false;
+                double est = 0.0;
+                for (unsigned c : cnt) est += c;
+                const double refine = est * (kSub - 2) * idx->len * 4.0 / kRefineBps;
+                const int full = filter_len_pad(idx->len);
+                const double save = 0.5 * (1.0 - (double)fs.f.dim / full) * filter_pass_cost(idx, a.mq, full);
+                if (refine > save) {
+                    FilterScratch fr;
+                    setup_filter(fr, idx, a, mode, fs.f.fcap, s, true);
+                    launch_quantise_queries(a, fr.f, fr.mq_pad, fr.qmax, s);
+                    fs = std::move(fr);
+                    if (profiling_on()) profile_add_bytes("filter_full_rows_switch", 1.0);
+                }
+            }
         }
         if (!over) break;
         if (attempt >= 8) throw Error{ISAX_EOVERFLOW, "filter candidates kept overflowing"};

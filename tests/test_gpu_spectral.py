@@ -72,11 +72,11 @@ def test_spectral_scores_bound_every_pair(isax, length, dim):
 def coll(isax):
     X = workload.random_walks(100_003, 256, seed=20090171, device="cuda")
     workload.planted_duplicates(X, [(99_998, 21), (40_000, 21)])
-    Qn, _, _ = workload.noisy_queries(X, 150, seed=20091171)
+    Qn, _, sig = workload.noisy_queries(X, 150, seed=20091171)
     Q = torch.cat([Qn, workload.fresh_queries(6, 256, seed=20091172, device="cuda"), X[21:22].clone()]).contiguous()
     both = isax.Index(X, 16, 8, precision=isax.PREC_BF16 | isax.PREC_SPECTRAL)
     ref_ids, ref_d2 = kr.knn_exact_c(_cpu(X), _cpu(Q), 100)
-    return {"X": X, "Q": Q, "idx": both, "ids": ref_ids, "d2": ref_d2}
+    return {"X": X, "Q": Q, "idx": both, "ids": ref_ids, "d2": ref_d2, "sig": sig}
 
 
 @pytest.mark.parametrize("k", [1, 10, 100])
@@ -163,3 +163,22 @@ def test_spectral_noalloc_and_server(isax, coll):
     for i, r in got.items():
         assert r["status"] == 0, r
         assert np.array_equal(np.asarray(r["ids"]), coll["ids"][i, :10])
+
+
+def test_spectral_switch_to_full_rows(isax, coll):
+    # with both copies the filter decides after a second sample of the collection: far
+    # queries at k = 100 switch the rest of the pass to the full rows, near queries at
+    # k = 1 stay on the spectral copy; the answers are the oracle's either way
+    idx, Q, sig = coll["idx"], coll["Q"], coll["sig"]
+    cases = [("far", np.where(sig == 1.0)[0], 100, True), ("near", np.where(sig == 0.01)[0], 1, False)]
+    for name, rows, k, want in cases:
+        sel = torch.from_numpy(rows).cuda()
+        isax.profile_reset()
+        isax.profile_enable(True)
+        try:
+            ids, d = idx.query(Q[sel].contiguous(), k=k, mode="bf16")
+            prof = isax.profile_read()
+        finally:
+            isax.profile_enable(False)
+        assert ("filter_full_rows_switch" in prof) == want, (name, sorted(prof))
+        _check(ids, d, coll["ids"][rows], coll["d2"][rows], k)

@@ -371,11 +371,15 @@ def serving_sweep(args, dev):
     import workload
 
     mode = args.sweep_mode
-    prec = {"bf16": 1, "fp8": 2, "hybrid": 1}.get(mode, 0)
     log("generating 50M x 256 and 20M x 128")
     cols = [workload.random_walks(50_000_000, 256, seed=20090165, device=dev),
             workload.random_walks(20_000_000, 128, seed=20090166, device=dev)]
-    idx = [isax.Index(X, 16, 8, precision=prec) for X in cols]
+
+    def prec(L):
+        # the spectral copy where three quarters of the padded length leave coefficients out (len 256: 192)
+        bf16_bits = isax.PREC_BF16 if args.no_spectral or L < 256 else isax.PREC_SPECTRAL
+        return {"bf16": bf16_bits, "fp8": isax.PREC_FP8, "hybrid": bf16_bits}.get(mode, 0)
+    idx = [isax.Index(X, 16, 8, precision=prec(X.shape[1])) for X in cols]
     rng = np.random.default_rng(20091165)
     pools = []
     for ci, X in enumerate(cols):
@@ -471,23 +475,44 @@ def precision_report(args, dev):
     log("generating 10M x 256")
     X = workload.random_walks(n, L, seed=20090162, device=dev)
     Q, _, _ = workload.noisy_queries(X, 4096, seed=20091164)
-    idx = isax.Index(X, 16, 8, precision=3)
+    # BF16 on the spectral copy (mode bf16) and on the full rows (bf16_full), FP8
+    idx = isax.Index(X, 16, 8, precision=isax.PREC_BF16 | isax.PREC_FP8 | isax.PREC_SPECTRAL)
     out = {"metric": "exact k-NN queries/s by mode; filter error vs FP64", "config": {
-        "workload": "10M x 256 random walks, 4 batches of 1024 noisy queries (sigma 0.01/0.1/1)"}, "qps": {}}
+        "workload": "10M x 256 random walks, 4 batches of 1024 noisy queries (sigma 0.01/0.1/1)",
+        "spectral_dim": idx.info()["spectral_dim"]}, "qps": {}, "split": {}}
     for k in (1, 10):
         ref = None
-        for mode in ("bf16", "fp8", "index", "scan"):
-            idx.query(Q[:1024].contiguous(), k=k, mode=mode)
+        for mode in ("bf16", "bf16_full", "fp8", "index", "scan"):
+            kw = {"mode": "bf16", "flags": isax.QF_FULL_ROWS} if mode == "bf16_full" else {"mode": mode}
+            idx.query(Q[:1024].contiguous(), k=k, **kw)
             torch.cuda.synchronize()
+            isax.profile_reset()
+            isax.profile_enable(True)
             t0 = time.perf_counter()
-            ids = [idx.query(Q[b:b + 1024].contiguous(), k=k, mode=mode, batch=1024)[0] for b in range(0, 4096, 1024)]
+            ids = [idx.query(Q[b:b + 1024].contiguous(), k=k, batch=1024, **kw)[0] for b in range(0, 4096, 1024)]
             torch.cuda.synchronize()
             out["qps"][f"{mode}_k{k}"] = round(4096 / (time.perf_counter() - t0), 1)
+            prof = isax.profile_read()
+            isax.profile_enable(False)
+            if mode in ("bf16", "bf16_full", "fp8"):
+                # where a filter batch's time goes, and how many series it refines per query
+                _, _, st = idx.query(Q[:1024].contiguous(), k=k, stats=True, **kw)
+                fk = "filter_fp8" if mode == "fp8" else "filter_bf16"
+                out["split"][f"{mode}_k{k}"] = {
+                    "filter_ms_per_batch": round(prof.get(fk, {}).get("total_ms", 0.0) / 4, 2),
+                    "refine_ms_per_batch": round(prof.get("refine_filtered", {}).get("total_ms", 0.0) / 4, 2),
+                    "refined_per_query": round(float(np.mean([x["series_refined"] for x in st])), 1),
+                    "kept_fraction": float(np.mean([x["series_refined"] for x in st])) / n,
+                    "full_rows_switches": int(prof.get("filter_full_rows_switch", {}).get("algorithmic_bytes", 0))}
             ids = torch.cat(ids)
             if ref is None:
                 ref = ids
             assert torch.equal(ids, ref), f"{mode} disagrees"
-            log(f"k={k} {mode}: {out['qps'][f'{mode}_k{k}']} queries/s")
+            log(f"k={k} {mode}: {out['qps'][f'{mode}_k{k}']} queries/s {out['split'].get(f'{mode}_k{k}', '')}")
+    del idx
+    torch.cuda.empty_cache()
+    # scores of the full rows and of FP8 (an index without the spectral copy), then of the spectral copy
+    idx = isax.Index(X, 16, 8, precision=isax.PREC_BF16 | isax.PREC_FP8)
     log("filter error vs FP64 on 4 sampled queries")
     sample = Q[[0, 1, 2, 3]].contiguous()
     # the bound check: plain FP64 squared distances (PyTorch on the device, in chunks)
@@ -506,6 +531,17 @@ def precision_report(args, dev):
                                  "mean_abs_err": float(err.mean()),
                                  "kept_fraction_at_final_bound_k1": float(((ap - mg) <= tau).mean())}
         log(f"{mode}: {out[f'filter_{mode}']}")
+    del idx
+    torch.cuda.empty_cache()
+    # the spectral copy's scores bound ED^2 from below only (approx - M <= ED^2)
+    idx = isax.Index(X, 16, 8, precision=isax.PREC_SPECTRAL)
+    ap, mg = (t.cpu().numpy().astype(np.float64) for t in idx.filter_scores(sample, "bf16"))
+    tau = np.sort(d64, axis=1)[:, 0:1]
+    out["filter_bf16_spectral"] = {"max_lower_bound_minus_ed2": float((ap - mg - d64).max()),
+                                   "mean_margin": float(mg.mean()),
+                                   "mean_gap_ed2_minus_approx": float((d64 - ap).mean()),
+                                   "kept_fraction_at_final_bound_k1": float(((ap - mg) <= tau).mean())}
+    log(f"bf16 spectral: {out['filter_bf16_spectral']}")
     print(json.dumps(out), flush=True)
 
 

@@ -71,8 +71,15 @@ enum {
     ISAX_QF_FILTER_CHEAP = 16,    /* hybrid mode: price the filter at 1/1000 of its model, or */
     ISAX_QF_FILTER_DEAR = 32,     /* at 1000 times it, so that small collections exercise each of the
                                      planner's routes (testing) */
-    ISAX_QF_FULL_ROWS = 64        /* BF16 filter: read the full-length BF16 copy even when the index also
+    ISAX_QF_FULL_ROWS = 64,       /* BF16 filter: read the full-length BF16 copy even when the index also
                                      holds the spectral copy (precision bit 3) */
+    ISAX_QF_NO_PRECHECK = 128     /* read rows directly.  By default (ED, an index with the full-row BF16
+                                     copy) a series that survives the iSAX bounds is first bounded from
+                                     below with its BF16 row, approx - M as in the filter, and its row is
+                                     read only if that bound is within the best-so-far; for a collection in
+                                     pinned host memory the approximate answer does the same, reading only
+                                     the series whose bound is within the k-th smallest upper bound
+                                     approx + M of its leaves */
 };
 
 /* Distance measures (isax_query_options.metric). */

@@ -26,7 +26,7 @@ METRIC_ED, METRIC_DTW = 0, 1
 METRICS = {"ed": METRIC_ED, "dtw": METRIC_DTW}
 MAX_WINDOW = 31
 QF_NO_SHARING, QF_NO_EARLY_ABANDON, QF_NO_BEST_FIRST, QF_NO_SHORTCUT, QF_FILTER_CHEAP, QF_FILTER_DEAR = 1, 2, 4, 8, 16, 32
-QF_FULL_ROWS = 64
+QF_FULL_ROWS, QF_NO_PRECHECK = 64, 128
 # isax_build_options.precision bits
 PREC_BF16, PREC_FP8, PREC_SORTED_ROWS, PREC_SPECTRAL = 1, 2, 4, 8
 SERVE_BATCHES = 1

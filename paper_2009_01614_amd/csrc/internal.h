@@ -154,6 +154,7 @@ struct isax_index {
     int device = 0;
     hipStream_t stream = nullptr;
     const float* data = nullptr;  // [n][len], borrowed
+    bool data_on_host = false;    // data is pinned host memory (rows cross the bus)
     int64_t n = 0;
     int32_t len = 0, w = 0, c = 0, m_seg = 0, ws = 0, ns = 0;  // ws: word stride bytes, ns = 2^c
     int32_t leaf_size = 256, key_bits = 64;

@@ -76,6 +76,14 @@ struct QueryArgs {
     int all_leaves;             // 1: no leaf or series bound (the plain scan under DTW)
     float* env_paa;             // [mq][2][w] PAA of the upper then lower query envelope (ED: the query PAA twice)
     float* qenv;                // [mq][2][len] DTW: upper then lower envelope of the query
+    // refinement precheck (ED, an index with the full-row BF16 copy): each series is first
+    // bounded from below with the copy, and only series whose bound is within the
+    // best-so-far have their rows read
+    const uint16_t* pc_x;       // [n][pc_stride] BF16 rows in leaf order, or null (no precheck)
+    const float4* pc_meta;      // [n] {|x|^2, |e_x| (up), |x~| (up), 1}
+    int pc_stride;
+    int pc_home;                // 1: the approximate answer prechecks its series too (rows in host memory)
+    float pc_gamma, pc_kappa;   // FP32 dot of len terms; slack on |q|^2 + |x|^2
 };
 constexpr int kDtwMaxLen = 2048;  // longest series the DTW path takes (its LDS plan)
 // The filter's first phase reads one tile in kFilterSub (an even sample of the

@@ -110,6 +110,30 @@ __device__ float refine16(const float* __restrict__ row, const float* qrow, int 
     return sum16(acc);
 }
 
+// Lower bound on ED^2 of the query (qrow, FP32, in LDS) to the series at sorted
+// position p from its BF16 copy, by a group of 16 lanes (the same value in all
+// of them): approx - M with approx = |q|^2 + |x|^2 - 2 fl(q.x~) and
+// M = 2 (|q| |e_x| + gamma |q| |x~|) + kappa (|q|^2 + |x|^2), since
+// q.x - q.x~ = q.e_x, the FP32 dot of len terms is within gamma |q| |x~| of
+// q.x~, and kappa covers the FP32 norms and this sum.  qn = |q|^2 (FP32), nq >= |q|.
+__device__ inline float precheck16(const QueryArgs& a, int64_t p, const float* qrow, int gl, float qn, float nq) {
+    const uint16_t* xr = a.pc_x + p * a.pc_stride;
+    float s = 0.f;
+    for (int j0 = gl * 8; j0 < a.len; j0 += 128) {
+        const uint4 v = *reinterpret_cast<const uint4*>(xr + j0);
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (j0 + e < a.len)
+                s = fmaf(qrow[j0 + e], __uint_as_float((e & 1) ? (w[e >> 1] & 0xFFFF0000u) : (w[e >> 1] << 16)), s);
+    }
+    s = sum16(s);
+    const float4 m = a.pc_meta[p];
+    const float approx = qn + m.x - 2.f * s;
+    const float M = (2.f * (nq * m.y + a.pc_gamma * nq * m.z) + a.pc_kappa * (qn + m.x)) * (1.f + 0x1p-20f);
+    return approx - M;
+}
+
 // ---------------------------------------------------------------------------------------------
 // DTW pieces.  The grid is D(i, j), i = query index, j = series index, band
 // |i - j| <= r.  Filled column by column (j), column j is held as band cells
@@ -634,13 +658,47 @@ __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
         // values seed the bound)
         const bool vec = a.len % 4 == 0 && (reinterpret_cast<uintptr_t>(a.data) & 15) == 0;
         const int g = lane >> 4, gl = lane & 15;
-        for (int i = wave * 4 + g; i < cnt; i += (int)(blockDim.x / 64) * 4) {
-            const int32_t id = a.ids_sorted[p0 + i];
-            const float* row = series_row(a, p0 + i, id);
-            int steps = 0;
-            const float acc = vec ? refine16<true>(row, qrow, a.len, gl, kInf, false, steps)
-                                  : refine16<false>(row, qrow, a.len, gl, kInf, false, steps);
-            if (gl == 0) keys[i] = make_key(acc, id);
+        float* lbs = qrow + a.len + 2 * kDtwPad;  // [kHomeMax] precheck bounds
+        if (a.pc_x && a.pc_home) {
+            // the BF16 copy first: the k-th smallest upper bound approx + M over these series
+            // bounds the k-th distance of the whole collection from above, and only the series
+            // whose lower bound approx - M is within it can be answers (their rows are read)
+            const float qn = a.qinfo[q].x, nq = sqrtf(qn) * (1.f + 0x1p-20f);
+            for (int i = wave * 4 + g; i < cnt; i += (int)(blockDim.x / 64) * 4) {
+                const float lb = precheck16(a, p0 + i, qrow, gl, qn, nq);
+                const float4 m = a.pc_meta[p0 + i];
+                const float M = (2.f * (nq * m.y + a.pc_gamma * nq * m.z) + a.pc_kappa * (qn + m.x)) * (1.f + 0x1p-20f);
+                // ub = lb + 2 M, rounded up (ub >= ED^2 >= 0)
+                const float ub = fmaxf(0.f, (lb + 2.f * M) * (1.f + 0x1p-20f) + 0x1p-100f);
+                if (gl == 0) {
+                    keys[i] = make_key(ub, i);
+                    lbs[i] = lb;
+                }
+            }
+            __syncthreads();
+            bitonic_sort_u64(keys, P);
+            const float tau = key_d2(keys[k - 1]);
+            __syncthreads();
+            for (int i = threadIdx.x; i < P; i += blockDim.x) keys[i] = kEmpty;
+            __syncthreads();
+            for (int i = wave * 4 + g; i < cnt; i += (int)(blockDim.x / 64) * 4) {
+                if (!(lbs[i] <= tau)) continue;  // the same in the group's 16 lanes
+                const int32_t id = a.ids_sorted[p0 + i];
+                const float* row = series_row(a, p0 + i, id);
+                int steps = 0;
+                const float acc = vec ? refine16<true>(row, qrow, a.len, gl, kInf, false, steps)
+                                      : refine16<false>(row, qrow, a.len, gl, kInf, false, steps);
+                if (gl == 0) keys[i] = make_key(acc, id);
+            }
+        } else {
+            for (int i = wave * 4 + g; i < cnt; i += (int)(blockDim.x / 64) * 4) {
+                const int32_t id = a.ids_sorted[p0 + i];
+                const float* row = series_row(a, p0 + i, id);
+                int steps = 0;
+                const float acc = vec ? refine16<true>(row, qrow, a.len, gl, kInf, false, steps)
+                                      : refine16<false>(row, qrow, a.len, gl, kInf, false, steps);
+                if (gl == 0) keys[i] = make_key(acc, id);
+            }
         }
     }
     __syncthreads();
@@ -649,9 +707,15 @@ __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
     if (!a.rerun)
         for (int i = threadIdx.x; i < k; i += blockDim.x) a.bestk[(int64_t)q * a.kmax + i] = keys[i];
     // entries <= thr form a prefix of the sorted keys
-    __shared__ int s_nc;
-    if (threadIdx.x == 0) s_nc = 0;
+    __shared__ int s_nc, s_read;
+    if (threadIdx.x == 0) {
+        s_nc = 0;
+        s_read = 0;
+    }
     __syncthreads();
+    if (RB == 0 && a.pc_x && a.pc_home)
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x)
+            if (keys[i] != kEmpty) atomicAdd(&s_read, 1);
     for (int i = threadIdx.x; i < cnt; i += blockDim.x)
         if (key_d2(keys[i]) <= thr) {
             atomicMax(&s_nc, i + 1);
@@ -667,8 +731,9 @@ __global__ void __launch_bounds__(256) k_homeleaf(QueryArgs a) {
             qi.w = key_d2(keys[k - 1]);
             a.qinfo[q] = qi;
             unsigned long long* st = a.stats + (int64_t)q * ST_N;
-            st[ST_REFINED] += (unsigned long long)cnt;
-            st[ST_REFINE_BYTES] += (unsigned long long)cnt * a.len * 4ull;
+            const int n_read = RB == 0 && a.pc_x && a.pc_home ? s_read : cnt;  // rows read (the precheck skips the others)
+            st[ST_REFINED] += (unsigned long long)n_read;
+            st[ST_REFINE_BYTES] += (unsigned long long)n_read * a.len * 4ull;
             st[ST_CANDS] += (unsigned long long)s_nc;
             if (RB > 0) {
                 st[ST_DTW] += (unsigned long long)cnt;
@@ -970,6 +1035,8 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
     // finished queries (re-runs), and queries that a hybrid batch hands to the filter
     if (a.done[q]) return;
     const int k = a.kq[q];
+    // (the refinement precheck's query norms)
+    const float pc_qn = a.pc_x ? a.qinfo[q].x : 0.f, pc_nq = sqrtf(pc_qn) * (1.f + 0x1p-20f);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t leaf_id = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t h0 = a.home[2 * q], h1 = a.home[2 * q + 1];
@@ -1136,7 +1203,7 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                             dn = rest;
                         }
                     } else {
-                        if (my < nc) {
+                        if (my < nc && !(a.pc_x && precheck16(a, pa + my_wl[my], qrow, gl, pc_qn, pc_nq) > thr)) {
                             const int64_t p2 = pa + my_wl[my];
                             const int32_t id = a.ids_sorted[p2];
                             const float* row = series_row(a, p2, id);
@@ -1576,7 +1643,8 @@ int dtw_band_regs(int r) {
 
 void launch_homeleaf(const QueryArgs& a, hipStream_t s) {
     ProfScope ps("homeleaf", s);
-    const size_t lds = kHomeMax * sizeof(unsigned long long) + (size_t)(a.len + 2 * kDtwPad) * 4;
+    const size_t lds = kHomeMax * sizeof(unsigned long long) + (size_t)(a.len + 2 * kDtwPad) * 4 +
+                       (a.pc_x && a.pc_home ? kHomeMax * sizeof(float) : 0);
     if (a.metric != ISAX_METRIC_DTW) {
         k_homeleaf<0><<<a.mq, 256, lds, s>>>(a);
     } else {

@@ -126,3 +126,48 @@ def test_raw_data_in_pinned_host_memory(isax):
             assert np.allclose(d.cpu().numpy(), np.sqrt(ref_d2), rtol=1e-4, atol=0)
     finally:
         isax.lib().isax_free(ctypes.c_void_p(h))
+
+
+@pytest.mark.parametrize("k", [1, 10])
+def test_host_rows_with_bf16_precheck(isax, k):
+    # pinned host rows with the BF16 copy in HBM: the approximate answer and the iSAX
+    # refinement bound each series with the copy first and read only the rows that can
+    # matter; answers are the oracle's in every mode
+    Xd = workload.random_walks(200_003, 256, seed=63, device="cuda")
+    workload.planted_duplicates(Xd, [(150_000, 7)])
+    Xh = torch.empty(Xd.shape, dtype=torch.float32, pin_memory=True)
+    Xh.copy_(Xd.cpu())
+    Qn, _, _ = workload.noisy_queries(Xd, 30, seed=64)
+    Q = torch.cat([Qn, Xd[7:8].clone()]).contiguous()
+    ref_ids, ref_d2 = kr.knn_exact_c(Xh.numpy(), Q.cpu().numpy(), k)
+    dev = isax.Index(Xd, 16, 8, precision=isax.PREC_BF16)
+    host = isax.Index(Xh, 16, 8, precision=isax.PREC_BF16)
+    for mode in ("index", "bf16", "hybrid"):
+        ids, d, st = host.query(Q, k=k, mode=mode, stats=True)
+        assert np.array_equal(ids.cpu().numpy(), ref_ids), mode
+        assert np.allclose(d.cpu().numpy(), np.sqrt(ref_d2), rtol=1e-4, atol=0), mode
+        ids2, d2 = dev.query(Q, k=k, mode=mode)
+        assert torch.equal(ids, ids2) and torch.equal(d, d2), mode
+    # rows read over the bus: far fewer than the device path refines
+    _, _, st_h = host.query(Q, k=k, mode="index", stats=True)
+    _, _, st_d = dev.query(Q, k=k, mode="index", stats=True)
+    read_h = sum(s["series_refined"] for s in st_h)
+    read_d = sum(s["series_refined"] for s in st_d)
+    assert read_h < 0.5 * read_d, (read_h, read_d)
+    del Xd
+
+
+@pytest.mark.parametrize("flags", [0, 1, 4])  # plain, no sharing, no best-first
+def test_precheck_on_device_data(isax, flags):
+    # the precheck is on by default with the full-row BF16 copy; ISAX_QF_NO_PRECHECK reads rows directly
+    X = workload.random_walks(150_001, 256, seed=65, device="cuda")
+    Qn, _, _ = workload.noisy_queries(X, 40, seed=66)
+    Q = torch.cat([Qn, workload.fresh_queries(4, 256, seed=67, device="cuda")]).contiguous()
+    idx = isax.Index(X, 16, 8, precision=isax.PREC_BF16)
+    ref_ids, ref_d2 = kr.knn_exact_c(X.cpu().numpy(), Q.cpu().numpy(), 10)
+    for k in (1, 10):
+        a, da, sa = idx.query(Q, k=k, mode="index", flags=flags | isax.QF_NO_PRECHECK, stats=True)
+        b, db, sb = idx.query(Q, k=k, mode="index", flags=flags, stats=True)
+        assert np.array_equal(b.cpu().numpy(), ref_ids[:, :k])
+        assert torch.equal(a, b) and torch.equal(da, db)
+        assert sum(s["series_refined"] for s in sb) <= sum(s["series_refined"] for s in sa)

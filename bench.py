@@ -80,6 +80,12 @@ def main():
     ap.add_argument("--next-report", action="store_true",
                     help="instead of the headline: DTW on the index, raw data in pinned host memory, embeddings")
     ap.add_argument("--next-n", type=int, default=10_000_000, help="collection size of the next-rows report")
+    ap.add_argument("--host-report", action="store_true",
+                    help="instead of the headline: a collection in pinned host memory larger than HBM holds "
+                         "with its BF16 copy (--host-n series of 256 points)")
+    ap.add_argument("--host-n", type=int, default=60_000_000,
+                    help="series of the host report (60M = 61.4 GB: the largest page-locked block the test box "
+                         "granted, 80M failed)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many bytes (3 times) to scale HBM counters")
     args = ap.parse_args()
@@ -103,6 +109,8 @@ def main():
         return serving_sweep(args, dev)
     if args.next_report:
         return next_report(args, dev)
+    if args.host_report:
+        return host_report(args, dev)
     if args.sigma_report:
         return sigma_report(args, dev)
     if args.precision_report:
@@ -619,6 +627,88 @@ def sigma_report(args, dev):
 # clock (no packed FP32) x 2.4 GHz = 39.3 T lane operations/s.
 PEAK_VALU_OPS = 256 * 64 * 2.4e9
 DTW_OPS_PER_CELL = 3
+
+
+def host_report(args, dev):
+    """Raw rows in pinned host memory (the paper's plan for data larger than GPU memory, Sec. V).
+
+    n x 256 random walks are drawn on the device chunk by chunk into page-locked host
+    memory (isax_host_alloc); the index keeps the iSAX layout and the full-row BF16 copy in
+    HBM (the refinement precheck reads that copy and crosses the bus only for rows that can
+    matter).  1000 noisy queries, k = 1 and 10, index / BF16 / hybrid modes (answers equal
+    across modes); 4 queries checked exactly against the C oracle streamed over the rows;
+    then the same collection in HBM for comparison where it fits.
+    """
+    import numpy as np
+    import torch
+
+    import paper_2009_01614_amd as isax
+    import workload
+    from oracle import knn_ref
+
+    n, L = args.host_n, 256
+    log(f"allocating {n} x {L} pinned host rows ({n * L * 4 / 1e9:.1f} GB)")
+    rows = isax.HostRows(n, L)  # exactly n x L x 4 bytes of page-locked memory
+    Xh = rows.tensor
+    t0 = time.perf_counter()
+    workload.random_walks(n, L, seed=20090167, device=dev, out=Xh)
+    log(f"generated in {time.perf_counter() - t0:.1f} s")
+    Q, src, sig = workload.noisy_queries(Xh, 1000, seed=20091167)
+    Q = Q.to(dev).contiguous()
+    _, hbm = torch.cuda.mem_get_info()
+    t0 = time.perf_counter()
+    idx = isax.Index(Xh, 16, 8, precision=isax.PREC_BF16)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    info = idx.info()
+    out = {"metric": "exact k-NN queries/s, rows in pinned host memory",
+           "config": {"n": n, "len": L, "host_row_bytes": n * L * 4, "device_bytes": info["device_bytes"],
+                      "hbm_bytes": hbm, "rows_plus_bf16_copy_fit_in_hbm": n * L * 4 + info["device_bytes"] <= hbm,
+                      "workload": f"{n} x {L} random walks in pinned host memory, 1000 noisy queries"},
+           "build_s": round(build_s, 2), "qps": {}, "rows_read_per_query": {}}
+    log(f"built in {build_s:.1f} s; device bytes {info['device_bytes'] / 1e9:.1f} GB of {hbm / 1e9:.1f}")
+    for k in (1, 10):
+        ref = None
+        for mode in ("index", "bf16", "hybrid"):
+            idx.query(Q[:64].contiguous(), k=k, mode=mode)
+            (ids, _), dt, _ = _timed_query(isax, idx, Q, k=k, mode=mode)
+            ref = ids if ref is None else ref
+            assert torch.equal(ids, ref), f"host rows: {mode} disagrees"
+            out["qps"][f"{mode}_k{k}"] = round(1000 / dt, 1)
+            _, _, st = idx.query(Q[:100].contiguous(), k=k, mode=mode, stats=True)
+            out["rows_read_per_query"][f"{mode}_k{k}"] = round(float(np.mean([x["series_refined"] for x in st])), 1)
+            log(f"k={k} {mode}: {out['qps'][f'{mode}_k{k}']} q/s, rows read per query "
+                f"{out['rows_read_per_query'][f'{mode}_k{k}']}")
+        last = ref
+    # the oracle over the whole collection for 4 queries (one per noise level and a fresh one's rows)
+    sample = [int(np.where(sig == sg)[0][0]) for sg in (0.01, 0.1, 1.0)] + [3]
+    t0 = time.perf_counter()
+    st = knn_ref.KnnState(Q[sample].cpu().numpy(), 10)
+    for a in range(0, n, 10_000_000):
+        st.merge(Xh[a:a + 10_000_000].numpy(), a)
+    ok = bool(np.array_equal(last[sample].cpu().numpy(), st.ids))
+    out["oracle_check"] = {"queries": len(sample), "k": 10, "ids_equal": ok, "seconds": round(time.perf_counter() - t0, 1)}
+    log(f"oracle check: {out['oracle_check']}")
+    assert ok, "host rows: answers differ from the oracle"
+    idx.close()
+    # the same collection in HBM, where rows and copy fit there too
+    if 2 * n * L * 4 + 16 * n < hbm:
+        Xd = Xh.to(dev)
+        idd = isax.Index(Xd, 16, 8, precision=isax.PREC_BF16)
+        out["device_qps"] = {}
+        for k in (1, 10):
+            for mode in ("index", "bf16", "hybrid"):
+                idd.query(Q[:64].contiguous(), k=k, mode=mode)
+                (ids, _), dt, _ = _timed_query(isax, idd, Q, k=k, mode=mode)
+                out["device_qps"][f"{mode}_k{k}"] = round(1000 / dt, 1)
+        out["host_over_device"] = {key: round(out["qps"][key] / v, 3) for key, v in out["device_qps"].items()}
+        log(f"rows in HBM: {out['device_qps']}; host / device: {out['host_over_device']}")
+        idd.close()
+        del Xd
+        torch.cuda.empty_cache()
+    del Xh
+    rows.close()
+    print(json.dumps(out), flush=True)
 
 
 def _timed_query(isax, idx, Q, **kw):

@@ -201,6 +201,17 @@ isax_index* isax_build_ex(const float* data, int64_t n, int32_t len, int32_t seg
 void isax_free(isax_index* idx);
 
 /*
+ * Page-locked host memory for a collection kept in host memory (the paper's
+ * plan for raw data that does not fit in GPU memory, Sec. V): `bytes` bytes
+ * mapped at the same address on the current device (hipHostMalloc), to pass
+ * to isax_build as `data`.  Returns NULL on failure (see isax_last_error());
+ * the caller owns the memory and releases it with isax_host_free (NULL is a
+ * no-op) after the last index over it is freed.
+ */
+void* isax_host_alloc(int64_t bytes);
+void isax_host_free(void* p);
+
+/*
  * Exact k-NN of m queries (device, m x len FP32).  Writes out_ids (device,
  * m x k int64) and out_dists (device, m x k FP32): for each query the k
  * series of smallest Euclidean distance, ascending, ties by lower id (Sec. II,

@@ -104,6 +104,8 @@ SIGNATURES = {
     "isax_summarize": (ctypes.c_int, [_VP, _I64, _I32, _I32, _I32, _VP, _F32P, _VP]),
     "isax_index_get_info": (ctypes.c_int, [_VP, ctypes.POINTER(IndexInfo)]),
     "isax_index_breakpoints": (ctypes.c_int, [_VP, _F32P]),
+    "isax_host_alloc": (ctypes.c_void_p, [ctypes.c_int64]),
+    "isax_host_free": (None, [_VP]),
     "isax_index_export": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
     "isax_lower_bounds": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
     "isax_filter_scores": (ctypes.c_int, [_VP, _VP, _I64, _I32, _VP, _VP]),
@@ -158,6 +160,35 @@ def _dev_f32(t: torch.Tensor, name: str, allow_pinned: bool = False) -> torch.Te
         kind = "CUDA or pinned host" if allow_pinned else "CUDA"
         raise ValueError(f"{name} must be a contiguous 2-D float32 {kind} tensor")
     return t
+
+
+class HostRows:
+    """Page-locked host memory from isax_host_alloc holding an FP32 [n, len] collection.
+
+    `tensor` is a CPU tensor over that memory (for filling it and for Index); keep this
+    object alive while any index uses the rows; close() (or deletion) releases them."""
+
+    def __init__(self, n: int, length: int):
+        import numpy as np
+        nbytes = int(n) * int(length) * 4
+        p = lib().isax_host_alloc(nbytes)
+        if not p:
+            raise IsaxError(ISAX_ENOMEM, last_error())
+        self._p = p
+        arr = np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_float)), shape=(int(n), int(length)))
+        self.tensor = torch.from_numpy(arr)
+
+    def close(self):
+        if getattr(self, "_p", None):
+            self.tensor = None
+            lib().isax_host_free(ctypes.c_void_p(self._p))
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ----------------------------------------------------------------------------- host-side helpers

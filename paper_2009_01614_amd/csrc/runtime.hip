@@ -1938,6 +1938,26 @@ int isax_index_breakpoints(const isax_index* idx, float* out) {
     });
 }
 
+void* isax_host_alloc(int64_t bytes) {
+    void* p = nullptr;
+    const int rc = guarded([&] {
+        ISAX_REQUIRE(bytes > 0, "bytes must be > 0");
+        const hipError_t e = hipHostMalloc(&p, (size_t)bytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            throw Error{ISAX_ENOMEM, std::string("hipHostMalloc of ") + std::to_string(bytes) +
+                                         " bytes failed: " + hipGetErrorString(e)};
+        }
+        return ISAX_OK;
+    });
+    return rc == ISAX_OK ? p : nullptr;
+}
+
+void isax_host_free(void* p) {
+    if (p) (void)hipHostFree(p);
+}
+
 int isax_index_get_info(const isax_index* idx, isax_index_info* out) {
     return guarded([&] {
         ISAX_REQUIRE(idx && out, "index and out must not be NULL");

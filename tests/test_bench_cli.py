@@ -22,6 +22,6 @@ def test_modes_and_reports_are_listed():
     r = _run("--help")
     assert r.returncode == 0
     for flag in ("--mode", "--serve-mode", "--sweep-mode", "--sigma-report", "--precision-report",
-                 "--next-report", "--serving-sweep", "--steps", "--warmup"):
+                 "--next-report", "--host-report", "--serving-sweep", "--steps", "--warmup"):
         assert flag in r.stdout, flag
     assert "hybrid" in r.stdout

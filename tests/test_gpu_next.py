@@ -171,3 +171,27 @@ def test_precheck_on_device_data(isax, flags):
         assert np.array_equal(b.cpu().numpy(), ref_ids[:, :k])
         assert torch.equal(a, b) and torch.equal(da, db)
         assert sum(s["series_refined"] for s in sb) <= sum(s["series_refined"] for s in sa)
+
+
+def test_host_alloc_rows(isax):
+    # rows in page-locked memory from isax_host_alloc (filled from the device), the
+    # index over them answers as the oracle; a size of zero is refused
+    n, L = 120_007, 256
+    rows = isax.HostRows(n, L)
+    try:
+        Xd = workload.random_walks(n, L, seed=68, device="cuda")
+        rows.tensor.copy_(Xd.cpu())
+        Qn, _, _ = workload.noisy_queries(Xd, 20, seed=69)
+        Q = Qn.contiguous()
+        del Xd
+        ref_ids, ref_d2 = kr.knn_exact_c(rows.tensor.numpy(), Q.cpu().numpy(), 10)
+        idx = isax.Index(rows.tensor, 16, 8, precision=isax.PREC_BF16)
+        for mode in ("index", "bf16", "hybrid"):
+            ids, d = idx.query(Q, k=10, mode=mode)
+            assert np.array_equal(ids.cpu().numpy(), ref_ids), mode
+            assert np.allclose(d.cpu().numpy(), np.sqrt(ref_d2), rtol=1e-4, atol=0), mode
+        idx.close()
+    finally:
+        rows.close()
+    with pytest.raises(isax.IsaxError, match="bytes must be > 0"):
+        isax.HostRows(0, 256)

@@ -14,9 +14,10 @@
 namespace isax {
 namespace {
 
-constexpr int kTile = 4096;            // radix-sort tile: 256 threads x 16 items
-constexpr int kSortThreads = 256;
-constexpr int kItemsPerWave = kTile / (kSortThreads / kWaveSize);  // 1024
+constexpr int kTile = 4096;            // radix-sort tile
+constexpr int kSortThreads = 256;      // histogram blocks: 16 items per thread
+constexpr int kScatterThreads = 256;   // scatter blocks: 4 waves of 1024 items
+constexpr int kItemsPerWave = kTile / (kScatterThreads / kWaveSize);
 
 __device__ inline unsigned float_ord(float v) { return __float_as_uint(v); }  // v >= 0
 
@@ -216,7 +217,10 @@ __global__ void k_make_keys(const uint8_t* __restrict__ words, int64_t n, int ws
 // exclusive scan, stable scatter.  Within a tile, each wave owns a contiguous
 // run of 1024 items processed 64 at a time; lanes holding the same digit are
 // found with eight ballots, ranked by popcount, and a per-wave LDS counter per
-// digit carries the running count, so the scatter is stable.
+// digit carries the running count, so the scatter is stable.  The scatter
+// first reorders the tile by digit in LDS and then writes it out in that
+// order, so each digit's run of the tile (16 items on average) leaves as
+// consecutive addresses from consecutive lanes.
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
                                                              int n_tiles, uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[256];
@@ -287,31 +291,40 @@ __global__ void k_scan_add(uint32_t* __restrict__ a, int64_t len, const uint32_t
     if (i < len) a[i] += sums[i / kScanChunk];
 }
 
-__global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint64_t* __restrict__ kin,
+__global__ void __launch_bounds__(kScatterThreads) k_radix_scatter(const uint64_t* __restrict__ kin,
                                                                 const int32_t* __restrict__ vin, int64_t n, int shift,
                                                                 int n_tiles, const uint32_t* __restrict__ offs,
                                                                 uint64_t* __restrict__ kout, int32_t* __restrict__ vout) {
-    constexpr int R = kItemsPerWave / 64;  // 16 rounds per wave
-    __shared__ uint32_t cnt[kSortThreads / 64][256];
-    __shared__ uint32_t base[256];
+    constexpr int R = kItemsPerWave / 64;  // rounds of 64 items per wave
+    constexpr int NW = kScatterThreads / 64;
+    static_assert(kScatterThreads >= 256, "one thread per digit");
+    __shared__ uint32_t cnt[NW][256];
+    __shared__ uint32_t delta[256];  // global start of the digit's run minus its start in the tile
+    __shared__ uint32_t wsum[4];
+    // the tile's keys in digit order, then its values in the same buffer (37 KB of
+    // LDS per block in all: four blocks per CU)
+    __shared__ uint64_t stage[kTile];
+    int32_t* sval = reinterpret_cast<int32_t*>(stage);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int wv = 0; wv < kSortThreads / 64; ++wv) cnt[wv][threadIdx.x] = 0;
-    base[threadIdx.x] = offs[(int64_t)threadIdx.x * n_tiles + blockIdx.x];
+    for (int i = threadIdx.x; i < NW * 256; i += kScatterThreads) cnt[i >> 8][i & 255] = 0;
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint64_t key[R];
     int32_t val[R];
-    uint32_t rank[R];
-    int dig[R];
+    uint32_t rd[R];  // rank within the wave's items of the digit (low 16 bits), digit + 1 (high; 0 = none)
     const int64_t start = (int64_t)blockIdx.x * kTile + (int64_t)wave * kItemsPerWave;
+    // all loads first: the wave barriers of the ranking below also stop the
+    // compiler from moving loads, which would leave one memory latency per round
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t i = start + r * 64 + lane;
-        const bool valid = i < n;
-        key[r] = valid ? kin[i] : 0ull;
-        val[r] = valid ? vin[i] : 0;
+        key[r] = i < n ? kin[i] : 0ull;
+        val[r] = i < n ? vin[i] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool valid = start + r * 64 + lane < n;
         const int d = (int)((key[r] >> shift) & 255);
-        dig[r] = valid ? d : -1;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -320,30 +333,77 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(const uint64_t* 
         }
         uint32_t prior = 0;
         if (valid) prior = cnt[wave][d];
-        rank[r] = prior + (uint32_t)__popcll(peers & lt);
+        rd[r] = valid ? ((uint32_t)(d + 1) << 16) | (prior + (uint32_t)__popcll(peers & lt)) : 0u;
         const int leader = valid ? (int)(__ffsll((long long)peers) - 1) : -1;
         __builtin_amdgcn_wave_barrier();
         if (valid && leader == lane) cnt[wave][d] = prior + (uint32_t)__popcll(peers);
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    {
-        uint32_t s = 0;
-        for (int wv = 0; wv < kSortThreads / 64; ++wv) {
-            const uint32_t c0 = cnt[wv][threadIdx.x];
-            cnt[wv][threadIdx.x] = s;
-            s += c0;
+    // digit d = threadIdx.x < 256: prefix over the waves, then the digit's start in
+    // the tile (exclusive scan of the tile's digit totals: within the wave by
+    // shuffles, then over the first four waves)
+    const int dd = threadIdx.x;
+    uint32_t tot = 0, incl = 0;
+    if (dd < 256) {
+        for (int wv = 0; wv < NW; ++wv) {
+            const uint32_t c0 = cnt[wv][dd];
+            cnt[wv][dd] = tot;
+            tot += c0;
+        }
+        incl = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) wsum[wave] = incl;
+    }
+    __syncthreads();
+    if (dd < 256) {
+        uint32_t tstart = incl - tot;
+        for (int wv = 0; wv < wave; ++wv) tstart += wsum[wv];
+        // unsigned wrap-around: delta + (tile position) is the global position (< 2^31)
+        delta[dd] = offs[(int64_t)dd * n_tiles + blockIdx.x] - tstart;
+        for (int wv = 0; wv < NW; ++wv) cnt[wv][dd] += tstart;
+    }
+    __syncthreads();
+    // the tile in digit order in LDS (stable: waves in order, ranks within a wave) ...
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (rd[r]) {
+            rd[r] = cnt[wave][(rd[r] >> 16) - 1] + (rd[r] & 0xFFFFu);  // now the position in the tile
+            stage[rd[r]] = key[r];
+        } else {
+            rd[r] = ~0u;
+        }
+    }
+    __syncthreads();
+    // ... then written out in that order: consecutive lanes write consecutive
+    // positions of one digit's run.  Keys first; the global positions are kept for
+    // the values, which then take the buffer.
+    constexpr int PT = kTile / kScatterThreads;
+    const int64_t left = n - (int64_t)blockIdx.x * kTile;
+    const int cnt_tile = left < kTile ? (int)left : kTile;
+    uint32_t dst[PT];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+        const int i = threadIdx.x + j * kScatterThreads;
+        dst[j] = ~0u;
+        if (i < cnt_tile) {
+            const uint64_t k = stage[i];
+            dst[j] = delta[(int)((k >> shift) & 255)] + (uint32_t)i;
+            kout[dst[j]] = k;
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (dig[r] >= 0) {
-            const uint32_t dst = base[dig[r]] + cnt[wave][dig[r]] + rank[r];
-            kout[dst] = key[r];
-            vout[dst] = val[r];
-        }
-    }
+    for (int r = 0; r < R; ++r)
+        if (rd[r] != ~0u) sval[rd[r]] = val[r];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PT; ++j)
+        if (dst[j] != ~0u) vout[dst[j]] = sval[threadIdx.x + j * kScatterThreads];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -704,7 +764,7 @@ void sort_keys(uint64_t* keys, int32_t* ids, int64_t n, int key_bits, hipStream_
         }
         {
             ProfScope ps("radix_scatter", s);
-            k_radix_scatter<<<n_tiles, kSortThreads, 0, s>>>(ka, va, n, shift, n_tiles, hist.as<uint32_t>(), kb, vb);
+            k_radix_scatter<<<n_tiles, kScatterThreads, 0, s>>>(ka, va, n, shift, n_tiles, hist.as<uint32_t>(), kb, vb);
         }
         ISAX_HIP(hipGetLastError());
         std::swap(ka, kb);

@@ -12,7 +12,10 @@
 // series is a candidate iff approx - M <= tau (1 + eps); candidates are then
 // refined with FP32 direct differences like every other path, so the answer
 // stays exact.  The query-side factors are replaced by their maxima over the
-// batch, which makes M separable: per element one FMA and one compare.
+// batch, which makes M separable.  In the BF16 kernels the accumulators start
+// at the row's threshold H / 2 (raised by the accumulation error that start
+// adds), so the test per element is a compare of the MFMA result with the
+// column's G / 2, screened by an integer maximum.
 //
 // Layout (verified on the device): for v_mfma_f32_32x32x16_bf16 lane l holds
 // 8 K-values of row/column l % 32 from K-half l / 32, and accumulator r of lane
@@ -248,6 +251,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
 
     const float A = __uint_as_float(qmax[0]), Cq = __uint_as_float(qmax[1]), QN = __uint_as_float(qmax[2]);
     const float kappa = f.kappa;
+    const float hslack = f.gamma * (1.f + 0x1p-10f) + 0x1p-22f;
 
     // query fragments: MT tiles x KS steps
     typedef typename std::conditional<KIND == 0, bf16x8, i32x8>::type Frag;
@@ -283,7 +287,12 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
             float H = -kInf;
             if (q < a.mq && !((a.rerun || a.skip_done) && a.done[q]))
                 H = read_tau(a, q, a.kq[q]) * a.tau_scale - f.qmeta[q].x;
-            s_H[i] = KIND == 0 ? 0.5f * H : H;
+            // BF16: H / 2 is the accumulators' starting value; raised by more than the
+            // accumulation error it adds (gamma |H / 2|), so that the sum stays above
+            // H / 2 + q~.x~ - gamma |q~| |x~|
+            float hv = KIND == 0 ? 0.5f * H : H;
+            if (KIND == 0 && fabsf(hv) < kInf) hv += fabsf(hv) * hslack;
+            s_H[i] = hv;
         }
     };
     refresh_H();
@@ -384,10 +393,18 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
         f32x16 acc[MT];
+        constexpr bool kAccH = KIND == 0 && !INSPECT;  // accumulators start at the rows' H / 2
 #pragma unroll
         for (int t = 0; t < MT; ++t)
 #pragma unroll
-            for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
+            for (int g = 0; g < 4; ++g) {
+                float4 H4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                if constexpr (kAccH) H4 = *reinterpret_cast<const float4*>(&s_H[wave * 32 * MT + 32 * t + 8 * g + 4 * h]);
+                acc[t][4 * g] = H4.x;
+                acc[t][4 * g + 1] = H4.y;
+                acc[t][4 * g + 2] = H4.z;
+                acc[t][4 * g + 3] = H4.w;
+            }
         const unsigned char* bsrc = &tile[buf][(kNT * c + r) * C::STRIDE + h * C::HALF];
         // B fragments read kBAhead steps ahead of the MFMAs that use them; the schedule is pinned
         // (reads first, then per step MT MFMAs and the next read) so that the LDS latency stays
@@ -407,7 +424,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
                 for (int t = 0; t < MT; ++t)
                     acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[t][s], bq[s % (PF + 1)], acc[t], 0, 0, 0);
             }
-            __builtin_amdgcn_sched_group_barrier(0x100, PF, 0);  // DS reads
+            __builtin_amdgcn_sched_group_barrier(0x100, PF + (kAccH ? 4 * MT : 0), 0);  // DS reads
             pin_schedule<PF, MT, 0, KS>();
         } else {
             i32x8 bq[2];
@@ -454,29 +471,25 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter(QueryArgs a, FilterArgs f
                     }
                 }
         } else if constexpr (KIND == 0) {
-            // candidate iff fl(acc + H/2) >= G/2 (the test fma(-2, acc, G) <= H halved; near the
-            // threshold the sum is about G/2, so its one rounding is within the kappa slack).  A lane
-            // first takes the maximum over its 16 MT rows (one add and half a max3 per element);
-            // only lanes whose maximum passes look at the rows one by one.
+            // acc = H/2 + q~.x~ (the accumulators started at H/2): candidate iff acc >= G/2, the
+            // test fma(-2, q~.x~, G) <= H halved.  A lane first takes the maximum of its 16 MT
+            // values as integers (half a max3 per element and no quieting of the MFMA results):
+            // for G/2 > 0 an element >= G/2 is positive and positive floats order as their bit
+            // patterns, which are above every negative one.  Only lanes whose maximum passes (or
+            // whose G/2 is not positive) look at the rows one by one.
             const float Gh = 0.5f * G;
-            float best = -kInf;
+            int best = -2147483647 - 1;
 #pragma unroll
             for (int t = 0; t < MT; ++t)
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const float4 H4 = *reinterpret_cast<const float4*>(&s_H[wave * 32 * MT + 32 * t + 8 * g + 4 * h]);
-                    best = fmaxf(best, fmaxf(acc[t][4 * g] + H4.x, acc[t][4 * g + 1] + H4.y));
-                    best = fmaxf(best, fmaxf(acc[t][4 * g + 2] + H4.z, acc[t][4 * g + 3] + H4.w));
-                }
-            if (__ballot(best >= Gh)) {
+                for (int e = 0; e < 16; e += 2)
+                    best = max(max(best, __float_as_int(acc[t][e])), __float_as_int(acc[t][e + 1]));
+            if (__ballot(!(Gh > 0.f) || best >= __float_as_int(Gh))) {
                 unsigned hit = 0u;
 #pragma unroll
                 for (int t = 0; t < MT; ++t)
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        const int row = 32 * t + 8 * (e >> 2) + 4 * h + (e & 3);
-                        hit |= (acc[t][e] + s_H[wave * 32 * MT + row] >= Gh ? 1u : 0u) << (16 * t + e);
-                    }
+                    for (int e = 0; e < 16; ++e) hit |= (acc[t][e] >= Gh ? 1u : 0u) << (16 * t + e);
                 while (hit) {
                     const int bit = __ffs(hit) - 1;
                     hit &= hit - 1u;
@@ -585,6 +598,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter_bf16(QueryArgs a, FilterA
 
     const float A = __uint_as_float(qmax[0]), Cq = __uint_as_float(qmax[1]), QN = __uint_as_float(qmax[2]);
     const float kappa = f.kappa;
+    const float hslack = f.gamma * (1.f + 0x1p-10f) + 0x1p-22f;
 
     bf16x8 fa[MT][KS];
 #pragma unroll
@@ -605,7 +619,10 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter_bf16(QueryArgs a, FilterA
             float H = -kInf;
             if (q < a.mq && !((a.rerun || a.skip_done) && a.done[q]))
                 H = read_tau(a, q, a.kq[q]) * a.tau_scale - f.qmeta[q].x;
-            s_H[i] = 0.5f * H;
+            // the accumulators' starting value, raised as in k_filter
+            float hv = 0.5f * H;
+            if (fabsf(hv) < kInf) hv += fabsf(hv) * hslack;
+            s_H[i] = hv;
         }
     };
     refresh_H();
@@ -706,11 +723,17 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter_bf16(QueryArgs a, FilterA
     auto compute = [&](const unsigned char* buf, int64_t tl, const float* Ghs) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            f32x16 acc[MT];
+            f32x16 acc[MT];  // starts at the rows' H / 2
 #pragma unroll
             for (int t = 0; t < MT; ++t)
 #pragma unroll
-                for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
+                for (int g = 0; g < 4; ++g) {
+                    const float4 H4 = *reinterpret_cast<const float4*>(&s_H[row_base + 32 * t + 8 * g + 4 * h]);
+                    acc[t][4 * g] = H4.x;
+                    acc[t][4 * g + 1] = H4.y;
+                    acc[t][4 * g + 2] = H4.z;
+                    acc[t][4 * g + 3] = H4.w;
+                }
             const unsigned char* bsrc = buf + (kNT * c + r) * C::STRIDE + h * C::HALF;
             constexpr int PF = KS < kBAhead / NC + 1 ? KS : kBAhead / NC + 1;
             bf16x8 bq[PF + 1];
@@ -726,29 +749,23 @@ __global__ void __launch_bounds__(64 * WAVES) k_filter_bf16(QueryArgs a, FilterA
                 for (int t = 0; t < MT; ++t)
                     acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[t][s], bq[s % (PF + 1)], acc[t], 0, 0, 0);
             }
-            __builtin_amdgcn_sched_group_barrier(0x100, PF, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, PF + 4 * MT, 0);
             pin_schedule<PF, MT, 0, KS>();
             const int64_t pos = tl * C::TS + kNT * c + r;
-            // candidate iff fl(acc + H/2) >= G/2, as in k_filter
+            // candidate iff acc >= G/2 (acc = H/2 + q~.x~), with the integer maximum first, as in k_filter
             const float Gh = Ghs[c];
-            float best = -kInf;
+            int best = -2147483647 - 1;
 #pragma unroll
             for (int t = 0; t < MT; ++t)
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const float4 H4 = *reinterpret_cast<const float4*>(&s_H[row_base + 32 * t + 8 * g + 4 * h]);
-                    best = fmaxf(best, fmaxf(acc[t][4 * g] + H4.x, acc[t][4 * g + 1] + H4.y));
-                    best = fmaxf(best, fmaxf(acc[t][4 * g + 2] + H4.z, acc[t][4 * g + 3] + H4.w));
-                }
-            if (__ballot(best >= Gh)) {
+                for (int e = 0; e < 16; e += 2)
+                    best = max(max(best, __float_as_int(acc[t][e])), __float_as_int(acc[t][e + 1]));
+            if (__ballot(!(Gh > 0.f) || best >= __float_as_int(Gh))) {
                 unsigned hit = 0u;
 #pragma unroll
                 for (int t = 0; t < MT; ++t)
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        const int row = 32 * t + 8 * (e >> 2) + 4 * h + (e & 3);
-                        hit |= (acc[t][e] + s_H[row_base + row] >= Gh ? 1u : 0u) << (16 * t + e);
-                    }
+                    for (int e = 0; e < 16; ++e) hit |= (acc[t][e] >= Gh ? 1u : 0u) << (16 * t + e);
                 hit &= pos < a.n ? valid : 0u;
                 // one hit per lane and round, at slot wcount + (rank among the lanes with a hit)
                 for (;;) {

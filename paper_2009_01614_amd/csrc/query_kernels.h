@@ -5,7 +5,8 @@
 namespace isax {
 
 // Per-query statistics slots (unsigned long long each).
-enum { ST_LEAVES = 0, ST_LEAVES_KEPT, ST_SERIES_LB, ST_REFINED, ST_REFINE_BYTES, ST_CANDS, ST_DTW, ST_DTW_CELLS, ST_N };
+enum { ST_LEAVES = 0, ST_LEAVES_KEPT, ST_SERIES_LB, ST_REFINED, ST_REFINE_BYTES, ST_CANDS, ST_DTW, ST_DTW_CELLS,
+       ST_PRECHECKED /* series bounded with their BF16 row before refinement */, ST_N };
 
 // Everything one batch of queries needs on the device.  Passed by value.
 struct QueryArgs {

@@ -1113,7 +1113,7 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
         const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
         const bool abandon = !(a.flags & ISAX_QF_NO_EARLY_ABANDON);
         const bool series_lb = !(DTW && a.all_leaves);
-        unsigned long long n_lb = 0, n_ref = 0, n_bytes = 0, n_emit = 0, n_dtw = 0, n_cells = 0;
+        unsigned long long n_lb = 0, n_ref = 0, n_bytes = 0, n_emit = 0, n_dtw = 0, n_cells = 0, n_pc = 0;
         int* my_wl = wl + wave * 64;
         int* dq = reinterpret_cast<int*>(smem + L.off_dq) + wave * kDtwQueue;
         int dn = 0;  // queued series of this wave (the same in every lane)
@@ -1203,6 +1203,7 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                             dn = rest;
                         }
                     } else {
+                        if (my < nc && a.pc_x && gl == 0) ++n_pc;
                         if (my < nc && !(a.pc_x && precheck16(a, pa + my_wl[my], qrow, gl, pc_qn, pc_nq) > thr)) {
                             const int64_t p2 = pa + my_wl[my];
                             const int32_t id = a.ids_sorted[p2];
@@ -1232,6 +1233,7 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
         if ((lane & 15) == 0) {
             atomicAdd(&s_st[ST_REFINED], n_ref);
             atomicAdd(&s_st[ST_REFINE_BYTES], n_bytes);
+            if (n_pc) atomicAdd(&s_st[ST_PRECHECKED], n_pc);
         }
         if (DTW) {
             atomicAdd(&s_st[ST_CANDS], n_emit);

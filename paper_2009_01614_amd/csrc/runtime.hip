@@ -780,7 +780,9 @@ double scan_bytes(const Batch& b, const isax_index* idx, hipStream_t s, const st
         const unsigned long long* r = &st[(size_t)i * ST_N];
         double leaf_bytes = 2.0 * idx->ws * r[ST_LEAVES];
         if (!cnt.empty()) leaf_bytes = cnt[i] <= b.a.leaf_cap ? 16.0 * cnt[i] : 2.0 * leaf_bytes;
-        tot += leaf_bytes + (double)idx->ws * r[ST_SERIES_LB] + (double)r[ST_REFINE_BYTES];
+        // the refinement precheck reads a BF16 row and its metadata per series
+        tot += leaf_bytes + (double)idx->ws * r[ST_SERIES_LB] + (double)r[ST_REFINE_BYTES] +
+               (2.0 * b.a.pc_stride + 16.0) * r[ST_PRECHECKED];
     }
     return tot;
 }

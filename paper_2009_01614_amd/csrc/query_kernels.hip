@@ -213,33 +213,39 @@ __device__ float dtw_lane(const float* qpad, const float* __restrict__ row, int 
 // refill: a lane that finishes or abandons takes the next queued series, so
 // lanes do not idle while the longest series of a batch runs to the end.  The
 // grid is walked row by row here (i = query index), band cells D[d] =
-// D(i, i - r + d) and the matching series values xw[d] = x_{i-r+d} in
-// registers (+inf outside the series or the band); from row i-1 to i:
-//   D(i-1, j-1) = old D[d],  D(i-1, j) = old D[d+1],  D(i, j-1) = new D[d-1],
-// and the x window moves down one cell, x_{i+r+1} entering at cell 2r.
-// A lane abandons once a whole row exceeds the bound (every warping path
-// crosses every row).  Results within the bound are emitted.
-template <int RB, bool VEC>
-__device__ void dtw_drain(const QueryArgs& a, int q, int k, const float* qpad, const int* dq, int dn, bool abandon,
-                          int lane, unsigned long long lt, unsigned long long& n_dtw, unsigned long long& n_cells,
-                          unsigned long long& n_emit) {
-    const int r = a.window, B = 2 * r + 1, len = a.len;
-    float D[RB], xw[RB];
+// D(i, i - r + d), d < B = 2r + 1 (a compile-time width); from row i-1 to i:
+//   D(i-1, j-1) = old D[d],  D(i-1, j) = old D[d+1],  D(i, j-1) = new D[d-1].
+// Rows go in groups of four: at a group's first row i0 the registers W[t] hold
+// x_{i0-r+t}, t < B + 3 (+inf outside the series), and row i0 + e takes cell
+// d's series value from W[d + e], so the window moves by four cells once per
+// group instead of one cell per row.  A lane abandons once a whole row exceeds
+// the bound (every warping path crosses every row).  Results within the bound
+// are emitted.
+struct DrainCounts {
+    unsigned long long dtw, cells, emit;
+};
+template <int B, bool VEC>
+__device__ DrainCounts dtw_drain(const QueryArgs& a, int q, int k, const float* qpad,
+                                                           const int* dq, int dn, bool abandon, int lane,
+                                                           unsigned long long lt) {
+    unsigned long long n_dtw = 0, n_cells = 0, n_emit = 0;
+    constexpr int r = (B - 1) / 2;
+    const int len = a.len;
+    float D[B], W[B + 3];
 #pragma unroll
-    for (int d = 0; d < RB; ++d) {
-        D[d] = kInf;
-        xw[d] = kInf;
-    }
+    for (int d = 0; d < B; ++d) D[d] = kInf;
+#pragma unroll
+    for (int t = 0; t < B + 3; ++t) W[t] = kInf;
     int row = len;  // >= len: no series
     int32_t id = 0;
     const float* x = a.data;
     int head = 0;
     float thr = read_tau(a, q, k) * a.tau_scale;
-    float xn[4];  // series values entering the window in the next four rows, loaded a step ahead
+    float xn[4];  // the values entering the window at the end of the next group, loaded a group ahead
     auto load_xn = [&]() {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int jn = row + e + 1 + r;
+            const int jn = row + 4 + r + e;
             xn[e] = jn < len ? x[jn] : kInf;
         }
     };
@@ -256,10 +262,11 @@ __device__ void dtw_drain(const QueryArgs& a, int q, int k, const float* qpad, c
                 x = series_row(a, pos, id);
                 row = 0;
 #pragma unroll
-                for (int d = 0; d < RB; ++d) {
-                    const int j = d - r;
-                    D[d] = d == r ? 0.f : kInf;
-                    xw[d] = (d < B && j >= 0 && j < len) ? x[j] : kInf;
+                for (int d = 0; d < B; ++d) D[d] = d == r ? 0.f : kInf;
+#pragma unroll
+                for (int t = 0; t < B + 3; ++t) {
+                    const int j = t - r;
+                    W[t] = (j >= 0 && j < len) ? x[j] : kInf;
                 }
                 load_xn();
                 ++n_dtw;
@@ -286,48 +293,83 @@ __device__ void dtw_drain(const QueryArgs& a, int q, int k, const float* qpad, c
 #pragma unroll
             for (int e = 0; e < 4; ++e) xc[e] = xn[e];
             row += 4;
-            load_xn();  // next step's values (+inf past the end), in flight during this step
+            load_xn();  // the group after this one (+inf past the end), in flight during this group
             row -= 4;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                // with len % 4 == 0 (VEC) every row of the step exists: no per-lane branch, so
+                // with len % 4 == 0 (VEC) every row of the group exists: no per-lane branch, so
                 // the band is not held twice across it
                 if (VEC || row + e < len) {
                     float left = kInf;
 #pragma unroll
-                    for (int d = 0; d < RB; ++d) {
-                        const float df = qv[e] - xw[d];
-                        const float up = d + 1 < RB ? D[d + 1] : kInf;
+                    for (int d = 0; d < B; ++d) {
+                        const float df = qv[e] - W[d + e];
+                        const float up = d + 1 < B ? D[d + 1] : kInf;
                         const float m = fminf(fminf(D[d], up), left);
                         D[d] = fmaf(df, df, m);
                         left = D[d];
                     }
-#pragma unroll
-                    for (int d = 0; d < RB; ++d) xw[d] = d + 1 == B ? xc[e] : (d + 1 < RB ? xw[d + 1] : kInf);
                 }
             }
+#pragma unroll
+            for (int t = 0; t < B + 3; ++t) W[t] = t + 4 < B + 3 ? W[t + 4] : xc[t - (B - 1)];
         }
         if (active) {
             const int done_rows = min(4, len - row);
             n_cells += (unsigned long long)done_rows * B;
             row += 4;
             if (row >= len) {
-                float res = kInf;
-#pragma unroll
-                for (int d = 0; d < RB; ++d)
-                    if (d == r) res = D[d];
-                if (res <= thr) {
-                    emit(a, q, k, res, id);
+                if (D[r] <= thr) {
+                    emit(a, q, k, D[r], id);
                     ++n_emit;
                 }
             } else if (abandon) {
                 float mn = D[0];
 #pragma unroll
-                for (int d = 1; d < RB; ++d) mn = fminf(mn, D[d]);
+                for (int d = 1; d < B; ++d) mn = fminf(mn, D[d]);
                 if (mn > thr) row = len;
             }
         }
     }
+    return DrainCounts{n_dtw, n_cells, n_emit};
+}
+
+// The drain for the bands of register class RB (the kernel's template), with
+// the band width as a compile-time constant.
+template <int RB, bool VEC>
+__device__ void dtw_drain_for(const QueryArgs& a, int q, int k, const float* qpad, const int* dq, int dn,
+                              bool abandon, int lane, unsigned long long lt, unsigned long long& n_dtw,
+                              unsigned long long& n_cells, unsigned long long& n_emit) {
+    DrainCounts c{0, 0, 0};
+#define ISAX_DRAIN(BW) c = dtw_drain<BW, VEC>(a, q, k, qpad, dq, dn, abandon, lane, lt)
+    if constexpr (RB == 56) {
+        switch (a.window) {
+            case 24: ISAX_DRAIN(49); break;
+            case 25: ISAX_DRAIN(51); break;
+            case 26: ISAX_DRAIN(53); break;
+            default: ISAX_DRAIN(55); break;
+        }
+    } else if constexpr (RB == 48) {
+        switch (a.window) {
+            case 20: ISAX_DRAIN(41); break;
+            case 21: ISAX_DRAIN(43); break;
+            case 22: ISAX_DRAIN(45); break;
+            default: ISAX_DRAIN(47); break;
+        }
+    } else if constexpr (RB == 40) {
+        switch (a.window) {
+            case 16: ISAX_DRAIN(33); break;
+            case 17: ISAX_DRAIN(35); break;
+            case 18: ISAX_DRAIN(37); break;
+            default: ISAX_DRAIN(39); break;
+        }
+    } else {
+        ISAX_DRAIN(RB - 1);
+    }
+#undef ISAX_DRAIN
+    n_dtw += c.dtw;
+    n_cells += c.cells;
+    n_emit += c.emit;
 }
 
 // LB_Keogh^2 of one row against the query envelope (U, L in LDS) by a group of
@@ -1015,7 +1057,7 @@ template <bool VEC, bool T_LDS, int RB>
 __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
     constexpr bool DTW = RB > 0;
     // queue drained with lane refill (dtw_drain) for the bands where it measured faster
-    constexpr bool REFILL = RB == 48 || RB == 56;
+    constexpr bool REFILL = RB == 40 || RB == 48 || RB == 56;
     extern __shared__ unsigned char smem[];
     const ScanSmem L = scan_smem(a.ns, a.w, a.len, DTW, T_LDS);
     float* lo_e = reinterpret_cast<float*>(smem + L.off_lo);
@@ -1186,7 +1228,7 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                         dn += __popcll(sm);
                         __builtin_amdgcn_wave_barrier();
                         if (REFILL && dn >= kDtwDrainAt) {
-                            dtw_drain<REFILL ? RB : 8, VEC>(a, q, k, qrow, dq, dn, abandon, lane, lt, n_dtw, n_cells,
+                            dtw_drain_for<REFILL ? RB : 8, VEC>(a, q, k, qrow, dq, dn, abandon, lane, lt, n_dtw, n_cells,
                                                             n_emit);
                             __builtin_amdgcn_wave_barrier();
                             dn = 0;
@@ -1226,7 +1268,7 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
             }
         }
         if (DTW && dn > 0) {
-            if (REFILL) dtw_drain<REFILL ? RB : 8, VEC>(a, q, k, qrow, dq, dn, abandon, lane, lt, n_dtw, n_cells, n_emit);
+            if (REFILL) dtw_drain_for<REFILL ? RB : 8, VEC>(a, q, k, qrow, dq, dn, abandon, lane, lt, n_dtw, n_cells, n_emit);
             else dtw_batch(dn);
         }
         atomicAdd(&s_st[ST_SERIES_LB], lane == 0 ? n_lb : 0ull);
@@ -1640,7 +1682,7 @@ void launch_qprep(const QueryArgs& a, hipStream_t s) {
 // Band cells held in registers for a DTW band of half-width r.
 int dtw_band_regs(int r) {
     const int B = 2 * r + 1;
-    return B <= 8 ? 8 : B <= 16 ? 16 : B <= 32 ? 32 : B <= 48 ? 48 : B <= 56 ? 56 : 64;
+    return B <= 8 ? 8 : B <= 16 ? 16 : B <= 32 ? 32 : B <= 40 ? 40 : B <= 48 ? 48 : B <= 56 ? 56 : 64;
 }
 
 void launch_homeleaf(const QueryArgs& a, hipStream_t s) {
@@ -1654,6 +1696,7 @@ void launch_homeleaf(const QueryArgs& a, hipStream_t s) {
             case 8: k_homeleaf<8><<<a.mq, 256, lds, s>>>(a); break;
             case 16: k_homeleaf<16><<<a.mq, 256, lds, s>>>(a); break;
             case 32: k_homeleaf<32><<<a.mq, 256, lds, s>>>(a); break;
+            case 40: k_homeleaf<40><<<a.mq, 256, lds, s>>>(a); break;
             case 48: k_homeleaf<48><<<a.mq, 256, lds, s>>>(a); break;
             case 56: k_homeleaf<56><<<a.mq, 256, lds, s>>>(a); break;
             default: k_homeleaf<64><<<a.mq, 256, lds, s>>>(a); break;
@@ -1724,6 +1767,7 @@ void launch_index_scan_t(const QueryArgs& a, const dim3& grid, hipStream_t s) {
         case 8: k_index_scan<VEC, TL, 8><<<grid, 256, L.total, s>>>(a); break;
         case 16: k_index_scan<VEC, TL, 16><<<grid, 256, L.total, s>>>(a); break;
         case 32: k_index_scan<VEC, TL, 32><<<grid, 256, L.total, s>>>(a); break;
+        case 40: k_index_scan<VEC, TL, 40><<<grid, 256, L.total, s>>>(a); break;
         case 48: k_index_scan<VEC, TL, 48><<<grid, 256, L.total, s>>>(a); break;
         case 56: k_index_scan<VEC, TL, 56><<<grid, 256, L.total, s>>>(a); break;
         default: k_index_scan<VEC, TL, 64><<<grid, 256, L.total, s>>>(a); break;

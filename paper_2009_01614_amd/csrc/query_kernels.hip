@@ -342,7 +342,14 @@ __device__ void dtw_drain_for(const QueryArgs& a, int q, int k, const float* qpa
                               unsigned long long& n_cells, unsigned long long& n_emit) {
     DrainCounts c{0, 0, 0};
 #define ISAX_DRAIN(BW) c = dtw_drain<BW, VEC>(a, q, k, qpad, dq, dn, abandon, lane, lt)
-    if constexpr (RB == 56) {
+    if constexpr (RB == 64) {
+        switch (a.window) {
+            case 28: ISAX_DRAIN(57); break;
+            case 29: ISAX_DRAIN(59); break;
+            case 30: ISAX_DRAIN(61); break;
+            default: ISAX_DRAIN(63); break;
+        }
+    } else if constexpr (RB == 56) {
         switch (a.window) {
             case 24: ISAX_DRAIN(49); break;
             case 25: ISAX_DRAIN(51); break;
@@ -1057,7 +1064,7 @@ template <bool VEC, bool T_LDS, int RB>
 __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
     constexpr bool DTW = RB > 0;
     // queue drained with lane refill (dtw_drain) for the bands where it measured faster
-    constexpr bool REFILL = RB == 40 || RB == 48 || RB == 56;
+    constexpr bool REFILL = RB >= 40;
     extern __shared__ unsigned char smem[];
     const ScanSmem L = scan_smem(a.ns, a.w, a.len, DTW, T_LDS);
     float* lo_e = reinterpret_cast<float*>(smem + L.off_lo);

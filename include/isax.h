@@ -76,10 +76,13 @@ enum {
     ISAX_QF_NO_PRECHECK = 128     /* read rows directly.  By default (ED, an index with the full-row BF16
                                      copy) a series that survives the iSAX bounds is first bounded from
                                      below with its BF16 row, approx - M as in the filter, and its row is
-                                     read only if that bound is within the best-so-far; for a collection in
-                                     pinned host memory the approximate answer does the same, reading only
-                                     the series whose bound is within the k-th smallest upper bound
-                                     approx + M of its leaves */
+                                     read only if that bound is within the best-so-far (in device memory
+                                     where sampled refinements show early abandoning reading more FP32
+                                     bytes per series than the BF16 row holds; in host memory always); for
+                                     a collection in pinned host memory the approximate answer does the
+                                     same, reading only the series whose bound is within the k-th smallest
+                                     upper bound approx + M of its leaves.  Answers are the same either
+                                     way */
 };
 
 /* Distance measures (isax_query_options.metric). */

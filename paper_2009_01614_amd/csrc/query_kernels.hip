@@ -1086,6 +1086,17 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
     const int k = a.kq[q];
     // (the refinement precheck's query norms)
     const float pc_qn = a.pc_x ? a.qinfo[q].x : 0.f, pc_nq = sqrtf(pc_qn) * (1.f + 0x1p-20f);
+    // The precheck reads a BF16 row and its metadata; it pays where early abandoning
+    // reads more FP32 bytes than that per series.  A wave refines the candidates of its
+    // first step (4 per step, one per group of 16 lanes) and then of every 64th step
+    // without it, and prechecks the others while the FP32 bytes of those samples
+    // average above the BF16 row's (rows in host memory: always, an FP32 read crosses
+    // the bus there).  The choice is the same in the whole wave, so its groups do not
+    // take both paths in one step.  Either way a series whose FP32 distance can be
+    // within the bound is refined, so the answer is the same.
+    const float pc_row = 2.f * a.pc_stride + 16.f;
+    unsigned pc_it = 0;
+    float pc_n = 0.f, pc_b = 0.f;  // wave-uniform
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t leaf_id = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t h0 = a.home[2 * q], h1 = a.home[2 * q + 1];
@@ -1252,13 +1263,19 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                             dn = rest;
                         }
                     } else {
-                        if (my < nc && a.pc_x && gl == 0) ++n_pc;
-                        if (my < nc && !(a.pc_x && precheck16(a, pa + my_wl[my], qrow, gl, pc_qn, pc_nq) > thr)) {
+                        // (uniform across the wave)
+                        const bool sample = a.pc_x && !a.pc_home && (pc_it & 63) == 0;
+                        const bool use_pc = a.pc_x && !sample && (a.pc_home || pc_b > pc_row * pc_n);
+                        ++pc_it;
+                        float sb = 0.f;  // this group's sampled FP32 bytes (its first lane)
+                        if (my < nc && use_pc && gl == 0) ++n_pc;
+                        if (my < nc && !(use_pc && precheck16(a, pa + my_wl[my], qrow, gl, pc_qn, pc_nq) > thr)) {
                             const int64_t p2 = pa + my_wl[my];
                             const int32_t id = a.ids_sorted[p2];
                             const float* row = series_row(a, p2, id);
                             int steps = 0;
                             const float d2 = refine16<VEC>(row, qrow, a.len, gl, thr, abandon, steps);
+                            if (sample && gl == 0) sb = (float)(min(a.len, steps * 64) * 4);
                             if (gl == 0) {
                                 ++n_ref;
                                 n_bytes += (unsigned long long)min(a.len, steps * 64) * 4ull;
@@ -1267,6 +1284,13 @@ __global__ void __launch_bounds__(256) k_index_scan(QueryArgs a) {
                                     ++n_emit;
                                 }
                             }
+                        }
+                        if (sample) {
+                            // the wave's sums over its groups' first lanes (0, 16, 32, 48)
+                            sb += __shfl_xor(sb, 16, 64);
+                            sb += __shfl_xor(sb, 32, 64);
+                            pc_b += __shfl(sb, 0, 64);
+                            pc_n += (float)__popcll(__ballot(my < nc && gl == 0));
                         }
                         thr = read_tau(a, q, k) * a.tau_scale;
                     }

@@ -162,3 +162,21 @@ def test_dtw_metamorphic_summaries(isax, coll, w, c):
     ref_ids, ref_d2 = _ref(coll, 12)
     ids, d = idx.query(coll["Q"], k=5, metric="dtw", window=12)
     _check(ids, d, ref_ids, ref_d2, 5)
+
+
+@pytest.fixture(scope="module")
+def wide(isax):
+    X = workload.random_walks(12_007, 128, seed=7011, device="cuda")
+    Qn, _, _ = workload.noisy_queries(X, 4, seed=7012)
+    Q = torch.cat([Qn, workload.fresh_queries(2, 128, seed=7013, device="cuda")]).contiguous()
+    return {"X": X, "Q": Q, "idx": isax.Index(X, 16, 8, leaf_size=64)}
+
+
+@pytest.mark.parametrize("r", list(range(16, 32)))
+def test_dtw_every_drain_width(isax, wide, r):
+    # windows 16-31 drain their queued series with a band width fixed at compile time
+    # (four widths per register class): each width against the oracle, both modes
+    ref_ids, ref_d2 = kr.knn_dtw_c(_cpu(wide["X"]), _cpu(wide["Q"]), 5, r)
+    for mode in ("index", "scan"):
+        ids, d = wide["idx"].query(wide["Q"], k=5, mode=mode, metric="dtw", window=r)
+        _check(ids, d, ref_ids, ref_d2, 5)

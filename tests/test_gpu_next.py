@@ -195,3 +195,22 @@ def test_host_alloc_rows(isax):
         rows.close()
     with pytest.raises(isax.IsaxError, match="bytes must be > 0"):
         isax.HostRows(0, 256)
+
+
+def test_precheck_choice_on_clustered_vectors(isax):
+    # 384-dimensional clustered vectors, 16 segments: early abandoning stops most FP32
+    # rows after their first step, so waves mostly skip the precheck; answers are the
+    # oracle's and the same with the precheck switched off
+    g = torch.Generator(device="cuda").manual_seed(384)
+    centres = torch.randn(200, 384, device="cuda", generator=g) * 3.0
+    lab = torch.randint(0, 200, (60_001,), device="cuda", generator=g)
+    E = (centres[lab] + torch.randn(60_001, 384, device="cuda", generator=g) * 0.7).contiguous()
+    Q = (centres[torch.randint(0, 200, (40,), device="cuda", generator=g)] +
+         torch.randn(40, 384, device="cuda", generator=g) * 0.7).contiguous()
+    idx = isax.Index(E, 16, 8, precision=isax.PREC_BF16)
+    ref_ids, ref_d2 = kr.knn_exact_c(E.cpu().numpy(), Q.cpu().numpy(), 10)
+    a, da = idx.query(Q, k=10, mode="index")
+    b, db = idx.query(Q, k=10, mode="index", flags=isax.QF_NO_PRECHECK)
+    assert np.array_equal(a.cpu().numpy(), ref_ids)
+    assert np.allclose(da.cpu().numpy(), np.sqrt(ref_d2), rtol=1e-4, atol=0)
+    assert torch.equal(a, b) and torch.equal(da, db)

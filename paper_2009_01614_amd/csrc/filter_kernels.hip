@@ -987,6 +987,17 @@ __global__ void __launch_bounds__(256) k_copy_rows(QueryArgs sa, FilterArgs sf, 
 // Large batches: 8 waves x 64 queries per block, one block per CU.  Small
 // batches (<= 64 queries): 2 waves x 32 queries, four blocks per CU; the pass is
 // then bound by reading the reduced-precision copy, not by the matrix cores.
+// Blocks of a kernel resident per CU (its registers and LDS), at least 1.
+template <typename Kernel>
+int resident_blocks(Kernel kernel, int threads) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    return nb;
+}
+
 template <int KIND, int KS, int MT, int WAVES>
 void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qmax, hipStream_t s) {
     // (the wide setting only where its double buffer fits the 160 KB of LDS: rows up to 512 bytes)
@@ -999,7 +1010,6 @@ void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qm
     // the kernel reads query rows [0, qtiles * QPB): they must exist in the padded codes
     if ((int64_t)qtiles * C::QPB > f.mq_pad)
         throw Error{ISAX_EINVAL, "internal: query codes padded to fewer rows than the filter reads"};
-    const int per_cu = WAVES >= 8 ? 1 : 4;
     static_assert(kFilterAlign % C::TS == 0, "the sample units and serving chunks start on a tile");
     constexpr int R = kFilterAlign / C::TS;
     const int64_t all_tiles = (a.n + C::TS - 1) / C::TS;
@@ -1015,18 +1025,27 @@ void launch_filter_t(const QueryArgs& a, const FilterArgs& f, const unsigned* qm
         n_tiles = (t_hi - filter_samples_before(t_hi, R)) - (t_lo - filter_samples_before(t_lo, R));
     }
     if (n_tiles <= 0) return;
-    // n_streams * qtiles blocks, n_streams a multiple of 8 (one group per XCD)
-    int n_streams = std::max(8, (per_cu * cus / qtiles) / 8 * 8);
-    while (n_streams > 8 && n_streams / 2 >= n_tiles) n_streams /= 2;
-    const int blocks = n_streams * qtiles;
+    // n_streams * qtiles blocks, n_streams a multiple of 8 (one group per XCD); up to 4 blocks
+    // per CU for the smaller classes, but no more than fit at once (registers and LDS), so the
+    // grid runs in whole rounds: 4 requested where 3 fit left the last third of the blocks
+    // running on a quarter of the chip
+    auto go = [&](auto kernel, int resident) {
+        const int per_cu = WAVES >= 8 ? 1 : std::min(4, resident);
+        int n_streams = std::max(8, (per_cu * cus / qtiles) / 8 * 8);
+        while (n_streams > 8 && n_streams / 2 >= n_tiles) n_streams /= 2;
+        const int blocks = n_streams * qtiles;
+        kernel<<<blocks, C::THREADS, 0, s>>>(a, f, qtiles, n_streams, qmax);
+    };
     if (f.out_approx) {
-        k_filter<KIND, KS, MT, WAVES, NC, true><<<blocks, C::THREADS, 0, s>>>(a, f, qtiles, n_streams, qmax);
+        go(k_filter<KIND, KS, MT, WAVES, NC, true>, 1);
     } else if constexpr (KIND == 0 && WAVES == 2 && DmaCfg<KS, MT, WAVES, NC>::LDS <= 160 * 1024) {
         // the 64-query class is bound by streaming the BF16 copy: whole-tile DMA prefetch
         // (100M x 256: 8.6 against 9.3 ms; the larger classes were 5-7% slower with it)
-        k_filter_bf16<KS, MT, WAVES, NC><<<blocks, C::THREADS, 0, s>>>(a, f, qtiles, n_streams, qmax);
+        static const int res = resident_blocks(k_filter_bf16<KS, MT, WAVES, NC>, C::THREADS);
+        go(k_filter_bf16<KS, MT, WAVES, NC>, res);
     } else {
-        k_filter<KIND, KS, MT, WAVES, NC, false><<<blocks, C::THREADS, 0, s>>>(a, f, qtiles, n_streams, qmax);
+        static const int res = resident_blocks(k_filter<KIND, KS, MT, WAVES, NC, false>, C::THREADS);
+        go(k_filter<KIND, KS, MT, WAVES, NC, false>, res);
     }
 }
 

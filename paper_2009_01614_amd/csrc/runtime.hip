@@ -845,9 +845,9 @@ constexpr double kFilterFlopsNarrow = 0.8e15;
 constexpr double kFilterPerQuery = 10e-6;
 // The spectral copy (fewer coefficients than the padded length) streams at
 // about kSpectralStreamBps and computes at kSpectralRate of the rates above
-// (fitted to 100M x 256 with 192 coefficients: 8.8 ms for 1-100 queries, 13.3
-// for 256, 19.0 for 512, 35.8 for 1000).
-constexpr double kSpectralStreamBps = 4.5e12;
+// (fitted to 100M x 256 with 192 coefficients: 7.4 ms for 1-64 queries, 8.1
+// for 100, 9.3 for 128, 14.1 for 256, 19.4 for 512, 35.8 for 1000).
+constexpr double kSpectralStreamBps = 5.4e12;
 constexpr double kSpectralRate = 0.74;
 // The hybrid's own work before and around the split (leaf pass, round 1, a
 // second approximate answer for the filter's queries, more synchronisation):

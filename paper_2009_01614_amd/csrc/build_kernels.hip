@@ -631,20 +631,23 @@ __global__ void __launch_bounds__(256) k_quantise(const float* __restrict__ data
 // ext(x) = (y_0 .. y_{D-2}, t) with t = sqrt(|x|^2 - |y_head|^2) the norm of the
 // dropped coefficients, and its BF16 codes.  A block takes tiles of 64 series,
 // staged through LDS kSpecChunk points at a time (rows of kSpecChunk + 1
-// floats: lanes read distinct banks); wave g computes coefficients
-// [g DQ, (g + 1) DQ) of every series of the tile, one series per lane, the
-// coefficients of T coming through scalar loads.
+// floats: lanes read distinct banks) together with the same kSpecChunk rows of
+// T; wave g computes coefficients [g DQ, (g + 1) DQ) of every series of the
+// tile, one series per lane, reading T from LDS (the same address in every
+// lane: one broadcast read per two coefficients).  Each coefficient sums its
+// products in point order, as a plain loop over the points would.
 // meta[p] = {|x|^2, |ext(x) - x~| (up), |x~| (up), 1}: the FP64 transform (T
 // within 2^-50 relative, sums of at most 512 terms) puts the head within
 // 1e-12 |x| of the exact one and the tail norm, from a difference of squares,
 // within 1.5e-6 |x|; 2^-18 |x| is added to |ext(x) - x~| for both.
-constexpr int kSpecChunk = 128;
+constexpr int kSpecChunk = 32;
 template <int DQ>
 __global__ void __launch_bounds__(256) k_spectral(const float* __restrict__ data, const int32_t* __restrict__ ids,
                                                   int64_t n, int len, const double* __restrict__ tt,
                                                   uint16_t* __restrict__ xs, float4* __restrict__ meta) {
     constexpr int D = 4 * DQ, JC = kSpecChunk;
     __shared__ float sx[64][JC + 1];
+    __shared__ __attribute__((aligned(16))) double sT[JC * D];  // rows j0 .. j0 + JC - 1 of T
     __shared__ double s_head[4][64], s_err[4][64], s_code[4][64];
     const int lane = threadIdx.x & 63;
     const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -655,22 +658,30 @@ __global__ void __launch_bounds__(256) k_spectral(const float* __restrict__ data
 #pragma unroll
         for (int r = 0; r < DQ; ++r) acc[r] = 0.0;
         double xn = 0.0;
-        const double* tg = tt + g * DQ;
         for (int j0 = 0; j0 < len; j0 += JC) {
             const int jn = min(JC, len - j0);
-            __syncthreads();  // the previous chunk's points are no longer read
+            __syncthreads();  // the previous chunk's points and rows of T are no longer read
             for (int e = threadIdx.x; e < 64 * JC; e += 256) {
                 const int r = e / JC, j = e % JC;
                 const int64_t p = p0 + r;
                 sx[r][j] = p < n && j < jn ? data[(int64_t)ids[p] * len + j0 + j] : 0.f;
             }
+            {
+                const double2* src = reinterpret_cast<const double2*>(tt + (int64_t)j0 * D);
+                double2* dst = reinterpret_cast<double2*>(sT);
+                for (int e = threadIdx.x; e < jn * D / 2; e += 256) dst[e] = src[e];
+            }
             __syncthreads();
             for (int j = 0; j < jn; ++j) {
                 const double v = (double)sx[lane][j];
                 xn = fma(v, v, xn);
-                const double* tj = tg + (int64_t)(j0 + j) * D;
+                const double2* tj = reinterpret_cast<const double2*>(sT + j * D + g * DQ);
 #pragma unroll
-                for (int r = 0; r < DQ; ++r) acc[r] = fma(tj[r], v, acc[r]);
+                for (int r = 0; r < DQ / 2; ++r) {
+                    const double2 t2 = tj[r];
+                    acc[2 * r] = fma(t2.x, v, acc[2 * r]);
+                    acc[2 * r + 1] = fma(t2.y, v, acc[2 * r + 1]);
+                }
             }
         }
         double hs = 0.0;

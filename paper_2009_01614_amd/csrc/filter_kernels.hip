@@ -867,12 +867,18 @@ __global__ void __launch_bounds__(256) k_refine_filtered(QueryArgs a, FilterArgs
     __syncthreads();
     const int g = threadIdx.x >> 4, gl = threadIdx.x & 15;
     const bool abandon = !(a.flags & ISAX_QF_NO_EARLY_ABANDON);
+    // candidates of the spectral copy, whose bound is looser than the full rows': bounded
+    // again with the full-row BF16 copy where the index holds it, before their FP32 rows
+    // are read (the refinement precheck of the iSAX scan)
+    const bool pc = f.spec && a.pc_x;
+    const float pc_qn = pc ? a.qinfo[q].x : 0.f, pc_nq = sqrtf(pc_qn) * (1.f + 0x1p-20f);
     unsigned long long n_ref = 0, n_bytes = 0, n_emit = 0;
     for (unsigned i = blockIdx.x * 16 + g; i < cnt; i += gridDim.x * 16) {
         const unsigned pos = f.fcand[(int64_t)q * f.fcap + i];
+        const float thr = read_tau(a, q, k) * a.tau_scale;
+        if (pc && precheck16(a, pos, qrow, gl, pc_qn, pc_nq) > thr) continue;  // the same in the group's lanes
         const int32_t id = a.ids_sorted[pos];
         const float* row = series_row(a, pos, id);
-        const float thr = read_tau(a, q, k) * a.tau_scale;
         const int S = (a.len + 63) >> 6;
         float acc = 0.f;
         int steps = 0;

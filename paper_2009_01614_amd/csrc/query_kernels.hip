@@ -61,13 +61,6 @@ __device__ inline void emit(const QueryArgs& a, int q, int k, float d2, int32_t 
     if (!a.rerun && !(a.flags & ISAX_QF_NO_SHARING)) bestk_insert(a.bestk + (int64_t)q * a.kmax, k, key);
 }
 
-__device__ inline float sum16(float v) {
-    v += __shfl_xor(v, 1, 16);
-    v += __shfl_xor(v, 2, 16);
-    v += __shfl_xor(v, 4, 16);
-    v += __shfl_xor(v, 8, 16);
-    return v;
-}
 __device__ inline float sum64(float v) {
     for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -110,29 +103,6 @@ __device__ float refine16(const float* __restrict__ row, const float* qrow, int 
     return sum16(acc);
 }
 
-// Lower bound on ED^2 of the query (qrow, FP32, in LDS) to the series at sorted
-// position p from its BF16 copy, by a group of 16 lanes (the same value in all
-// of them): approx - M with approx = |q|^2 + |x|^2 - 2 fl(q.x~) and
-// M = 2 (|q| |e_x| + gamma |q| |x~|) + kappa (|q|^2 + |x|^2), since
-// q.x - q.x~ = q.e_x, the FP32 dot of len terms is within gamma |q| |x~| of
-// q.x~, and kappa covers the FP32 norms and this sum.  qn = |q|^2 (FP32), nq >= |q|.
-__device__ inline float precheck16(const QueryArgs& a, int64_t p, const float* qrow, int gl, float qn, float nq) {
-    const uint16_t* xr = a.pc_x + p * a.pc_stride;
-    float s = 0.f;
-    for (int j0 = gl * 8; j0 < a.len; j0 += 128) {
-        const uint4 v = *reinterpret_cast<const uint4*>(xr + j0);
-        const unsigned w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-            if (j0 + e < a.len)
-                s = fmaf(qrow[j0 + e], __uint_as_float((e & 1) ? (w[e >> 1] & 0xFFFF0000u) : (w[e >> 1] << 16)), s);
-    }
-    s = sum16(s);
-    const float4 m = a.pc_meta[p];
-    const float approx = qn + m.x - 2.f * s;
-    const float M = (2.f * (nq * m.y + a.pc_gamma * nq * m.z) + a.pc_kappa * (qn + m.x)) * (1.f + 0x1p-20f);
-    return approx - M;
-}
 
 // ---------------------------------------------------------------------------------------------
 // DTW pieces.  The grid is D(i, j), i = query index, j = series index, band

@@ -165,8 +165,10 @@ def _dev_f32(t: torch.Tensor, name: str, allow_pinned: bool = False) -> torch.Te
 class HostRows:
     """Page-locked host memory from isax_host_alloc holding an FP32 [n, len] collection.
 
-    `tensor` is a CPU tensor over that memory (for filling it and for Index); keep this
-    object alive while any index uses the rows; close() (or deletion) releases them."""
+    `tensor` is a CPU tensor over that memory (for filling it and for Index).  The tensor
+    holds this object, so the memory lives as long as the tensor or anything keeping it (an
+    Index keeps its data tensor); close() releases it at once, and must not be called
+    while an index over the rows is still in use."""
 
     def __init__(self, n: int, length: int):
         import numpy as np
@@ -177,6 +179,7 @@ class HostRows:
         self._p = p
         arr = np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_float)), shape=(int(n), int(length)))
         self.tensor = torch.from_numpy(arr)
+        self.tensor._isax_host_rows = self  # the owner lives as long as the tensor
 
     def close(self):
         if getattr(self, "_p", None):

@@ -197,6 +197,33 @@ def test_host_alloc_rows(isax):
         isax.HostRows(0, 256)
 
 
+def test_host_rows_live_as_long_as_their_tensor(isax):
+    # an index keeps its data tensor, and the tensor keeps the page-locked block: dropping
+    # the HostRows object itself must not release memory the index still reads
+    import gc
+    import weakref
+    rows = isax.HostRows(30_011, 128)
+    owner = weakref.ref(rows)
+    t = rows.tensor
+    del rows
+    gc.collect()
+    assert owner() is not None, "the page-locked block was released while its tensor lives"
+    Xd = workload.random_walks(30_011, 128, seed=70, device="cuda")
+    t.copy_(Xd.cpu())
+    Q = workload.noisy_queries(Xd, 8, seed=71)[0].contiguous()
+    idx = isax.Index(t, 16, 8)
+    del t
+    gc.collect()
+    assert owner() is not None
+    ref_ids, _ = kr.knn_exact_c(Xd.cpu().numpy(), Q.cpu().numpy(), 5)
+    ids, _ = idx.query(Q, k=5, mode="index")
+    assert np.array_equal(ids.cpu().numpy(), ref_ids)
+    idx.close()
+    del idx
+    gc.collect()
+    assert owner() is None, "the block outlived every user"
+
+
 def test_precheck_choice_on_clustered_vectors(isax):
     # 384-dimensional clustered vectors, 16 segments: early abandoning stops most FP32
     # rows after their first step, so waves mostly skip the precheck; answers are the
